@@ -1,0 +1,232 @@
+"""ctypes wrapper around the plain FP64 CPU oracle (oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
+benchmark's CPU-baseline leg.  The product library never imports it.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB = os.path.join(HERE, "liboracle.so")
+
+
+def build(verbose: bool = False) -> str:
+    cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+           "-fPIC", "-shared", "-Wall", "-Wextra", "-Wno-maybe-uninitialized", "-o", LIB,
+           os.path.join(HERE, "oracle.c"), "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    return LIB
+
+
+class _Model(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int), ("npoints", C.c_int),
+        ("pos", C.c_void_p), ("vel", C.c_void_p),
+        ("nbs_off", C.c_void_p), ("nbs", C.c_void_p), ("bdy", C.c_void_p),
+        ("T", C.c_void_p), ("vturb2", C.c_void_p), ("nspec", C.c_void_p), ("ncoll", C.c_void_p),
+        ("nrays", C.c_int), ("ray_dir", C.c_void_p), ("ray_w", C.c_void_p),
+        ("antipode", C.c_void_p),
+        ("mass", C.c_double), ("nlev", C.c_int), ("E", C.c_void_p), ("g", C.c_void_p),
+        ("nlines", C.c_int), ("up", C.c_void_p), ("lo", C.c_void_p), ("A", C.c_void_p),
+        ("nu", C.c_void_p),
+        ("ncoll_tr", C.c_int), ("cu", C.c_void_p), ("cl", C.c_void_p), ("K0", C.c_void_p),
+        ("nbins", C.c_int), ("xmax", C.c_double), ("Tcmb", C.c_double),
+        ("branch_threshold", C.c_double), ("tau_floor", C.c_double),
+        ("chi_min", C.c_double), ("pop_floor", C.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = C.CDLL(LIB)
+        P = C.c_void_p
+        L.orc_trace.argtypes = [P, C.c_int, C.c_int, C.c_int, P, P, P, P]
+        L.orc_trace.restype = C.c_int
+        L.orc_use_semi_analytic.argtypes = [P, C.c_int, C.c_double, C.c_int, C.c_double]
+        L.orc_line_coeffs.argtypes = [P, P, P, P, P]
+        L.orc_dtau_trapezoid.argtypes = [C.c_double] * 3
+        L.orc_dtau_trapezoid.restype = C.c_double
+        L.orc_dtau_semi_analytic.argtypes = [C.c_double] * 6
+        L.orc_dtau_semi_analytic.restype = C.c_double
+        L.orc_erf_difference.argtypes = [C.c_double] * 2
+        L.orc_erf_difference.restype = C.c_double
+        L.orc_planck.argtypes = [C.c_double] * 2
+        L.orc_planck.restype = C.c_double
+        L.orc_feautrier.argtypes = [C.c_int, P, P, C.c_double, C.c_double, C.c_int, P, P, P]
+        L.orc_solve_origin.argtypes = [P, P, P, C.c_int, P, P]
+        L.orc_solve_origins.argtypes = [P, P, P, C.c_int, P, P, P]
+        L.orc_lte.argtypes = [P, P]
+        L.orc_stateq_point.argtypes = [P, C.c_int, P, P, P, P]
+        L.orc_stateq.argtypes = [P, P, P, P, P]
+        L.orc_rel_change.argtypes = [P, P, P, C.c_int64]
+        L.orc_rel_change.restype = C.c_double
+        L.orc_ng.argtypes = [C.c_int, C.c_int64, P, P, P]
+        L.orc_iterate.argtypes = [P, P, C.c_double, C.c_int, C.c_int, C.c_int, P, P, P]
+        L.orc_num_threads.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def feautrier(dtau, S, I0, IM, o):
+    """u_o, Lambda*_oo and the full u for one Feautrier system."""
+    dtau = np.ascontiguousarray(dtau, np.float64)
+    S = np.ascontiguousarray(S, np.float64)
+    M = dtau.size
+    assert S.size == M + 1
+    uo, lo = C.c_double(), C.c_double()
+    u = np.zeros(M + 1)
+    lib().orc_feautrier(M, _p(dtau), _p(S), I0, IM, o, C.byref(uo), C.byref(lo), _p(u))
+    return uo.value, lo.value, u
+
+
+def planck(nu, T):
+    return lib().orc_planck(nu, T)
+
+
+def dtau_trapezoid(dx, chi0, chi1):
+    return lib().orc_dtau_trapezoid(dx, chi0, chi1)
+
+
+def dtau_semi_analytic(dx, chi_ij0, chi_ij1, d0, d1, dnu_bar):
+    return lib().orc_dtau_semi_analytic(dx, chi_ij0, chi_ij1, d0, d1, dnu_bar)
+
+
+def erf_difference(a, b):
+    return lib().orc_erf_difference(a, b)
+
+
+def num_threads():
+    return lib().orc_num_threads()
+
+
+def ng(hist):
+    """Ng prediction from a (nhist, n) array of iterates, oldest first."""
+    hist = np.ascontiguousarray(hist, np.float64)
+    nh, n = hist.shape
+    out = np.zeros(n)
+    c = np.zeros(max(nh - 1, 1))
+    st = lib().orc_ng(nh, n, _p(hist), _p(out), _p(c))
+    return st, out, c[: nh - 1]
+
+
+class Oracle:
+    """Binds one synthetic model (paper_2411_03040_amd.synth.Model) to the oracle."""
+
+    def __init__(self, model, branch_threshold=0.35, tau_floor=1e-15, chi_min=1e-30,
+                 pop_floor=1e-12):
+        self.model = model
+        a = model.arrays()
+        self._keep = a
+        s = _Model()
+        s.dim = model.dim
+        s.npoints = model.npoints
+        for k in ("pos", "vel", "nbs_off", "nbs", "bdy", "T", "vturb2", "nspec", "ncoll",
+                  "ray_dir", "ray_w", "antipode", "E", "g", "up", "lo", "A", "nu", "cu",
+                  "cl", "K0"):
+            setattr(s, k, a[k].ctypes.data)
+        s.nrays = model.nrays
+        s.mass = model.mass
+        s.nlev = model.nlev
+        s.nlines = model.nlines
+        s.ncoll_tr = int(a["K0"].size)
+        s.nbins = model.nbins
+        s.xmax = model.xmax
+        s.Tcmb = model.Tcmb
+        s.branch_threshold = branch_threshold
+        s.tau_floor = tau_floor
+        s.chi_min = chi_min
+        s.pop_floor = pop_floor
+        self.s = s
+        self.ptr = C.cast(C.pointer(s), C.c_void_p)
+
+    # -- trace -------------------------------------------------------------
+    def trace(self, origin, ray):
+        cap = 2 * self.model.npoints + 2
+        idx = np.zeros(cap, np.int32)
+        Z = np.zeros(cap)
+        dv = np.zeros(cap)
+        hole = C.c_int()
+        n = lib().orc_trace(self.ptr, origin, ray, cap, _p(idx), _p(Z), _p(dv), C.byref(hole))
+        return idx[:n].copy(), Z[:n].copy(), dv[:n].copy(), bool(hole.value)
+
+    def use_semi_analytic(self, p0, dv0, p1, dv1):
+        return bool(lib().orc_use_semi_analytic(self.ptr, p0, dv0, p1, dv1))
+
+    # -- populations / coefficients ------------------------------------------
+    def lte(self):
+        pops = np.zeros((self.model.npoints, self.model.nlev))
+        lib().orc_lte(self.ptr, _p(pops))
+        return pops
+
+    def line_coeffs(self, pops):
+        pops = np.ascontiguousarray(pops, np.float64)
+        N, nl = self.model.npoints, self.model.nlines
+        chi = np.zeros((N, nl))
+        eta = np.zeros((N, nl))
+        S = np.zeros((N, nl))
+        masing = lib().orc_line_coeffs(self.ptr, _p(pops), _p(chi), _p(eta), _p(S))
+        return chi, eta, S, masing
+
+    def solve_origins(self, pops, origins=None):
+        chi, _, S, _ = self.line_coeffs(pops)
+        nl = self.model.nlines
+        if origins is None:
+            cnt = self.model.npoints
+            optr = None
+        else:
+            origins = np.ascontiguousarray(origins, np.int32)
+            cnt = origins.size
+            optr = _p(origins)
+        J = np.zeros((cnt, nl))
+        L = np.zeros((cnt, nl))
+        lib().orc_solve_origins(self.ptr, _p(chi), _p(S), cnt, optr, _p(J), _p(L))
+        return J, L
+
+    def stateq(self, J, L, S):
+        J = np.ascontiguousarray(J, np.float64)
+        L = np.ascontiguousarray(L, np.float64)
+        S = np.ascontiguousarray(S, np.float64)
+        out = np.zeros((self.model.npoints, self.model.nlev))
+        st = lib().orc_stateq(self.ptr, _p(J), _p(L), _p(S), _p(out))
+        return st, out
+
+    def stateq_point(self, p, J, L, S):
+        J = np.ascontiguousarray(J, np.float64)
+        L = np.ascontiguousarray(L, np.float64)
+        S = np.ascontiguousarray(S, np.float64)
+        out = np.zeros(self.model.nlev)
+        st = lib().orc_stateq_point(self.ptr, p, _p(J), _p(L), _p(S), _p(out))
+        return st, out
+
+    def rel_change(self, a, b):
+        a = np.ascontiguousarray(a, np.float64)
+        b = np.ascontiguousarray(b, np.float64)
+        return lib().orc_rel_change(self.ptr, _p(a), _p(b), a.size)
+
+    def iterate(self, pops=None, tol=1e-10, max_iter=500, ng_mode=0, ng_param=4):
+        if pops is None:
+            pops = self.lte()
+        pops = np.ascontiguousarray(pops, np.float64).copy()
+        iters, ch = C.c_int(), C.c_double()
+        hist = np.zeros(max_iter)
+        st = lib().orc_iterate(self.ptr, _p(pops), tol, max_iter, ng_mode, ng_param,
+                               C.byref(iters), C.byref(ch), _p(hist))
+        return dict(status=st, pops=pops, iters=iters.value, change=ch.value,
+                    history=hist[: iters.value].copy())
