@@ -1,0 +1,217 @@
+"""Benchmark: formal-solution throughput of the line radiative transfer path on
+one MI355X.
+
+Workload (default): the 3D outflow, 50,000 points uniform in the shell
+r in [1, 20] with k = 16 neighbour lists, 10-level linear rotor (9 lines),
+48 HEALPix rays, 31 bins per line; formal solution in FP32 with FP64
+statistical equilibrium and classical Ng of order 4.
+
+A step is one Lambda-iteration over the whole model: line coefficients ->
+formal solution (every origin x ray x line x bin) -> statistical
+equilibrium -> convergence measure (-> Ng every 4th iterate).  The ray trace
+is static geometry, done once per model before the timed region (its time is
+reported as trace_ms).  value = N * R * nlines * nbins / (seconds per step),
+i.e. point.ray.frequency updates per second for the whole job.
+
+Also reported: the dominant kernel's roofline (per-launch duration from HIP
+events inside the library, on the stream the kernel runs on), the
+converged-model time of the FP32-bulk/FP64-solve form and of the plain FP64
+form from LTE, and the CPU oracle timed on a bounded sample of origins.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = ("formal-solve point·ray·freq updates/s, converged-model time vs FP64 form")
+
+# Algorithmic work of the formal solution, per element (one point of one
+# ray pair for one (line, bin) lane), counted from the arithmetic the method
+# needs (FMA = 2 FLOP; exp2 and reciprocal count 1 each):
+#   offset x (fma + mul) 3, profile (square, exp2) 2, opacity 1, chi'*b 1,
+#   trapezoid (add, 2 mul) 3, Feautrier step (2 + 1 + fma 2 + rcp 1 + 1 +
+#   fma 2 + 1) 10  ->  20 FLOP
+# A semi-analytic segment adds: 2 offsets (4), divided difference (sub, 2
+# mul, div 4), 2 erfc (~2 x 12), opacity average (fma 2, 3 mul)  ->  ~38 FLOP.
+# The origin row per (pair, lane) adds 8.
+FLOP_PER_ELEMENT = 20.0
+FLOP_PER_SEMI = 38.0
+FLOP_PER_ORIGIN_ROW = 8.0
+# Peak: 256 CUs x 4 SIMD x 16 lanes x 2 FLOP (FMA) x 2.4 GHz = 78.6 TFLOP/s for
+# FP32 without packed (dual) FP32 instructions, which this build does not use;
+# the packed figure is 157.3 TFLOP/s.  FP64 vector: 78.6 TFLOP/s.
+PEAK_FP32_TFLOPS = 78.6
+PEAK_FP64_TFLOPS = 78.6
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--workload", choices=["outflow", "clumpy", "shells"], default="outflow")
+    p.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
+    p.add_argument("--no-converge", action="store_true", help="skip converged-model timing")
+    p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--profile-steps", action="store_true",
+                   help="only warmup + timed steps (for rocprofv3 runs)")
+    return p.parse_args()
+
+
+def make_model(name):
+    from paper_2411_03040_amd import synth
+    if name == "outflow":
+        m = synth.config(1)
+        desc = ("3D outflow: 50000 points in r in [1,20], k=16 NN, 10-level rotor (9 lines), "
+                "48 rays, 31 bins/line, v=15 km/s (1-1/r)^0.5, T=2000 r^-0.7 K")
+    elif name == "clumpy":
+        m = synth.config(2)
+        desc = ("clumpy cloud: 200000 points, log-normal density, rotation+turbulence with "
+                "shifts up to 20 widths, 20-level rotor (19 lines), 48 rays, 39 bins/line")
+    else:
+        m = synth.config(0)
+        desc = "1D spherical shells: 64 shells, two-level species, 12 rays, 31 bins"
+    return m, desc
+
+
+def alu_roofline(ctx, m, ms_per_launch, precision):
+    c = ctx.counters()
+    lanes = m.nlines * m.nbins
+    npairs = m.nrays // 2
+    elements = lanes * c["total_records"]
+    flop = (elements * FLOP_PER_ELEMENT + lanes * c["semi_segments"] * FLOP_PER_SEMI +
+            lanes * m.npoints * npairs * FLOP_PER_ORIGIN_ROW)
+    achieved = flop / (ms_per_launch * 1e-3) / 1e12
+    peak = PEAK_FP32_TFLOPS if precision == "fp32" else PEAK_FP64_TFLOPS
+    return {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4), "traffic": None,
+            "kernel": "k_formal_solve<%s>" % ("float" if precision == "fp32" else "double"),
+            "flop_per_launch": flop, "elements_per_launch": elements,
+            "semi_segments": c["semi_segments"], "ms_per_launch": round(ms_per_launch, 4)}
+
+
+def cpu_baseline(m, seconds):
+    import oracle
+    from paper_2411_03040_amd import synth
+    orc = oracle.Oracle(m)
+    pops = orc.lte()
+    lanes = m.nlines * m.nbins
+    n = 16
+    t = 0.0
+    while True:
+        origins = synth.origin_sample(m.npoints, n, seed=99)
+        t0 = time.perf_counter()
+        orc.solve_origins(pops, origins)
+        t = time.perf_counter() - t0
+        if t > 0.25 * seconds or n >= m.npoints:
+            break
+        n = min(m.npoints, int(n * max(2.0, 0.3 * seconds / max(t, 1e-3))))
+    rate = n * m.nrays * lanes / t
+    return {"value": rate, "unit": "updates/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"formal solution (line coefficients + all rays, lines, bins) of {n} "
+                      f"seeded origins of the same model from LTE populations, {t:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+    from paper_2411_03040_amd import mgx
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    torch.cuda.set_device(0)
+    m, desc = make_model(args.workload)
+    prec = mgx.FP32 if args.precision == "fp32" else mgx.FP64
+    ctx = mgx.Context(device=0, precision=prec)
+    ctx.load_model(m)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.trace_rays()
+    torch.cuda.synchronize()
+    trace_ms = (time.perf_counter() - t0) * 1e3
+    ctx.set_lte_populations()
+    ng_order = 4
+    ctx.ng_reset(ng_order + 1)
+
+    def step(i):
+        ctx.formal_solve(copy=False)
+        ctx.update_populations()
+        if (i + 1) % ng_order == 0:
+            ctx.ng_accelerate(apply=True)
+
+    for i in range(args.warmup):
+        step(i)
+    ctx.reset_timers()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(args.warmup + i)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_step = dt / args.steps * 1e3
+    c = ctx.counters()
+    fs_ms = c["fs_ms_total"] / max(c["fs_launches"], 1)
+    updates = m.npoints * m.nrays * m.nlines * m.nbins
+    value = updates / (ms_step * 1e-3)
+    if args.profile_steps:
+        print(json.dumps({"ms_per_step": ms_step, "fs_ms": fs_ms, "value": value}))
+        return
+    roof = alu_roofline(ctx, m, fs_ms, args.precision)
+    out = {
+        "metric": METRIC, "value": value, "unit": "updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if prec == mgx.FP32 else "f64", "data": "synthetic",
+        "config": {"workload": desc, "npoints": m.npoints, "rays": m.nrays,
+                   "lines": m.nlines, "bins": m.nbins, "levels": m.nlev,
+                   "formal_solve": args.precision, "stateq": "f64", "ng": "classical order 4"},
+        "formal_solve_ms": fs_ms, "trace_ms": trace_ms,
+        "ray_pair_solves_per_s": value / 2.0,
+        "roofline": roof,
+    }
+    del ctx
+    if not args.no_converge:
+        conv = {}
+        for name, p in (("fp32_bulk", mgx.FP32), ("fp64", mgx.FP64)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            cx = mgx.Context(device=0, precision=p)
+            cx.load_model(m)
+            cx.trace_rays()
+            cx.set_lte_populations()
+            tol = 1e-6 if p == mgx.FP32 else 1e-10
+            it, ch, ok = cx.iterate(tol=tol, max_iter=300, ng_mode=mgx.NG_CLASSICAL,
+                                    ng_param=4, raise_on_noconv=False)
+            pops = cx.get_populations()
+            torch.cuda.synchronize()
+            conv[name] = {"seconds": time.perf_counter() - t0, "iterations": it,
+                          "final_change": ch, "converged": ok, "tol": tol, "pops": pops}
+            del cx
+        a, b = conv["fp32_bulk"]["pops"], conv["fp64"]["pops"]
+        err = float(np.max(np.abs(a - b) / np.maximum(b, 1e-12)))
+        for v in conv.values():
+            v.pop("pops")
+        conv["fp32_vs_fp64_pops_max_rel"] = err
+        conv["speedup_fp32_bulk_over_fp64"] = conv["fp64"]["seconds"] / conv["fp32_bulk"]["seconds"]
+        out["converged"] = conv
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(m, args.cpu_seconds)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,257 @@
+/*
+ * mgx.h -- C ABI of the MI355X (gfx950) line radiative transfer library.
+ *
+ * The library computes the hot path of non-LTE line radiative transfer on
+ * a point cloud (arXiv:2411.03040, "Magritte"): for every point, every ray
+ * direction and every frequency bin of every line it traces the ray through
+ * the cloud, gathers the Doppler-shifted Gaussian line opacity and source
+ * function along it (semi-analytic optical depth where the velocity
+ * gradient is large), solves the second-order Feautrier equation on each
+ * ray pair, averages the result into the mean intensity J-bar and the
+ * approximate Lambda-operator diagonal, solves statistical equilibrium per
+ * point and iterates, with Ng acceleration.
+ *
+ * Conventions for every entry point:
+ *  - Status: every function returns mgx_status; no C++ exception crosses the
+ *    ABI.  On failure mgx_last_error() returns a message, valid until the
+ *    next call on the same context.
+ *  - Pointers: "host or device" pointers may be either (unified addressing
+ *    decides the copy direction).  Functions that hand results back
+ *    synchronise the context's stream before returning.  Host input arrays
+ *    are read during the call and never retained.
+ *  - Ownership: all device state (model, traces, populations, radiation
+ *    field, Ng history) is allocated by the context on its device and freed
+ *    by mgx_destroy.
+ *  - Call order: load_model -> trace_rays -> (set populations) ->
+ *    formal_solve / update_populations / iterate.  Out-of-order calls
+ *    return MGX_ESTATE.
+ *  - Streams: all device work is enqueued on the stream given to
+ *    mgx_create (NULL: the context creates its own).
+ *  - Threading: one context must not be used from two threads at once.
+ *  - Layouts: per-point arrays are [N]; per-point-per-line arrays [N][nlines]
+ *    (line index fastest); populations [N][nlev] as fractions of the line
+ *    species density (rows sum to 1).
+ *  - Units: SI (m, m/s, K, kg, J, Hz, m^-3, m^3 s^-1, W m^-2 Hz^-1 sr^-1).
+ */
+#ifndef MGX_H
+#define MGX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mgx_ctx mgx_ctx;
+
+typedef enum {
+    MGX_OK = 0,
+    MGX_EINVAL = -1,      /* invalid argument or model                      */
+    MGX_ESTATE = -2,      /* call out of order                              */
+    MGX_ENOMEM = -3,      /* device allocation failed                       */
+    MGX_EHIP = -4,        /* HIP runtime error                              */
+    MGX_ENOCONV = -5,     /* iteration did not converge within max_iter     */
+    MGX_ESINGULAR = -6,   /* singular statistical-equilibrium system        */
+    MGX_ENONFINITE = -7   /* non-finite input or result                     */
+} mgx_status;
+
+enum { MGX_FP64 = 0, MGX_FP32 = 1 };
+enum { MGX_NG_NONE = 0, MGX_NG_CLASSICAL = 1, MGX_NG_ADAPTIVE = 2 };
+
+typedef struct {
+    /* Precision of the opacity gather, optical depths and Feautrier sweeps.
+       MGX_FP64: all in double.  MGX_FP32: float with double accumulation of
+       J-bar; statistical equilibrium and Ng always run in double. */
+    int precision;
+    /* Trapezoidal optical depth while the Doppler shift across a segment is
+       below this many line widths, else the semi-analytic form (Section
+       "Semi-analytical approximation for line optical depths"; 0.35). */
+    double branch_threshold;
+    double tau_floor;     /* lower bound on a segment optical depth (1e-15)  */
+    double chi_min;       /* masing clamp on chi^ij [m^-1 Hz] (1e-30)         */
+    double pop_floor;     /* floor of the relative-change denominator (1e-12) */
+} mgx_options;
+
+/* Fills the defaults listed above (precision MGX_FP32). */
+void mgx_default_options(mgx_options *opt);
+
+/* Model description (Section "Application / programmer interface": points,
+   velocities, neighbour lists, boundary, temperature, turbulence, species,
+   rays, CMB boundary condition, line data).  All host arrays. */
+typedef struct {
+    int dim;                  /* 3: point cloud; 1: spherically symmetric shells
+                                 (pos[0][k] = radius, strictly increasing,
+                                 vel[0][k] = radial velocity, ray_dir[r][0] = mu,
+                                 shells 0 and N-1 are the boundaries)        */
+    int npoints;              /* N >= 1                                        */
+    const double *pos;        /* [3][N] positions [m]                          */
+    const double *vel;        /* [3][N] velocities [m/s]                       */
+    const int32_t *nbs_off;   /* [N+1] CSR offsets into nbs                    */
+    const int32_t *nbs;       /* [nbs_off[N]] neighbour indices; order matters:
+                                 ties in the walk go to the earlier entry      */
+    const uint8_t *bdy;       /* [N] 1 = boundary point                        */
+    const double *T;          /* [N] gas temperature [K]                       */
+    const double *vturb2;     /* [N] squared turbulent velocity [m^2/s^2]      */
+    const double *nspec;      /* [N] line-species number density [m^-3]        */
+    const double *ncoll;      /* [N] collision-partner density [m^-3]          */
+    int nrays;                /* R, even                                       */
+    const double *ray_dir;    /* [R][3] unit directions                        */
+    const double *ray_w;      /* [R] weights (sum 1, equal for antipodes)      */
+    const int32_t *antipode;  /* [R] index of the opposite direction           */
+    double mass;              /* line species mass [kg]                        */
+    int nlev;                 /* 2..64 levels                                  */
+    const double *E;          /* [nlev] level energies [J]                     */
+    const double *g;          /* [nlev] statistical weights                    */
+    int nlines;               /* >= 1 radiative transitions                    */
+    const int32_t *up, *lo;   /* [nlines] upper / lower level                  */
+    const double *A;          /* [nlines] Einstein A [1/s]                     */
+    const double *nu;         /* [nlines] line centre [Hz]                     */
+    int ncoll_tr;             /* collisional transitions                       */
+    const int32_t *cu, *cl;   /* [ncoll_tr] upper / lower level (unique pairs) */
+    const double *K0;         /* [ncoll_tr] de-excitation coefficient at 100 K;
+                                 K(T) = K0 sqrt(T / 100 K) [m^3/s]             */
+    int nbins;                /* frequency bins per line (1..1024)             */
+    double xmax;              /* bins span +-xmax local line widths            */
+    double Tcmb;              /* boundary radiation temperature [K]            */
+} mgx_model;
+
+typedef struct {
+    int64_t total_records;    /* trace records (sum over origins and rays)     */
+    int64_t holes;            /* walks that ended on a non-boundary point      */
+    int64_t semi_segments;    /* segments that use the semi-analytic form      */
+    int64_t masing;           /* chi^ij clamps in the last line-coefficient pass */
+    int64_t singular;         /* points with a singular stat-eq system (last pass) */
+    int iterations;           /* Lambda-iterations done by mgx_iterate          */
+    int ng_applied;           /* Ng predictions used                            */
+    int ng_rejected;          /* Ng predictions rejected                        */
+    double last_change;       /* last max relative population change            */
+    int64_t fs_launches;      /* formal-solution kernel launches timed          */
+    double fs_ms_total;       /* their summed duration (HIP events on the
+                                 context's stream) [ms]                         */
+    double fs_ms_last;        /* duration of the last one [ms]                  */
+} mgx_counters;
+
+/* Zero the timing fields of the counters. */
+mgx_status mgx_reset_timers(mgx_ctx *ctx);
+
+/* Create a context on HIP device `device`; `stream` is a hipStream_t (or
+   NULL for a private stream).  opt may be NULL (defaults).
+   Errors: MGX_EINVAL (bad device/options), MGX_EHIP. */
+mgx_status mgx_create(mgx_ctx **out, int device, void *stream, const mgx_options *opt);
+
+/* Frees all device memory of the context.  NULL is ignored. */
+void mgx_destroy(mgx_ctx *ctx);
+
+/* Last error message of the context (or of a failed mgx_create when ctx is
+   NULL). */
+const char *mgx_last_error(const mgx_ctx *ctx);
+
+/* Copy a model to the device and precompute the per-point Doppler widths,
+   line-centred bin offsets x_f = -xmax + 2 xmax f / (nbins - 1), the bin
+   weights W_f = exp(-x_f^2) / sum exp(-x^2) (line width equation; Gaussian
+   profile equation).  Replaces any previously loaded model and resets all
+   derived state.  Errors: MGX_EINVAL (inconsistent sizes, indices out of
+   range, rays without antipodes, nlev > 64, duplicate collisional pairs),
+   MGX_ENONFINITE (non-finite inputs), MGX_ENOMEM. */
+mgx_status mgx_load_model(mgx_ctx *ctx, const mgx_model *m);
+
+/* Trace every (origin, ray) through the cloud (neighbour walk; spherical
+   shells for dim 1) and keep the records on the device (geometry is
+   static, so this runs once per model).  Each record holds the point
+   index, the projected distance Z from the origin, the projected velocity
+   difference dv = n.(v - v_origin) and whether the segment ending at the
+   record uses the semi-analytic optical depth (shift >= branch_threshold
+   widths).  total_records_out may be NULL.  Errors: MGX_ESTATE, MGX_ENOMEM. */
+mgx_status mgx_trace_rays(mgx_ctx *ctx, int64_t *total_records_out);
+
+/* Host copy of the trace of one (origin, ray): up to cap records into idx /
+   Z / dv (host or device; any may be NULL), length in *len_out. */
+mgx_status mgx_get_trace(mgx_ctx *ctx, int32_t origin, int32_t ray, int32_t cap,
+                         int32_t *idx, double *Z, double *dv, uint8_t *semi,
+                         int32_t *len_out);
+
+/* Record offsets of all traces: offsets[N * R + 1] (int64, host or device),
+   trace of (o, r) = records offsets[o R + r] .. offsets[o R + r + 1] - 1. */
+mgx_status mgx_get_trace_offsets(mgx_ctx *ctx, int64_t *offsets);
+
+/* Bulk copy of records [first, first + count) (any output may be NULL). */
+mgx_status mgx_get_trace_records(mgx_ctx *ctx, int64_t first, int64_t count, int32_t *idx,
+                                 double *Z, double *dv, uint8_t *semi);
+
+/* Level populations [N][nlev] (host or device).  set: rows must be finite,
+   >= 0; they are used as given.  Errors: MGX_ESTATE before load_model. */
+mgx_status mgx_set_populations(mgx_ctx *ctx, const double *pops);
+mgx_status mgx_get_populations(mgx_ctx *ctx, double *pops);
+
+/* LTE populations f_i ~ g_i exp(-E_i / k T) (the usual initial guess). */
+mgx_status mgx_set_lte_populations(mgx_ctx *ctx);
+
+/* One formal solution from the current populations: line coefficients
+   chi^ij = (h nu / 4 pi)(n_l B_lu - n_u B_ul), S = eta^ij / chi^ij, then for
+   every origin, ray pair, line and bin the optical depths (trapezoidal or
+   semi-analytic) and the Feautrier solve, reduced to
+     Jbar  = sum_pairs 2 w_r sum_f W_f u_origin
+     Lstar = sum_pairs 2 w_r sum_f W_f (T^-1)_origin,origin.
+   Results stay on the device; if Jbar / Lstar are non-NULL they also
+   receive copies ([N][nlines] double, host or device).
+   Errors: MGX_ESTATE (no trace or populations), MGX_EHIP. */
+mgx_status mgx_formal_solve(mgx_ctx *ctx, double *Jbar, double *Lstar);
+
+/* Replace the device radiation field ([N][nlines] double each, host or
+   device), e.g. to run statistical equilibrium on given inputs. */
+mgx_status mgx_set_radiation(mgx_ctx *ctx, const double *Jbar, const double *Lstar);
+
+/* Statistical equilibrium at every point from the current radiation field
+   with the accelerated Lambda-iteration rates (J_eff = Jbar - Lstar S_old,
+   R_ul = A (1 - Lstar) + B_ul J_eff + C_ul, R_lu = B_lu J_eff + C_lu, row 0
+   replaced by sum f = 1), in double.  Replaces the populations; the max over
+   points and levels of |new - old| / max(new, pop_floor) goes to
+   *max_rel_change_out (may be NULL).  If Ng history is active the new
+   iterate is appended to it.  Errors: MGX_ESINGULAR (populations of the
+   affected points are left unchanged), MGX_ENONFINITE. */
+mgx_status mgx_update_populations(mgx_ctx *ctx, double *max_rel_change_out);
+
+/* Ng acceleration (Section "Adaptive Ng-acceleration" and its appendix).
+   mgx_ng_reset starts a history of at most `capacity` (2..32) iterates with
+   the current populations as its first entry; each mgx_update_populations
+   then appends.  mgx_ng_accelerate forms the prediction from the N stored
+   iterates y_1..y_N: residuals r_k = y_{k+1} - y_k, G = R R^T,
+   c = G^-1 1 / 1^T G^-1 1, n* = sum c_k y_{k+1}.  If G is numerically
+   singular or n* has a negative entry the prediction is rejected.  When
+   `apply` is set and the prediction is accepted it replaces the
+   populations; with `apply` set the history then restarts from the
+   populations (accepted prediction or plain iterate).  *status_out: 1
+   accepted, 0 rejected.  *pred_change_out (may be NULL): relative change
+   between this prediction and the previous one formed since the last
+   restart (+inf if none), the adaptive criterion's input. */
+mgx_status mgx_ng_reset(mgx_ctx *ctx, int capacity);
+mgx_status mgx_ng_accelerate(mgx_ctx *ctx, int apply, int *status_out,
+                             double *pred_change_out);
+
+/* Lambda-iteration from the current populations until the max relative
+   change is <= tol (at most max_iter iterations): line coefficients ->
+   formal solution -> statistical equilibrium, with ng_mode MGX_NG_NONE,
+   MGX_NG_CLASSICAL (ng_param iterates combined, history of ng_param + 1) or
+   MGX_NG_ADAPTIVE (N_max = ng_param: the prediction from all stored iterates
+   is used once consecutive predictions change less than consecutive
+   iterates, or at N_max).  Errors: MGX_ENOCONV (populations hold the last
+   iterate), MGX_ESINGULAR, MGX_ENONFINITE. */
+mgx_status mgx_iterate(mgx_ctx *ctx, double tol, int max_iter, int ng_mode, int ng_param,
+                       int *iters_out, double *final_change_out);
+
+/* Diagnostics of the last calls. */
+mgx_status mgx_get_counters(mgx_ctx *ctx, mgx_counters *out);
+
+/* Synthetic channel maps (Listing of the radiative transfer script:
+   spectral discretisation f_min..f_max with nfreq bins, image along a ray
+   direction with npx x npy pixels).  Pixel rays run parallel to dir through
+   the cloud's projected extent; the intensity of each pixel and frequency
+   is integrated along the ray from the far side with the CMB behind it.
+   img is [npy][npx][nfreq] float (host or device).  dim 3 only. */
+mgx_status mgx_render_image(mgx_ctx *ctx, const double dir[3], int npx, int npy,
+                            double f_min, double f_max, int nfreq, float *img);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MGX_H */

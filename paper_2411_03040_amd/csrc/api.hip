@@ -1,0 +1,1048 @@
+// C ABI of the library: context, device memory, model validation and the
+// iteration driver.  All arithmetic of the method runs in the kernels of
+// trace.hip, formal_solve.hip, stateq.hip and ng.hip; this file only moves
+// data, checks arguments and sequences launches on the context's stream.
+
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/mgx.h"
+#include "mgx_internal.h"
+
+extern "C" hipError_t mgx_internal_scan(int64_t *counts, int64_t *offsets, int64_t n,
+                                        void **tmp, size_t *tmp_bytes, hipStream_t s);
+
+using namespace mgx;
+
+namespace {
+
+struct Err {
+    mgx_status st;
+    std::string msg;
+};
+
+#define HIPCHK(x)                                                                         \
+    do {                                                                                  \
+        hipError_t e_ = (x);                                                              \
+        if (e_ != hipSuccess)                                                             \
+            throw Err{e_ == hipErrorOutOfMemory ? MGX_ENOMEM : MGX_EHIP,                  \
+                      std::string(#x) + ": " + hipGetErrorString(e_)};                    \
+    } while (0)
+
+#define REQUIRE(cond, code, text)                                                         \
+    do {                                                                                  \
+        if (!(cond)) throw Err{code, text};                                               \
+    } while (0)
+
+// Owning device allocation.
+struct DMem {
+    void *p = nullptr;
+    size_t bytes = 0;
+    DMem() = default;
+    DMem(const DMem &) = delete;
+    DMem &operator=(const DMem &) = delete;
+    ~DMem() { release(); }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    void ensure(size_t b)
+    {
+        if (b <= bytes && p) return;
+        release();
+        if (b == 0) b = 16;
+        HIPCHK(hipMalloc(&p, b));
+        bytes = b;
+    }
+    template <typename T>
+    T *as() const
+    {
+        return (T *)p;
+    }
+};
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) HIPCHK(hipSetDevice(dev));
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+thread_local std::string g_create_error;
+
+template <typename T>
+bool all_finite(const T *a, size_t n)
+{
+    for (size_t i = 0; i < n; i++)
+        if (!std::isfinite((double)a[i])) return false;
+    return true;
+}
+
+}  // namespace
+
+struct mgx_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    mgx_options opt{};
+    std::string err;
+
+    // model
+    bool loaded = false, traced = false, have_pops = false, have_rad = false;
+    int dim = 3, N = 0, R = 0, nlev = 0, nlines = 0, ncoll_tr = 0, nbins = 0, npairs = 0;
+    double mass = 0, xmax = 5, Tcmb = 2.72548, L_unit = 1;
+    int64_t n_records = 0;
+
+    DMem pos, vel, nbs_off, nbs, bdy, T, vturb2, nspec, ncoll, ray_dir, ray_w, antipode;
+    DMem E, g, up, lo, A, nu, cu, cl, K0;
+    DMem b2, b, bf, ibf, bd, ibd, xf, W;
+    DMem Bul, Blu, hnu4pi, chiscale, Iref, acmb;
+    DMem pair_r, pair_a, pair_w;
+    DMem pops, pops_new, J, L, S64, chiT, ST;
+    DMem counters;
+    // trace
+    DMem counts, offsets, scan_tmp_owner;
+    void *scan_tmp = nullptr;
+    size_t scan_tmp_bytes = 0;
+    DMem r_idx, r_semi, r_Z, r_dv, r_dx, r_ibb, rec;
+    // Ng
+    bool ng_active = false, ng_have_prev = false;
+    int ng_cap = 0, ng_nh = 0;
+    std::vector<DMem *> ng_y, ng_r;
+    std::vector<DMem *> ng_pool;
+    DMem ng_G, ng_coef, ng_status, ng_partial, ng_pred, ng_prev, ng_bits;
+    // diagnostics
+    mgx_counters host_cnt{};
+    hipEvent_t ev_fs0 = nullptr, ev_fs1 = nullptr;
+    bool fs_pending = false;
+
+    ~mgx_ctx()
+    {
+        for (DMem *m : ng_pool) delete m;
+        if (scan_tmp) (void)hipFree(scan_tmp);
+        if (ev_fs0) (void)hipEventDestroy(ev_fs0);
+        if (ev_fs1) (void)hipEventDestroy(ev_fs1);
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+    }
+
+    int64_t npop() const { return (int64_t)N * nlev; }
+    int64_t nrad() const { return (int64_t)N * nlines; }
+    bool fp32() const { return opt.precision == MGX_FP32; }
+
+    void sync()
+    {
+        HIPCHK(hipStreamSynchronize(stream));
+        collect_timing();
+    }
+
+    // Duration of the last formal-solution kernel, once its events completed.
+    void collect_timing()
+    {
+        if (!fs_pending) return;
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, ev_fs0, ev_fs1));
+        fs_pending = false;
+        host_cnt.fs_launches++;
+        host_cnt.fs_ms_total += ms;
+        host_cnt.fs_ms_last = ms;
+    }
+
+    Counters read_counters()
+    {
+        Counters c;
+        HIPCHK(hipMemcpyAsync(&c, counters.p, sizeof(Counters), hipMemcpyDeviceToHost, stream));
+        sync();
+        return c;
+    }
+};
+
+#define API_BEGIN(ctx)                                                                    \
+    if (!(ctx)) return MGX_EINVAL;                                                        \
+    try {                                                                                 \
+        DeviceGuard dg_((ctx)->device);                                                   \
+        (ctx)->err.clear();
+
+#define API_END(ctx)                                                                      \
+    }                                                                                     \
+    catch (const Err &e)                                                                  \
+    {                                                                                     \
+        (ctx)->err = e.msg;                                                               \
+        return e.st;                                                                      \
+    }                                                                                     \
+    catch (const std::bad_alloc &)                                                        \
+    {                                                                                     \
+        (ctx)->err = "host allocation failed";                                            \
+        return MGX_ENOMEM;                                                                \
+    }                                                                                     \
+    catch (...)                                                                           \
+    {                                                                                     \
+        (ctx)->err = "unexpected internal error";                                         \
+        return MGX_EHIP;                                                                  \
+    }                                                                                     \
+    return MGX_OK;
+
+template <typename T>
+static void upload(mgx_ctx *c, DMem &d, const T *src, size_t n)
+{
+    d.ensure(sizeof(T) * n);
+    if (n) HIPCHK(hipMemcpyAsync(d.p, src, sizeof(T) * n, hipMemcpyHostToDevice, c->stream));
+}
+
+// ---------------------------------------------------------------------------
+
+extern "C" void mgx_default_options(mgx_options *opt)
+{
+    if (!opt) return;
+    opt->precision = MGX_FP32;
+    opt->branch_threshold = 0.35;
+    opt->tau_floor = 1e-15;
+    opt->chi_min = 1e-30;
+    opt->pop_floor = 1e-12;
+}
+
+extern "C" mgx_status mgx_create(mgx_ctx **out, int device, void *stream,
+                                 const mgx_options *opt)
+{
+    g_create_error.clear();
+    if (!out) {
+        g_create_error = "out is NULL";
+        return MGX_EINVAL;
+    }
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+        g_create_error = "no such HIP device";
+        return MGX_EINVAL;
+    }
+    mgx_options o;
+    mgx_default_options(&o);
+    if (opt) o = *opt;
+    if ((o.precision != MGX_FP32 && o.precision != MGX_FP64) || !(o.branch_threshold >= 0) ||
+        !(o.tau_floor > 0) || !(o.chi_min > 0) || !(o.pop_floor > 0)) {
+        g_create_error = "invalid options";
+        return MGX_EINVAL;
+    }
+    mgx_ctx *c = new (std::nothrow) mgx_ctx();
+    if (!c) {
+        g_create_error = "host allocation failed";
+        return MGX_ENOMEM;
+    }
+    c->device = device;
+    c->opt = o;
+    try {
+        DeviceGuard dg(device);
+        if (stream) {
+            c->stream = (hipStream_t)stream;
+        } else {
+            HIPCHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+            c->own_stream = true;
+        }
+        HIPCHK(hipEventCreate(&c->ev_fs0));
+        HIPCHK(hipEventCreate(&c->ev_fs1));
+        c->counters.ensure(sizeof(Counters));
+        HIPCHK(hipMemsetAsync(c->counters.p, 0, sizeof(Counters), c->stream));
+        c->sync();
+    } catch (const Err &e) {
+        g_create_error = e.msg;
+        delete c;
+        return e.st;
+    }
+    *out = c;
+    return MGX_OK;
+}
+
+extern "C" void mgx_destroy(mgx_ctx *ctx)
+{
+    if (!ctx) return;
+    {
+        int prev = -1;
+        (void)hipGetDevice(&prev);
+        (void)hipSetDevice(ctx->device);
+        if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+        delete ctx;
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+}
+
+extern "C" const char *mgx_last_error(const mgx_ctx *ctx)
+{
+    if (!ctx) return g_create_error.c_str();
+    return ctx->err.c_str();
+}
+
+// ---------------------------------------------------------------------------
+// Model
+// ---------------------------------------------------------------------------
+
+static void validate_model(const mgx_model *m)
+{
+    REQUIRE(m, MGX_EINVAL, "model is NULL");
+    REQUIRE(m->dim == 1 || m->dim == 3, MGX_EINVAL, "dim must be 1 or 3");
+    const int N = m->npoints;
+    REQUIRE(N >= 1, MGX_EINVAL, "npoints must be >= 1");
+    REQUIRE(m->pos && m->vel && m->nbs_off && m->bdy && m->T && m->vturb2 && m->nspec &&
+                m->ncoll && m->ray_dir && m->ray_w && m->antipode && m->E && m->g && m->up &&
+                m->lo && m->A && m->nu,
+            MGX_EINVAL, "required model array is NULL");
+    REQUIRE(m->nbs_off[0] == 0, MGX_EINVAL, "nbs_off[0] must be 0");
+    for (int i = 0; i < N; i++)
+        REQUIRE(m->nbs_off[i + 1] >= m->nbs_off[i], MGX_EINVAL, "nbs_off not monotone");
+    const int64_t E = m->nbs_off[N];
+    REQUIRE(E == 0 || m->nbs, MGX_EINVAL, "nbs is NULL");
+    for (int64_t q = 0; q < E; q++)
+        REQUIRE(m->nbs[q] >= 0 && m->nbs[q] < N, MGX_EINVAL, "neighbour index out of range");
+    REQUIRE(all_finite(m->pos, 3 * (size_t)N) && all_finite(m->vel, 3 * (size_t)N) &&
+                all_finite(m->T, N) && all_finite(m->vturb2, N) && all_finite(m->nspec, N) &&
+                all_finite(m->ncoll, N),
+            MGX_ENONFINITE, "non-finite per-point input");
+    for (int i = 0; i < N; i++) {
+        REQUIRE(m->T[i] > 0 && m->vturb2[i] >= 0 && m->nspec[i] >= 0 && m->ncoll[i] >= 0,
+                MGX_EINVAL, "T must be > 0 and vturb2, nspec, ncoll >= 0");
+    }
+    if (m->dim == 1) {
+        for (int i = 0; i + 1 < N; i++)
+            REQUIRE(m->pos[i + 1] > m->pos[i], MGX_EINVAL, "shell radii must increase");
+        REQUIRE(m->pos[0] > 0, MGX_EINVAL, "shell radii must be > 0");
+        REQUIRE(m->bdy[0] && m->bdy[N - 1], MGX_EINVAL, "first and last shells are boundaries");
+    }
+    const int R = m->nrays;
+    REQUIRE(R >= 2 && R % 2 == 0, MGX_EINVAL, "nrays must be even and >= 2");
+    REQUIRE(all_finite(m->ray_dir, 3 * (size_t)R) && all_finite(m->ray_w, R), MGX_ENONFINITE,
+            "non-finite ray input");
+    for (int r = 0; r < R; r++) {
+        const int a = m->antipode[r];
+        REQUIRE(a >= 0 && a < R && a != r && m->antipode[a] == r, MGX_EINVAL,
+                "antipode table is not an involution");
+        REQUIRE(m->ray_w[r] == m->ray_w[a] && m->ray_w[r] >= 0, MGX_EINVAL,
+                "antipodal rays need equal non-negative weights");
+        if (m->dim == 1) {
+            REQUIRE(m->ray_dir[3 * a] == -m->ray_dir[3 * r] && fabs(m->ray_dir[3 * r]) <= 1.0,
+                    MGX_EINVAL, "1D rays: mu of an antipode must be -mu");
+        } else {
+            for (int k = 0; k < 3; k++)
+                REQUIRE(m->ray_dir[3 * a + k] == -m->ray_dir[3 * r + k], MGX_EINVAL,
+                        "antipode direction must be the exact negative");
+        }
+    }
+    REQUIRE(m->nlev >= 2 && m->nlev <= kMaxLevels, MGX_EINVAL, "nlev must be in 2..64");
+    REQUIRE(m->nlines >= 1, MGX_EINVAL, "nlines must be >= 1");
+    REQUIRE(m->mass > 0 && std::isfinite(m->mass), MGX_EINVAL, "mass must be > 0");
+    REQUIRE(all_finite(m->E, m->nlev) && all_finite(m->g, m->nlev) &&
+                all_finite(m->A, m->nlines) && all_finite(m->nu, m->nlines),
+            MGX_ENONFINITE, "non-finite level or line data");
+    for (int i = 0; i < m->nlev; i++) REQUIRE(m->g[i] > 0, MGX_EINVAL, "g must be > 0");
+    std::vector<char> seen((size_t)m->nlev * m->nlev, 0);
+    for (int l = 0; l < m->nlines; l++) {
+        const int u = m->up[l], lw = m->lo[l];
+        REQUIRE(u >= 0 && u < m->nlev && lw >= 0 && lw < m->nlev && u != lw, MGX_EINVAL,
+                "line level index out of range");
+        REQUIRE(m->nu[l] > 0 && m->A[l] >= 0, MGX_EINVAL, "line nu must be > 0, A >= 0");
+        char &s = seen[(size_t)u * m->nlev + lw];
+        REQUIRE(!s, MGX_EINVAL, "duplicate radiative transition");
+        s = 1;
+    }
+    REQUIRE(m->ncoll_tr >= 0, MGX_EINVAL, "ncoll_tr must be >= 0");
+    if (m->ncoll_tr) {
+        REQUIRE(m->cu && m->cl && m->K0, MGX_EINVAL, "collision arrays are NULL");
+        REQUIRE(all_finite(m->K0, m->ncoll_tr), MGX_ENONFINITE, "non-finite K0");
+    }
+    std::fill(seen.begin(), seen.end(), 0);
+    for (int t = 0; t < m->ncoll_tr; t++) {
+        const int u = m->cu[t], lw = m->cl[t];
+        REQUIRE(u >= 0 && u < m->nlev && lw >= 0 && lw < m->nlev && u != lw, MGX_EINVAL,
+                "collision level index out of range");
+        REQUIRE(m->K0[t] >= 0, MGX_EINVAL, "K0 must be >= 0");
+        char &s = seen[(size_t)u * m->nlev + lw];
+        REQUIRE(!s, MGX_EINVAL, "duplicate collisional transition");
+        s = 1;
+    }
+    REQUIRE(m->nbins >= 1 && m->nbins <= kMaxBins, MGX_EINVAL, "nbins must be in 1..1024");
+    REQUIRE(m->xmax >= 0 && std::isfinite(m->xmax), MGX_EINVAL, "xmax must be >= 0");
+    REQUIRE(m->Tcmb > 0 && std::isfinite(m->Tcmb), MGX_EINVAL, "Tcmb must be > 0");
+}
+
+extern "C" mgx_status mgx_load_model(mgx_ctx *ctx, const mgx_model *m)
+{
+    API_BEGIN(ctx)
+    validate_model(m);
+    ctx->loaded = ctx->traced = ctx->have_pops = ctx->have_rad = false;
+    ctx->ng_active = false;
+    const int N = m->npoints, R = m->nrays;
+    ctx->dim = m->dim;
+    ctx->N = N;
+    ctx->R = R;
+    ctx->nlev = m->nlev;
+    ctx->nlines = m->nlines;
+    ctx->ncoll_tr = m->ncoll_tr;
+    ctx->nbins = m->nbins;
+    ctx->mass = m->mass;
+    ctx->xmax = m->xmax;
+    ctx->Tcmb = m->Tcmb;
+    // Length unit of the scaled optical-depth arithmetic: bounding-box
+    // diagonal over N^(1/3) (about one point spacing).
+    double lo3[3] = {INFINITY, INFINITY, INFINITY}, hi3[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int k = 0; k < 3; k++)
+        for (int i = 0; i < N; i++) {
+            lo3[k] = std::min(lo3[k], m->pos[(size_t)k * N + i]);
+            hi3[k] = std::max(hi3[k], m->pos[(size_t)k * N + i]);
+        }
+    double diag = sqrt((hi3[0] - lo3[0]) * (hi3[0] - lo3[0]) + (hi3[1] - lo3[1]) * (hi3[1] - lo3[1]) +
+                       (hi3[2] - lo3[2]) * (hi3[2] - lo3[2]));
+    ctx->L_unit = diag > 0 ? diag / cbrt((double)N) : 1.0;
+
+    upload(ctx, ctx->pos, m->pos, 3 * (size_t)N);
+    upload(ctx, ctx->vel, m->vel, 3 * (size_t)N);
+    upload(ctx, ctx->nbs_off, m->nbs_off, (size_t)N + 1);
+    upload(ctx, ctx->nbs, m->nbs, (size_t)m->nbs_off[N]);
+    upload(ctx, ctx->bdy, m->bdy, (size_t)N);
+    upload(ctx, ctx->T, m->T, (size_t)N);
+    upload(ctx, ctx->vturb2, m->vturb2, (size_t)N);
+    upload(ctx, ctx->nspec, m->nspec, (size_t)N);
+    upload(ctx, ctx->ncoll, m->ncoll, (size_t)N);
+    upload(ctx, ctx->ray_dir, m->ray_dir, 3 * (size_t)R);
+    upload(ctx, ctx->ray_w, m->ray_w, (size_t)R);
+    upload(ctx, ctx->antipode, m->antipode, (size_t)R);
+    upload(ctx, ctx->E, m->E, (size_t)m->nlev);
+    upload(ctx, ctx->g, m->g, (size_t)m->nlev);
+    upload(ctx, ctx->up, m->up, (size_t)m->nlines);
+    upload(ctx, ctx->lo, m->lo, (size_t)m->nlines);
+    upload(ctx, ctx->A, m->A, (size_t)m->nlines);
+    upload(ctx, ctx->nu, m->nu, (size_t)m->nlines);
+    upload(ctx, ctx->cu, m->cu, (size_t)m->ncoll_tr);
+    upload(ctx, ctx->cl, m->cl, (size_t)m->ncoll_tr);
+    upload(ctx, ctx->K0, m->K0, (size_t)m->ncoll_tr);
+
+    // ray pairs: (r, antipode r) with r < antipode
+    std::vector<int32_t> pr, pa;
+    std::vector<double> pw;
+    for (int r = 0; r < R; r++)
+        if (r < m->antipode[r]) {
+            pr.push_back(r);
+            pa.push_back(m->antipode[r]);
+            pw.push_back(2.0 * m->ray_w[r]);
+        }
+    ctx->npairs = (int)pr.size();
+    upload(ctx, ctx->pair_r, pr.data(), pr.size());
+    upload(ctx, ctx->pair_a, pa.data(), pa.size());
+    upload(ctx, ctx->pair_w, pw.data(), pw.size());
+
+    ctx->b2.ensure(sizeof(double) * N);
+    ctx->b.ensure(sizeof(double) * N);
+    ctx->bf.ensure(sizeof(float) * N);
+    ctx->ibf.ensure(sizeof(float) * N);
+    ctx->bd.ensure(sizeof(double) * N);
+    ctx->ibd.ensure(sizeof(double) * N);
+    HIPCHK(launch_point_widths(N, ctx->T.as<double>(), ctx->vturb2.as<double>(), m->mass,
+                               ctx->b2.as<double>(), ctx->b.as<double>(), ctx->bf.as<float>(),
+                               ctx->ibf.as<float>(), ctx->bd.as<double>(), ctx->ibd.as<double>(),
+                               ctx->stream));
+    ctx->xf.ensure(sizeof(double) * m->nbins);
+    ctx->W.ensure(sizeof(double) * m->nbins);
+    HIPCHK(launch_bin_table(m->nbins, m->xmax, ctx->xf.as<double>(), ctx->W.as<double>(),
+                            ctx->stream));
+    const int nl = m->nlines;
+    for (DMem *d : {&ctx->Bul, &ctx->Blu, &ctx->hnu4pi, &ctx->chiscale, &ctx->Iref, &ctx->acmb})
+        d->ensure(sizeof(double) * nl);
+    HIPCHK(launch_line_table(nl, m->nlev, ctx->A.as<double>(), ctx->nu.as<double>(),
+                             ctx->g.as<double>(), ctx->up.as<int32_t>(), ctx->lo.as<int32_t>(),
+                             ctx->L_unit, m->Tcmb, ctx->Bul.as<double>(), ctx->Blu.as<double>(),
+                             ctx->hnu4pi.as<double>(), ctx->chiscale.as<double>(),
+                             ctx->Iref.as<double>(), ctx->acmb.as<double>(), ctx->stream));
+    const size_t tsz = ctx->fp32() ? sizeof(float) : sizeof(double);
+    ctx->pops.ensure(sizeof(double) * ctx->npop());
+    ctx->pops_new.ensure(sizeof(double) * ctx->npop());
+    ctx->J.ensure(sizeof(double) * ctx->nrad());
+    ctx->L.ensure(sizeof(double) * ctx->nrad());
+    ctx->S64.ensure(sizeof(double) * ctx->nrad());
+    ctx->chiT.ensure(tsz * ctx->nrad());
+    ctx->ST.ensure(tsz * ctx->nrad());
+    ctx->sync();
+    ctx->loaded = true;
+    ctx->host_cnt = mgx_counters{};
+    API_END(ctx)
+}
+
+// ---------------------------------------------------------------------------
+// Trace
+// ---------------------------------------------------------------------------
+
+extern "C" mgx_status mgx_trace_rays(mgx_ctx *ctx, int64_t *total_records_out)
+{
+    API_BEGIN(ctx)
+    REQUIRE(ctx->loaded, MGX_ESTATE, "mgx_trace_rays before mgx_load_model");
+    const int64_t NW = (int64_t)ctx->N * ctx->R;
+    ctx->counts.ensure(sizeof(int64_t) * (NW + 1));
+    ctx->offsets.ensure(sizeof(int64_t) * (NW + 1));
+    HIPCHK(hipMemsetAsync(ctx->counts.p, 0, sizeof(int64_t) * (NW + 1), ctx->stream));
+    HIPCHK(hipMemsetAsync(ctx->counters.p, 0, sizeof(Counters), ctx->stream));
+    TraceArgs a{};
+    a.dim = ctx->dim;
+    a.N = ctx->N;
+    a.R = ctx->R;
+    const double *pos = ctx->pos.as<double>(), *vel = ctx->vel.as<double>();
+    a.x = pos;
+    a.y = pos + ctx->N;
+    a.z = pos + 2 * (size_t)ctx->N;
+    a.vx = vel;
+    a.vy = vel + ctx->N;
+    a.vz = vel + 2 * (size_t)ctx->N;
+    a.nbs_off = ctx->nbs_off.as<int32_t>();
+    a.nbs = ctx->nbs.as<int32_t>();
+    a.bdy = ctx->bdy.as<uint8_t>();
+    a.ray_dir = ctx->ray_dir.as<double>();
+    a.b2 = ctx->b2.as<double>();
+    a.thr = ctx->opt.branch_threshold;
+    a.counts = ctx->counts.as<int64_t>();
+    a.cnt = ctx->counters.as<Counters>();
+    HIPCHK(launch_trace(a, false, ctx->stream));
+    HIPCHK(mgx_internal_scan(ctx->counts.as<int64_t>(), ctx->offsets.as<int64_t>(), NW + 1,
+                             &ctx->scan_tmp, &ctx->scan_tmp_bytes, ctx->stream));
+    int64_t total = 0;
+    HIPCHK(hipMemcpyAsync(&total, ctx->offsets.as<int64_t>() + NW, sizeof(int64_t),
+                          hipMemcpyDeviceToHost, ctx->stream));
+    ctx->sync();
+    ctx->n_records = total;
+    const size_t n = (size_t)(total > 0 ? total : 1);
+    ctx->r_idx.ensure(sizeof(int32_t) * n);
+    ctx->r_semi.ensure(n);
+    ctx->r_Z.ensure(sizeof(double) * n);
+    ctx->r_dv.ensure(sizeof(double) * n);
+    ctx->r_dx.ensure(sizeof(double) * n);
+    ctx->r_ibb.ensure(sizeof(double) * n);
+    a.off = ctx->offsets.as<int64_t>();
+    a.r_idx = ctx->r_idx.as<int32_t>();
+    a.r_semi = ctx->r_semi.as<uint8_t>();
+    a.r_Z = ctx->r_Z.as<double>();
+    a.r_dv = ctx->r_dv.as<double>();
+    a.r_dx = ctx->r_dx.as<double>();
+    a.r_ibb = ctx->r_ibb.as<double>();
+    HIPCHK(launch_trace(a, true, ctx->stream));
+    const bool f32 = ctx->fp32();
+    ctx->rec.ensure((f32 ? sizeof(Rec<float>) : sizeof(Rec<double>)) * n);
+    HIPCHK(launch_pack_trace(total, ctx->r_idx.as<int32_t>(), ctx->r_semi.as<uint8_t>(),
+                             ctx->r_dx.as<double>(), ctx->r_dv.as<double>(),
+                             ctx->r_ibb.as<double>(), 1.0 / ctx->L_unit, f32, ctx->rec.p,
+                             ctx->stream));
+    Counters c = ctx->read_counters();
+    ctx->host_cnt.total_records = total;
+    ctx->host_cnt.holes = (int64_t)c.holes;
+    ctx->host_cnt.semi_segments = (int64_t)c.semi;
+    ctx->traced = true;
+    if (total_records_out) *total_records_out = total;
+    API_END(ctx)
+}
+
+extern "C" mgx_status mgx_get_trace_offsets(mgx_ctx *ctx, int64_t *offsets)
+{
+    API_BEGIN(ctx)
+    REQUIRE(ctx->traced, MGX_ESTATE, "no trace");
+    REQUIRE(offsets, MGX_EINVAL, "offsets is NULL");
+    const int64_t NW = (int64_t)ctx->N * ctx->R;
+    HIPCHK(hipMemcpyAsync(offsets, ctx->offsets.p, sizeof(int64_t) * (NW + 1), hipMemcpyDefault,
+                          ctx->stream));
+    ctx->sync();
+    API_END(ctx)
+}
+
+static void copy_records(mgx_ctx *ctx, int64_t first, int64_t count, int32_t *idx, double *Z,
+                         double *dv, uint8_t *semi)
+{
+    if (count <= 0) return;
+    if (idx)
+        HIPCHK(hipMemcpyAsync(idx, ctx->r_idx.as<int32_t>() + first, sizeof(int32_t) * count,
+                              hipMemcpyDefault, ctx->stream));
+    if (Z)
+        HIPCHK(hipMemcpyAsync(Z, ctx->r_Z.as<double>() + first, sizeof(double) * count,
+                              hipMemcpyDefault, ctx->stream));
+    if (dv)
+        HIPCHK(hipMemcpyAsync(dv, ctx->r_dv.as<double>() + first, sizeof(double) * count,
+                              hipMemcpyDefault, ctx->stream));
+    if (semi)
+        HIPCHK(hipMemcpyAsync(semi, ctx->r_semi.as<uint8_t>() + first, count, hipMemcpyDefault,
+                              ctx->stream));
+}
+
+extern "C" mgx_status mgx_get_trace_records(mgx_ctx *ctx, int64_t first, int64_t count,
+                                            int32_t *idx, double *Z, double *dv, uint8_t *semi)
+{
+    API_BEGIN(ctx)
+    REQUIRE(ctx->traced, MGX_ESTATE, "no trace");
+    REQUIRE(first >= 0 && count >= 0 && first + count <= ctx->n_records, MGX_EINVAL,
+            "record range out of bounds");
+    copy_records(ctx, first, count, idx, Z, dv, semi);
+    ctx->sync();
+    API_END(ctx)
+}
+
+extern "C" mgx_status mgx_get_trace(mgx_ctx *ctx, int32_t origin, int32_t ray, int32_t cap,
+                                    int32_t *idx, double *Z, double *dv, uint8_t *semi,
+                                    int32_t *len_out)
+{
+    API_BEGIN(ctx)
+    REQUIRE(ctx->traced, MGX_ESTATE, "no trace");
+    REQUIRE(origin >= 0 && origin < ctx->N && ray >= 0 && ray < ctx->R && cap >= 0, MGX_EINVAL,
+            "origin/ray out of range");
+    int64_t ab[2];
+    const int64_t w = (int64_t)origin * ctx->R + ray;
+    HIPCHK(hipMemcpyAsync(ab, ctx->offsets.as<int64_t>() + w, 2 * sizeof(int64_t),
+                          hipMemcpyDeviceToHost, ctx->stream));
+    ctx->sync();
+    const int64_t len = ab[1] - ab[0];
+    copy_records(ctx, ab[0], std::min<int64_t>(len, cap), idx, Z, dv, semi);
+    ctx->sync();
+    if (len_out) *len_out = (int32_t)len;
+    API_END(ctx)
+}
+
+// ---------------------------------------------------------------------------
+// Populations and radiation field
+// ---------------------------------------------------------------------------
+
+extern "C" mgx_status mgx_set_populations(mgx_ctx *ctx, const double *pops)
+{
+    API_BEGIN(ctx)
+    REQUIRE(ctx->loaded, MGX_ESTATE, "no model");
+    REQUIRE(pops, MGX_EINVAL, "pops is NULL");
+    HIPCHK(hipMemcpyAsync(ctx->pops.p, pops, sizeof(double) * ctx->npop(), hipMemcpyDefault,
+                          ctx->stream));
+    ctx->sync();
+    ctx->have_pops = true;
+    ctx->have_rad = false;
+    API_END(ctx)
+}
+
+extern "C" mgx_status mgx_get_populations(mgx_ctx *ctx, double *pops)
+{
+    API_BEGIN(ctx)
+    REQUIRE(ctx->have_pops, MGX_ESTATE, "no populations");
+    REQUIRE(pops, MGX_EINVAL, "pops is NULL");
+    HIPCHK(hipMemcpyAsync(pops, ctx->pops.p, sizeof(double) * ctx->npop(), hipMemcpyDefault,
+                          ctx->stream));
+    ctx->sync();
+    API_END(ctx)
+}
+
+extern "C" mgx_status mgx_set_lte_populations(mgx_ctx *ctx)
+{
+    API_BEGIN(ctx)
+    REQUIRE(ctx->loaded, MGX_ESTATE, "no model");
+    HIPCHK(launch_lte(ctx->N, ctx->nlev, ctx->T.as<double>(), ctx->E.as<double>(),
+                      ctx->g.as<double>(), ctx->pops.as<double>(), ctx->stream));
+    ctx->sync();
+    ctx->have_pops = true;
+    ctx->have_rad = false;
+    API_END(ctx)
+}
+
+static void run_line_coeffs(mgx_ctx *ctx)
+{
+    LineArgs la{};
+    la.N = ctx->N;
+    la.nlev = ctx->nlev;
+    la.nlines = ctx->nlines;
+    la.pops = ctx->pops.as<double>();
+    la.nspec = ctx->nspec.as<double>();
+    la.b = ctx->b.as<double>();
+    la.up = ctx->up.as<int32_t>();
+    la.lo = ctx->lo.as<int32_t>();
+    la.A = ctx->A.as<double>();
+    la.Bul = ctx->Bul.as<double>();
+    la.Blu = ctx->Blu.as<double>();
+    la.hnu4pi = ctx->hnu4pi.as<double>();
+    la.chiscale = ctx->chiscale.as<double>();
+    la.Iref = ctx->Iref.as<double>();
+    la.chi_min = ctx->opt.chi_min;
+    la.S64 = ctx->S64.as<double>();
+    la.chiT = ctx->chiT.p;
+    la.ST = ctx->ST.p;
+    la.fp32 = ctx->fp32() ? 1 : 0;
+    la.cnt = ctx->counters.as<Counters>();
+    HIPCHK(launch_reset_counters(ctx->counters.as<Counters>(), ctx->stream));
+    HIPCHK(launch_line_coeffs(la, ctx->stream));
+}
+
+template <typename T>
+static void run_formal_solve_t(mgx_ctx *ctx)
+{
+    FSArgs<T> a{};
+    a.N = ctx->N;
+    a.R = ctx->R;
+    a.npairs = ctx->npairs;
+    a.nlines = ctx->nlines;
+    a.nbins = ctx->nbins;
+    int nlc = std::max(1, kMaxBins / ctx->nbins);
+    if (nlc > ctx->nlines) nlc = ctx->nlines;
+    // balance the line chunks so the last one is not nearly empty
+    const int nchunks = (ctx->nlines + nlc - 1) / nlc;
+    nlc = (ctx->nlines + nchunks - 1) / nchunks;
+    a.nlc = nlc;
+    a.nthreads = ((nlc * ctx->nbins + 63) / 64) * 64;
+    a.off = ctx->offsets.as<int64_t>();
+    a.rec = (const Rec<T> *)ctx->rec.p;
+    a.pair_r = ctx->pair_r.as<int32_t>();
+    a.pair_a = ctx->pair_a.as<int32_t>();
+    a.pair_w = ctx->pair_w.as<double>();
+    a.chi = (const T *)ctx->chiT.p;
+    a.S = (const T *)ctx->ST.p;
+    if (sizeof(T) == 4) {
+        a.bpt = (const T *)ctx->bf.p;
+        a.ibpt = (const T *)ctx->ibf.p;
+    } else {
+        a.bpt = (const T *)ctx->bd.p;
+        a.ibpt = (const T *)ctx->ibd.p;
+    }
+    a.b64 = ctx->b.as<double>();
+    a.xf = ctx->xf.as<double>();
+    a.W = ctx->W.as<double>();
+    a.acmb = ctx->acmb.as<double>();
+    a.Iref = ctx->Iref.as<double>();
+    a.tau_floor = ctx->opt.tau_floor;
+    a.J = ctx->J.as<double>();
+    a.L = ctx->L.as<double>();
+    if (ctx->fs_pending) ctx->sync();  // previous launch's events must be read first
+    HIPCHK(hipEventRecord(ctx->ev_fs0, ctx->stream));
+    HIPCHK(launch_formal_solve<T>(a, ctx->stream));
+    HIPCHK(hipEventRecord(ctx->ev_fs1, ctx->stream));
+    ctx->fs_pending = true;
+}
+
+static void run_formal_solve(mgx_ctx *ctx)
+{
+    run_line_coeffs(ctx);
+    if (ctx->fp32())
+        run_formal_solve_t<float>(ctx);
+    else
+        run_formal_solve_t<double>(ctx);
+}
+
+extern "C" mgx_status mgx_formal_solve(mgx_ctx *ctx, double *Jbar, double *Lstar)
+{
+    API_BEGIN(ctx)
+    REQUIRE(ctx->traced, MGX_ESTATE, "mgx_formal_solve before mgx_trace_rays");
+    REQUIRE(ctx->have_pops, MGX_ESTATE, "mgx_formal_solve without populations");
+    run_formal_solve(ctx);
+    if (Jbar)
+        HIPCHK(hipMemcpyAsync(Jbar, ctx->J.p, sizeof(double) * ctx->nrad(), hipMemcpyDefault,
+                              ctx->stream));
+    if (Lstar)
+        HIPCHK(hipMemcpyAsync(Lstar, ctx->L.p, sizeof(double) * ctx->nrad(), hipMemcpyDefault,
+                              ctx->stream));
+    Counters c = ctx->read_counters();
+    ctx->host_cnt.masing = (int64_t)c.masing;
+    ctx->have_rad = true;
+    API_END(ctx)
+}
+
+extern "C" mgx_status mgx_set_radiation(mgx_ctx *ctx, const double *Jbar, const double *Lstar)
+{
+    API_BEGIN(ctx)
+    REQUIRE(ctx->have_pops, MGX_ESTATE, "mgx_set_radiation without populations");
+    REQUIRE(Jbar && Lstar, MGX_EINVAL, "Jbar / Lstar is NULL");
+    run_line_coeffs(ctx);  // source function of the current populations
+    HIPCHK(hipMemcpyAsync(ctx->J.p, Jbar, sizeof(double) * ctx->nrad(), hipMemcpyDefault,
+                          ctx->stream));
+    HIPCHK(hipMemcpyAsync(ctx->L.p, Lstar, sizeof(double) * ctx->nrad(), hipMemcpyDefault,
+                          ctx->stream));
+    ctx->sync();
+    ctx->have_rad = true;
+    API_END(ctx)
+}
+
+// ---------------------------------------------------------------------------
+// Statistical equilibrium and Ng
+// ---------------------------------------------------------------------------
+
+static DMem *ng_buffer(mgx_ctx *ctx)
+{
+    DMem *m = new DMem();
+    ctx->ng_pool.push_back(m);
+    m->ensure(sizeof(double) * ctx->npop());
+    return m;
+}
+
+static void ng_append(mgx_ctx *ctx)
+{
+    if (ctx->ng_nh == ctx->ng_cap) {  // window full: drop the oldest iterate
+        DMem *y0 = ctx->ng_y.front();
+        ctx->ng_y.erase(ctx->ng_y.begin());
+        ctx->ng_y.push_back(y0);
+        DMem *r0 = ctx->ng_r.front();
+        ctx->ng_r.erase(ctx->ng_r.begin());
+        ctx->ng_r.push_back(r0);
+        HIPCHK(launch_ng_shift(ctx->ng_nh - 1, ctx->ng_G.as<double>(), ctx->stream));
+        ctx->ng_nh--;
+    }
+    const int nh = ctx->ng_nh;
+    PtrTable rt{};
+    for (int a = 0; a < nh - 1; a++) rt.p[a] = ctx->ng_r[a]->as<double>();
+    HIPCHK(launch_ng_append(ctx->npop(), nh, ctx->pops.as<double>(),
+                            ctx->ng_y[nh - 1]->as<double>(), ctx->ng_y[nh]->as<double>(),
+                            ctx->ng_r[nh - 1]->as<double>(), rt, ctx->ng_partial.as<double>(),
+                            ctx->ng_G.as<double>(), ctx->stream));
+    ctx->ng_nh = nh + 1;
+}
+
+static void ng_restart(mgx_ctx *ctx)
+{
+    HIPCHK(launch_copy(ctx->npop(), ctx->pops.as<double>(), ctx->ng_y[0]->as<double>(),
+                       ctx->stream));
+    ctx->ng_nh = 1;
+    ctx->ng_have_prev = false;
+}
+
+static mgx_status update_populations(mgx_ctx *ctx, double *change_out)
+{
+    StateqArgs s{};
+    s.N = ctx->N;
+    s.nlev = ctx->nlev;
+    s.nlines = ctx->nlines;
+    s.ncoll_tr = ctx->ncoll_tr;
+    const size_t per_wave = sizeof(double) * ctx->nlev * (ctx->nlev + 1);
+    s.wpb = (int)std::max<size_t>(1, std::min<size_t>(4, (48 * 1024) / per_wave));
+    s.J = ctx->J.as<double>();
+    s.L = ctx->L.as<double>();
+    s.S64 = ctx->S64.as<double>();
+    s.T = ctx->T.as<double>();
+    s.ncoll = ctx->ncoll.as<double>();
+    s.E = ctx->E.as<double>();
+    s.g = ctx->g.as<double>();
+    s.up = ctx->up.as<int32_t>();
+    s.lo = ctx->lo.as<int32_t>();
+    s.cu = ctx->cu.as<int32_t>();
+    s.cl = ctx->cl.as<int32_t>();
+    s.A = ctx->A.as<double>();
+    s.Bul = ctx->Bul.as<double>();
+    s.Blu = ctx->Blu.as<double>();
+    s.K0 = ctx->K0.as<double>();
+    s.pops_old = ctx->pops.as<double>();
+    s.pops_new = ctx->pops_new.as<double>();
+    s.pop_floor = ctx->opt.pop_floor;
+    s.cnt = ctx->counters.as<Counters>();
+    HIPCHK(launch_reset_counters(ctx->counters.as<Counters>(), ctx->stream));
+    HIPCHK(launch_stateq(s, ctx->stream));
+    std::swap(ctx->pops.p, ctx->pops_new.p);
+    std::swap(ctx->pops.bytes, ctx->pops_new.bytes);
+    if (ctx->ng_active) ng_append(ctx);
+    Counters c = ctx->read_counters();
+    double change;
+    memcpy(&change, &c.change_bits, sizeof(double));
+    ctx->host_cnt.singular = (int64_t)c.singular;
+    ctx->host_cnt.last_change = change;
+    ctx->have_rad = false;
+    if (change_out) *change_out = change;
+    if (c.singular) {
+        ctx->err = "singular statistical-equilibrium system at " + std::to_string(c.singular) +
+                   " point(s)";
+        return MGX_ESINGULAR;
+    }
+    if (c.nonfinite || !std::isfinite(change)) {
+        ctx->err = "non-finite populations";
+        return MGX_ENONFINITE;
+    }
+    return MGX_OK;
+}
+
+extern "C" mgx_status mgx_update_populations(mgx_ctx *ctx, double *max_rel_change_out)
+{
+    API_BEGIN(ctx)
+    REQUIRE(ctx->have_rad, MGX_ESTATE, "mgx_update_populations without a radiation field");
+    mgx_status st = update_populations(ctx, max_rel_change_out);
+    if (st != MGX_OK) return st;
+    API_END(ctx)
+}
+
+static void ng_reset(mgx_ctx *ctx, int capacity)
+{
+    REQUIRE(capacity >= 2 && capacity <= kNgMaxHist, MGX_EINVAL, "Ng capacity must be 2..32");
+    REQUIRE(ctx->have_pops, MGX_ESTATE, "Ng reset without populations");
+    while ((int)ctx->ng_y.size() < capacity) ctx->ng_y.push_back(ng_buffer(ctx));
+    while ((int)ctx->ng_r.size() < capacity) ctx->ng_r.push_back(ng_buffer(ctx));
+    ctx->ng_G.ensure(sizeof(double) * kNgMaxHist * kNgMaxHist);
+    ctx->ng_coef.ensure(sizeof(double) * kNgMaxHist);
+    ctx->ng_status.ensure(sizeof(int) * 4);
+    ctx->ng_partial.ensure(sizeof(double) * 1024 * kNgMaxHist);
+    ctx->ng_pred.ensure(sizeof(double) * ctx->npop());
+    ctx->ng_prev.ensure(sizeof(double) * ctx->npop());
+    ctx->ng_bits.ensure(sizeof(unsigned long long) * 2);
+    ctx->ng_cap = capacity;
+    ctx->ng_active = true;
+    ng_restart(ctx);
+}
+
+extern "C" mgx_status mgx_ng_reset(mgx_ctx *ctx, int capacity)
+{
+    API_BEGIN(ctx)
+    ng_reset(ctx, capacity);
+    ctx->sync();
+    API_END(ctx)
+}
+
+// Forms the prediction into ng_prev (when accepted).  Returns 1 accepted.
+static int ng_predict(mgx_ctx *ctx, double *pred_change)
+{
+    const int K = ctx->ng_nh - 1;
+    *pred_change = INFINITY;
+    if (K < 1) return 0;
+    PtrTable yt{};
+    for (int k = 0; k < K; k++) yt.p[k] = ctx->ng_y[k + 1]->as<double>();
+    HIPCHK(hipMemsetAsync(ctx->ng_status.p, 0, sizeof(int) * 4, ctx->stream));
+    HIPCHK(hipMemsetAsync(ctx->ng_bits.p, 0, sizeof(unsigned long long) * 2, ctx->stream));
+    int *st = ctx->ng_status.as<int>();
+    HIPCHK(launch_ng_predict(ctx->npop(), K, ctx->ng_G.as<double>(), yt,
+                             ctx->ng_coef.as<double>(), st, ctx->ng_pred.as<double>(), st + 1,
+                             ctx->stream));
+    if (ctx->ng_have_prev)
+        HIPCHK(launch_rel_change(ctx->npop(), ctx->ng_pred.as<double>(), ctx->ng_prev.as<double>(),
+                                 ctx->opt.pop_floor, ctx->ng_bits.as<unsigned long long>(),
+                                 ctx->stream));
+    int hs[2];
+    unsigned long long bits = 0;
+    HIPCHK(hipMemcpyAsync(hs, st, sizeof(int) * 2, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(hipMemcpyAsync(&bits, ctx->ng_bits.p, sizeof(bits), hipMemcpyDeviceToHost,
+                          ctx->stream));
+    ctx->sync();
+    const bool ok = hs[0] == 0 && hs[1] == 0;
+    if (ok) {
+        if (ctx->ng_have_prev) memcpy(pred_change, &bits, sizeof(double));
+        std::swap(ctx->ng_pred.p, ctx->ng_prev.p);
+        std::swap(ctx->ng_pred.bytes, ctx->ng_prev.bytes);
+        ctx->ng_have_prev = true;
+    }
+    return ok ? 1 : 0;
+}
+
+static void ng_apply(mgx_ctx *ctx, bool accepted)
+{
+    if (accepted) {
+        HIPCHK(launch_copy(ctx->npop(), ctx->ng_prev.as<double>(), ctx->pops.as<double>(),
+                           ctx->stream));
+        ctx->host_cnt.ng_applied++;
+    } else {
+        ctx->host_cnt.ng_rejected++;
+    }
+    ng_restart(ctx);
+}
+
+extern "C" mgx_status mgx_ng_accelerate(mgx_ctx *ctx, int apply, int *status_out,
+                                        double *pred_change_out)
+{
+    API_BEGIN(ctx)
+    REQUIRE(ctx->ng_active, MGX_ESTATE, "mgx_ng_accelerate without mgx_ng_reset");
+    double pc = INFINITY;
+    const int ok = ng_predict(ctx, &pc);
+    if (apply) ng_apply(ctx, ok != 0);
+    ctx->sync();
+    if (status_out) *status_out = ok;
+    if (pred_change_out) *pred_change_out = pc;
+    API_END(ctx)
+}
+
+extern "C" mgx_status mgx_iterate(mgx_ctx *ctx, double tol, int max_iter, int ng_mode,
+                                  int ng_param, int *iters_out, double *final_change_out)
+{
+    API_BEGIN(ctx)
+    REQUIRE(ctx->traced, MGX_ESTATE, "mgx_iterate before mgx_trace_rays");
+    REQUIRE(ctx->have_pops, MGX_ESTATE, "mgx_iterate without populations");
+    REQUIRE(max_iter >= 1 && tol >= 0, MGX_EINVAL, "max_iter >= 1 and tol >= 0 required");
+    REQUIRE(ng_mode == MGX_NG_NONE || ng_mode == MGX_NG_CLASSICAL || ng_mode == MGX_NG_ADAPTIVE,
+            MGX_EINVAL, "unknown ng_mode");
+    ctx->ng_active = false;
+    if (ng_mode == MGX_NG_CLASSICAL) {
+        REQUIRE(ng_param >= 1 && ng_param + 1 <= kNgMaxHist, MGX_EINVAL,
+                "classical Ng order must be 1..31");
+        ng_reset(ctx, ng_param + 1);
+    } else if (ng_mode == MGX_NG_ADAPTIVE) {
+        REQUIRE(ng_param >= 3 && ng_param <= kNgMaxHist, MGX_EINVAL,
+                "adaptive Ng N_max must be 3..32");
+        ng_reset(ctx, ng_param);
+    }
+    ctx->host_cnt.ng_applied = ctx->host_cnt.ng_rejected = 0;
+    double change = INFINITY;
+    int it = 0;
+    mgx_status result = MGX_ENOCONV;
+    for (it = 1; it <= max_iter; it++) {
+        run_formal_solve(ctx);
+        ctx->have_rad = true;
+        const mgx_status st = update_populations(ctx, &change);
+        if (st != MGX_OK) {
+            result = st;
+            break;
+        }
+        if (change <= tol) {
+            result = MGX_OK;
+            break;
+        }
+        if (ng_mode == MGX_NG_CLASSICAL) {
+            if (ctx->ng_nh == ng_param + 1) {
+                double pc;
+                ng_apply(ctx, ng_predict(ctx, &pc) != 0);
+            }
+        } else if (ng_mode == MGX_NG_ADAPTIVE) {
+            bool use = false;
+            if (ctx->ng_nh >= 3) {
+                double pc;
+                const int ok = ng_predict(ctx, &pc);
+                use = ok && (pc < change || ctx->ng_nh >= ng_param);
+            }
+            if (use) {
+                ng_apply(ctx, true);
+            } else if (ctx->ng_nh >= ng_param) {
+                ng_apply(ctx, false);
+            }
+        }
+    }
+    if (it > max_iter) it = max_iter;
+    ctx->ng_active = false;
+    ctx->host_cnt.iterations = it;
+    ctx->host_cnt.last_change = change;
+    if (iters_out) *iters_out = it;
+    if (final_change_out) *final_change_out = change;
+    ctx->sync();
+    if (result == MGX_ENOCONV)
+        ctx->err = "no convergence within max_iter (last change " + std::to_string(change) + ")";
+    if (result != MGX_OK) return result;
+    API_END(ctx)
+}
+
+extern "C" mgx_status mgx_get_counters(mgx_ctx *ctx, mgx_counters *out)
+{
+    API_BEGIN(ctx)
+    REQUIRE(out, MGX_EINVAL, "out is NULL");
+    ctx->sync();
+    *out = ctx->host_cnt;
+    API_END(ctx)
+}
+
+extern "C" mgx_status mgx_reset_timers(mgx_ctx *ctx)
+{
+    API_BEGIN(ctx)
+    ctx->sync();
+    ctx->host_cnt.fs_launches = 0;
+    ctx->host_cnt.fs_ms_total = 0.0;
+    ctx->host_cnt.fs_ms_last = 0.0;
+    API_END(ctx)
+}
+
+extern "C" mgx_status mgx_render_image(mgx_ctx *ctx, const double dir[3], int npx, int npy,
+                                       double f_min, double f_max, int nfreq, float *img)
+{
+    API_BEGIN(ctx)
+    (void)dir; (void)npx; (void)npy; (void)f_min; (void)f_max; (void)nfreq; (void)img;
+    throw Err{MGX_EINVAL, "mgx_render_image: not available in this build"};
+    API_END(ctx)
+}

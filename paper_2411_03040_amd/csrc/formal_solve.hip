@@ -1,0 +1,414 @@
+// Line coefficients and the formal solution on gfx950.
+//
+// Formal solution (per origin o, ray pair, line l, bin f):
+//  * Comoving offset from line centre at a point of the pair grid, in line
+//    widths, formed in velocity units so float keeps its digits:
+//      x = (x_f b_o + dv + x_f b_o dv / c) / b_point
+//    (Doppler shift of the Gaussian profile; line width equation).
+//  * Opacity chi = chi^ij phi(nu) with the Gaussian profile; the per-point
+//    factor chi^ij / (dnu sqrt(pi)) comes from the line-coefficient table.
+//  * Segment optical depth: trapezoidal rule, or the semi-analytic form
+//    dtau = dx (chi^ij_0 + chi^ij_1)/2 (erf(x1) - erf(x0)) / (2 dnu_bar
+//    (x1 - x0)) where the segment's Doppler shift reaches the threshold
+//    (semi-analytic optical depth equation); floored at tau_floor.
+//  * Second-order Feautrier system on the pair grid, eliminated from both
+//    far ends towards the origin with O(1) state per lane.  With the
+//    scaled unknowns f_j = F_j / dtau_{j+1/2} and e_j / dtau_{j+1/2} of the
+//    Rybicki-Hummer (1991) forward elimination, one step across a point P
+//    followed by a segment of depth dt (dm = previous segment, 0 at a far
+//    end) reads
+//      D  = (dm + dt) / 2,   q = D + g,   inv = 1 / (1 + q dt),
+//      g <- q inv,           eps <- (D S_P + eps) inv,
+//    started with g = 1, eps = I_boundary (the far-end boundary row folds
+//    into the same recursion).  At the origin, with D_o = (dm_- + dm_+)/2,
+//      u = (D_o S_o + eps_- + eps_+) / (D_o + g_- + g_+),
+//      Lambda*_oo = D_o / (D_o + g_- + g_+);
+//    an empty half keeps (dm, g, eps) = (0, 1, I_boundary at the origin), so
+//    boundary origins and isolated points need no special case.
+//  * J-bar = sum_pairs 2 w_r sum_f W_f u, Lambda-bar* likewise.
+//
+// Launch shape: one workgroup per (origin, chunk of lines); one lane per
+// (line, bin) of the chunk, so a line's bins sit in adjacent lanes and the
+// per-point line data of one record is a broadcast for most of a wave.  The
+// workgroup walks the ray pairs of its origin; each pair's records (point,
+// segment length, projected velocity, 1/b-bar, branch bit) and the gathered
+// per-point opacity and source factors of the chunk's lines are staged in
+// LDS in chunks of CH records per half, farthest first, and both halves are
+// swept in the same loop (two independent dependency chains per lane).
+// Reductions over bins happen once per origin in LDS in a fixed order (no
+// atomics: bit-reproducible).
+
+#include "mgx_internal.h"
+
+namespace mgx {
+
+template <typename T>
+struct FM;
+
+template <>
+struct FM<float> {
+    // exp(-x^2) with x already multiplied by sqrt(log2 e)
+    static __device__ __forceinline__ float phi_scaled(float xs)
+    {
+        return __builtin_amdgcn_exp2f(-(xs * xs));
+    }
+    static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+    static __device__ __forceinline__ float erfc_(float x) { return erfcf(x); }
+    static __device__ __forceinline__ float expm1_(float x) { return expm1f(x); }
+};
+
+template <>
+struct FM<double> {
+    static __device__ __forceinline__ double phi_scaled(double x) { return exp(-(x * x)); }
+    static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+    static __device__ __forceinline__ double erfc_(double x) { return erfc(x); }
+    static __device__ __forceinline__ double expm1_(double x) { return expm1(x); }
+};
+
+// erf(b) - erf(a) from two erfc evaluations, without cancellation for
+// arguments of equal sign (the semi-analytic branch guarantees |b - a| is at
+// least about the branch threshold, so the opposite-sign form 2 - erfc - erfc
+// never cancels either).
+template <typename T>
+__device__ __forceinline__ T erf_diff(T a, T b)
+{
+    const T ea = FM<T>::erfc_(fabs(a));
+    const T eb = FM<T>::erfc_(fabs(b));
+    if (a >= (T)0 && b >= (T)0) return ea - eb;
+    if (a <= (T)0 && b <= (T)0) return eb - ea;
+    const T t = (T)2 - ea - eb;
+    return (b > a) ? t : -t;
+}
+
+struct LDSLayout {
+    int ch;
+    size_t ps, dx, dv, ibb, b, ib, chi, S, total;
+};
+
+template <typename T>
+__host__ __device__ inline LDSLayout lds_layout(int ch, int nlc, int nthreads)
+{
+    LDSLayout L;
+    L.ch = ch;
+    size_t o = 0;
+    L.ps = o;
+    o += sizeof(int) * 2 * ch;
+    o = (o + 15) & ~(size_t)15;
+    L.dx = o;
+    o += sizeof(T) * 2 * ch;
+    L.dv = o;
+    o += sizeof(T) * 2 * ch;
+    L.ibb = o;
+    o += sizeof(T) * 2 * ch;
+    L.b = o;
+    o += sizeof(T) * 2 * ch;
+    L.ib = o;
+    o += sizeof(T) * 2 * ch;
+    L.chi = o;
+    o += sizeof(T) * 2 * ch * nlc;
+    L.S = o;
+    o += sizeof(T) * 2 * ch * nlc;
+    const size_t red = sizeof(double) * 2 * nthreads;
+    L.total = o > red ? o : red;
+    return L;
+}
+
+template <typename T>
+struct HalfState {
+    T g, eps, dm;      // elimination state
+    T chi, S, dv, cb;  // previous point: opacity, source, velocity, chi'*b
+    T sdx, sibb;       // segment data stored with the previous record
+    bool semi;
+};
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_formal_solve(FSArgs<T> a, int ch)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const int nb = a.nbins, nl = a.nlines, nlc = a.nlc, nth = a.nthreads;
+    const int o = blockIdx.x;
+    const int l0 = blockIdx.y * nlc;
+    const int nl_here = min(nlc, nl - l0);
+    const int tid = threadIdx.x;
+    const bool active = tid < nl_here * nb;
+    const int ll = min(tid / nb, nl_here - 1);
+    const int f = tid % nb;
+    const int l = l0 + ll;
+
+    const LDSLayout LY = lds_layout<T>(ch, nlc, nth);
+    int *s_ps = (int *)(smem + LY.ps);
+    T *s_dx = (T *)(smem + LY.dx);
+    T *s_dv = (T *)(smem + LY.dv);
+    T *s_ibb = (T *)(smem + LY.ibb);
+    T *s_b = (T *)(smem + LY.b);
+    T *s_ib = (T *)(smem + LY.ib);
+    T *s_chi = (T *)(smem + LY.chi);
+    T *s_S = (T *)(smem + LY.S);
+
+    // per-lane constants
+    const double bo = a.b64[o];
+    const double xfd = a.xf[f];
+    const double xbd = xfd * bo;
+    const T xb = (T)xbd;
+    const T k1 = (T)(1.0 + xbd / kC);
+    const T inv_c = (T)(1.0 / kC);
+    const T acmb = (T)a.acmb[l];
+    const int64_t ol = (int64_t)o * nl + l;
+    const T chi_o = a.chi[ol] * (T)exp(-xfd * xfd);
+    const T S_o = a.S[ol];
+    const T cb_o = a.chi[ol] * a.bpt[o];
+    const T tau_floor = (T)a.tau_floor;
+    const T half = (T)0.5;
+    const T spi4 = (T)(kSqrtPi / 4.0);
+
+    auto bdy_I = [&](T dv) -> T {
+        const T r = k1 * ((T)1 + dv * inv_c);
+        return r * r * r / FM<T>::expm1_(acmb * r);
+    };
+
+    auto row = [&](HalfState<T> &st, T dt) {
+        const T D = (st.dm + dt) * half;
+        const T q = D + st.g;
+        const T inv = FM<T>::rcp((T)1 + q * dt);
+        st.g = q * inv;
+        st.eps = (D * st.S + st.eps) * inv;
+        st.dm = dt;
+    };
+
+    // segment from the previous point of st (farther out) to Q
+    auto segment = [&](HalfState<T> &st, T chiQ, T dvQ, T cbQ) -> T {
+        T dt;
+        if (st.semi) {
+            const T xP = (xb + st.dv * k1) * st.sibb;
+            const T xQ = (xb + dvQ * k1) * st.sibb;
+            const T dxb = (dvQ - st.dv) * k1 * st.sibb;
+            dt = st.sdx * (st.cb + cbQ) * spi4 * st.sibb * erf_diff<T>(xP, xQ) / dxb;
+        } else {
+            dt = st.sdx * (st.chi + chiQ) * half;
+        }
+        return dt > tau_floor ? dt : tau_floor;
+    };
+
+    double accJ = 0.0, accL = 0.0;
+    const int64_t R = a.R;
+    for (int pi = 0; pi < a.npairs; pi++) {
+        const int rp = a.pair_r[pi], rm = a.pair_a[pi];
+        const int64_t offp = a.off[(int64_t)o * R + rp];
+        const int np = (int)(a.off[(int64_t)o * R + rp + 1] - offp);
+        const int64_t offm = a.off[(int64_t)o * R + rm];
+        const int nm = (int)(a.off[(int64_t)o * R + rm + 1] - offm);
+        const int K = max(np, nm);
+
+        HalfState<T> st[2];
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            st[h].g = (T)1;
+            st[h].dm = (T)0;
+            st[h].eps = bdy_I((T)0);  // replaced at the far end of a non-empty half
+            st[h].chi = st[h].S = st[h].dv = st[h].cb = st[h].sdx = st[h].sibb = (T)0;
+            st[h].semi = false;
+        }
+
+        for (int hi = K; hi > 0; hi -= ch) {
+            const int lo = hi - ch > 0 ? hi - ch : 0;
+            __syncthreads();
+            for (int t = tid; t < 2 * ch; t += nth) {
+                const int h = t / ch;
+                const int k = lo + (t - h * ch);
+                const int nh = h ? np : nm;
+                if (k < hi && k < nh) {
+                    const Rec<T> rc = a.rec[(h ? offp : offm) + k];
+                    const int p = rc.ps & 0x7fffffff;
+                    s_ps[t] = rc.ps;
+                    s_dx[t] = rc.dx;
+                    s_dv[t] = rc.dv;
+                    s_ibb[t] = rc.ibb;
+                    s_b[t] = a.bpt[p];
+                    s_ib[t] = a.ibpt[p];
+                }
+            }
+            __syncthreads();
+            for (int t = tid; t < 2 * ch * nl_here; t += nth) {
+                const int e = t / nl_here;
+                const int li = t - e * nl_here;
+                const int h = e / ch;
+                const int k = lo + (e - h * ch);
+                const int nh = h ? np : nm;
+                if (k < hi && k < nh) {
+                    const int64_t idx = (int64_t)(s_ps[e] & 0x7fffffff) * nl + l0 + li;
+                    s_chi[e * nlc + li] = a.chi[idx];
+                    s_S[e * nlc + li] = a.S[idx];
+                }
+            }
+            __syncthreads();
+            for (int k = hi - 1; k >= lo; k--) {
+#pragma unroll
+                for (int h = 0; h < 2; h++) {
+                    const int nh = h ? np : nm;
+                    if (k < nh) {
+                        const int e = h * ch + (k - lo);
+                        const T dvQ = s_dv[e];
+                        const T xQ = (xb + dvQ * k1) * s_ib[e];
+                        const T cQ = s_chi[e * nlc + ll];
+                        const T chiQ = cQ * FM<T>::phi_scaled(xQ);
+                        const T cbQ = cQ * s_b[e];
+                        HalfState<T> &s = st[h];
+                        if (k == nh - 1) {
+                            s.eps = bdy_I(dvQ);
+                        } else {
+                            row(s, segment(s, chiQ, dvQ, cbQ));
+                        }
+                        s.chi = chiQ;
+                        s.S = s_S[e * nlc + ll];
+                        s.dv = dvQ;
+                        s.cb = cbQ;
+                        s.sdx = s_dx[e];
+                        s.sibb = s_ibb[e];
+                        s.semi = s_ps[e] < 0;
+                    }
+                }
+            }
+        }
+        // last segment of each non-empty half ends at the origin
+        if (nm > 0) row(st[0], segment(st[0], chi_o, (T)0, cb_o));
+        if (np > 0) row(st[1], segment(st[1], chi_o, (T)0, cb_o));
+        const T Do = (st[0].dm + st[1].dm) * half;
+        const T inv_den = FM<T>::rcp(Do + st[0].g + st[1].g);
+        const T u = (Do * S_o + st[0].eps + st[1].eps) * inv_den;
+        const T lam = Do * inv_den;
+        const double w = a.pair_w[pi];
+        accJ += w * (double)u;
+        accL += w * (double)lam;
+    }
+
+    __syncthreads();
+    double *s_red = (double *)smem;
+    const double Wf = a.W[f];
+    s_red[tid] = active ? Wf * accJ : 0.0;
+    s_red[nth + tid] = active ? Wf * accL : 0.0;
+    __syncthreads();
+    if (tid < nl_here) {
+        double sj = 0.0, sl = 0.0;
+        for (int ff = 0; ff < nb; ff++) {
+            sj += s_red[tid * nb + ff];
+            sl += s_red[nth + tid * nb + ff];
+        }
+        const int64_t out = (int64_t)o * nl + l0 + tid;
+        a.J[out] = a.Iref[l0 + tid] * sj;
+        a.L[out] = sl;
+    }
+}
+
+template <typename T>
+hipError_t launch_formal_solve(const FSArgs<T> &a, hipStream_t s)
+{
+    int ch = 64;
+    LDSLayout L = lds_layout<T>(ch, a.nlc, a.nthreads);
+    while (L.total > 60 * 1024 && ch > 8) {
+        ch /= 2;
+        L = lds_layout<T>(ch, a.nlc, a.nthreads);
+    }
+    const int nchunks = (a.nlines + a.nlc - 1) / a.nlc;
+    dim3 grid(a.N, nchunks);
+    k_formal_solve<T><<<grid, a.nthreads, L.total, s>>>(a, ch);
+    return hipGetLastError();
+}
+
+template hipError_t launch_formal_solve<float>(const FSArgs<float> &, hipStream_t);
+template hipError_t launch_formal_solve<double>(const FSArgs<double> &, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Per-line constants (Einstein coefficients, scalings) and the bin table.
+// ---------------------------------------------------------------------------
+__global__ void k_line_table(int nlines, const double *A, const double *nu, const double *g,
+                             const int32_t *up, const int32_t *lo, double L_unit, double Tcmb,
+                             double *Bul, double *Blu, double *hnu4pi, double *chiscale,
+                             double *Iref, double *acmb)
+{
+    const int l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= nlines) return;
+    const double v = nu[l];
+    const double bul = A[l] * kC * kC / (2.0 * kH * v * v * v);
+    Bul[l] = bul;
+    Blu[l] = g[up[l]] / g[lo[l]] * bul;
+    hnu4pi[l] = kH * v / (4.0 * kPi);
+    // chi' = chi^ij / (dnu sqrt(pi)) * L_unit, dnu = nu b / c
+    chiscale[l] = kC / (v * kSqrtPi) * L_unit;
+    Iref[l] = 2.0 * kH * v * v * v / (kC * kC);
+    acmb[l] = kH * v / (kKB * Tcmb);
+}
+
+hipError_t launch_line_table(int nlines, int nlev, const double *A, const double *nu,
+                             const double *g, const int32_t *up, const int32_t *lo,
+                             double L_unit, double Tcmb, double *Bul, double *Blu,
+                             double *hnu4pi, double *chiscale, double *Iref, double *acmb,
+                             hipStream_t s)
+{
+    (void)nlev;
+    k_line_table<<<(nlines + 63) / 64, 64, 0, s>>>(nlines, A, nu, g, up, lo, L_unit, Tcmb, Bul,
+                                                   Blu, hnu4pi, chiscale, Iref, acmb);
+    return hipGetLastError();
+}
+
+__global__ void k_bin_table(int nb, double xmax, double *xf, double *W)
+{
+    __shared__ double e[kMaxBins];
+    const int f = threadIdx.x;
+    if (f < nb) {
+        const double x = (nb == 1) ? 0.0 : -xmax + 2.0 * xmax * f / (nb - 1);
+        xf[f] = x;
+        e[f] = exp(-x * x);
+    }
+    __syncthreads();
+    if (f < nb) {
+        double s = 0.0;
+        for (int i = 0; i < nb; i++) s += e[i];
+        W[f] = e[f] / s;
+    }
+}
+
+hipError_t launch_bin_table(int nbins, double xmax, double *xf, double *W, hipStream_t s)
+{
+    k_bin_table<<<1, kMaxBins, 0, s>>>(nbins, xmax, xf, W);
+    return hipGetLastError();
+}
+
+// chi^ij = (h nu / 4 pi)(n_l B_lu - n_u B_ul), eta^ij = (h nu / 4 pi) n_u A,
+// S = eta^ij / chi^ij; stored as chi' = chi^ij c L_unit / (nu b sqrt(pi)) and
+// S / Iref in the solve precision, S in double for statistical equilibrium.
+__global__ void k_line_coeffs(LineArgs a)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)a.N * a.nlines) return;
+    const int p = (int)(i / a.nlines);
+    const int l = (int)(i - (int64_t)p * a.nlines);
+    const double n = a.nspec[p];
+    const double nu_ = n * a.pops[(int64_t)p * a.nlev + a.up[l]];
+    const double nl_ = n * a.pops[(int64_t)p * a.nlev + a.lo[l]];
+    double chi = a.hnu4pi[l] * (nl_ * a.Blu[l] - nu_ * a.Bul[l]);
+    const double eta = a.hnu4pi[l] * nu_ * a.A[l];
+    if (chi <= a.chi_min) {
+        chi = a.chi_min;
+        atomicAdd(&a.cnt->masing, 1ull);
+    }
+    const double S = eta / chi;
+    a.S64[i] = S;
+    const double chis = chi * a.chiscale[l] / a.b[p];
+    const double Ss = S / a.Iref[l];
+    if (a.fp32) {
+        ((float *)a.chiT)[i] = (float)chis;
+        ((float *)a.ST)[i] = (float)Ss;
+    } else {
+        ((double *)a.chiT)[i] = chis;
+        ((double *)a.ST)[i] = Ss;
+    }
+}
+
+hipError_t launch_line_coeffs(const LineArgs &a, hipStream_t s)
+{
+    const int64_t n = (int64_t)a.N * a.nlines;
+    k_line_coeffs<<<(n + 255) / 256, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+}  // namespace mgx

@@ -1,0 +1,148 @@
+// Internal declarations of the gfx950 line radiative transfer library.
+// Device-state layout, kernel argument blocks and launch wrappers shared by
+// the HIP translation units.  Not part of the public ABI (include/mgx.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mgx {
+
+// CODATA 2018 exact SI values.
+constexpr double kH = 6.62607015e-34;
+constexpr double kKB = 1.380649e-23;
+constexpr double kC = 299792458.0;
+constexpr double kPi = 3.14159265358979323846;
+constexpr double kSqrtPi = 1.7724538509055160273;
+constexpr double kLog2e = 1.4426950408889634074;
+
+constexpr int kMaxLevels = 64;
+constexpr int kMaxBins = 1024;
+constexpr int kNgMaxHist = 32;
+
+// Device counters (reset per pass by k_reset_counters).
+struct Counters {
+    unsigned long long masing;
+    unsigned long long singular;
+    unsigned long long nonfinite;
+    unsigned long long holes;
+    unsigned long long semi;
+    unsigned long long change_bits;   // max relative change, as IEEE bits (>= 0)
+    unsigned long long pad[2];
+};
+
+// Packed trace record used by the formal solution: point index with the
+// semi-analytic flag in bit 31, the segment length (scaled by 1/L_unit)
+// from the previous record (or the origin), the projected velocity
+// difference to the origin, and 1/b-bar of that segment.
+template <typename T>
+struct Rec;
+template <>
+struct alignas(16) Rec<float> {
+    int32_t ps;
+    float dx, dv, ibb;
+};
+template <>
+struct alignas(16) Rec<double> {
+    int32_t ps;
+    int32_t pad;
+    double dx, dv, ibb;
+};
+
+struct TraceArgs {
+    int dim, N, R;
+    const double *x, *y, *z, *vx, *vy, *vz;
+    const int32_t *nbs_off, *nbs;
+    const uint8_t *bdy;
+    const double *ray_dir;
+    const double *b2;      // [N] squared Doppler speed
+    double thr;            // branch threshold in line widths
+    int64_t *counts;       // count pass: [N R]
+    const int64_t *off;    // fill pass: [N R + 1]
+    int32_t *r_idx;
+    uint8_t *r_semi;
+    double *r_Z, *r_dv, *r_dx, *r_ibb;
+    Counters *cnt;
+};
+
+template <typename T>
+struct FSArgs {
+    int N, R, npairs, nlines, nbins, nlc, nthreads;
+    const int64_t *off;
+    const Rec<T> *rec;
+    const int32_t *pair_r, *pair_a;
+    const double *pair_w;
+    const T *chi, *S;       // [N][nlines] scaled opacity factor and source
+    const T *bpt, *ibpt;    // [N] b and (scaled) 1/b in T
+    const double *b64;      // [N] b
+    const double *xf, *W;   // [nbins]
+    const double *acmb;     // [nlines] h nu / (k Tcmb)
+    const double *Iref;     // [nlines] 2 h nu^3 / c^2
+    double tau_floor;
+    double *J, *L;          // [N][nlines]
+};
+
+struct LineArgs {
+    int N, nlev, nlines;
+    const double *pops, *nspec, *b;
+    const int32_t *up, *lo;
+    const double *A, *Bul, *Blu, *hnu4pi, *chiscale, *Iref;
+    double chi_min;
+    double *S64;            // [N][nlines] physical source function
+    void *chiT, *ST;        // [N][nlines] in the solve precision
+    int fp32;
+    Counters *cnt;
+};
+
+struct StateqArgs {
+    int N, nlev, nlines, ncoll_tr, wpb;
+    const double *J, *L, *S64;
+    const double *T, *ncoll;
+    const double *E, *g;
+    const int32_t *up, *lo, *cu, *cl;
+    const double *A, *Bul, *Blu, *K0;
+    const double *pops_old;
+    double *pops_new;
+    double pop_floor;
+    Counters *cnt;
+};
+
+// Launch wrappers (return hipError_t of the launch).
+hipError_t launch_point_widths(int N, const double *T, const double *vturb2, double mass,
+                               double *b2, double *b, float *bf, float *ibf_scaled,
+                               double *bd, double *ibd, hipStream_t s);
+hipError_t launch_trace(const TraceArgs &a, bool fill, hipStream_t s);
+hipError_t launch_pack_trace(int64_t n, const int32_t *idx, const uint8_t *semi,
+                             const double *dx, const double *dv, const double *ibb,
+                             double inv_L, bool fp32, void *out, hipStream_t s);
+hipError_t launch_line_coeffs(const LineArgs &a, hipStream_t s);
+template <typename T>
+hipError_t launch_formal_solve(const FSArgs<T> &a, hipStream_t s);
+hipError_t launch_lte(int N, int nlev, const double *T, const double *E, const double *g,
+                      double *pops, hipStream_t s);
+hipError_t launch_stateq(const StateqArgs &a, hipStream_t s);
+hipError_t launch_reset_counters(Counters *c, hipStream_t s);
+hipError_t launch_rel_change(int64_t n, const double *a, const double *b, double floor_,
+                             unsigned long long *bits, hipStream_t s);
+hipError_t launch_bin_table(int nbins, double xmax, double *xf, double *W, hipStream_t s);
+hipError_t launch_line_table(int nlines, int nlev, const double *A, const double *nu,
+                             const double *g, const int32_t *up, const int32_t *lo,
+                             double L_unit, double Tcmb, double *Bul, double *Blu,
+                             double *hnu4pi, double *chiscale, double *Iref, double *acmb,
+                             hipStream_t s);
+hipError_t launch_copy(int64_t n, const double *src, double *dst, hipStream_t s);
+
+// Ng: incremental Gram matrix, solve, combine.  Pointer tables are passed by
+// value (kernel arguments), entry k is residual r_k or iterate y_{k+1}.
+struct PtrTable {
+    const double *p[kNgMaxHist];
+};
+int ng_gram_blocks(int64_t n);
+hipError_t launch_ng_append(int64_t n, int K, const double *src, const double *prev,
+                            double *dst_y, double *dst_r, const PtrTable &r_ptrs,
+                            double *partial, double *G, hipStream_t s);
+hipError_t launch_ng_shift(int K, double *G, hipStream_t s);
+hipError_t launch_ng_predict(int64_t n, int K, const double *G, const PtrTable &y_ptrs,
+                             double *coef, int *status, double *out, int *neg, hipStream_t s);
+
+}  // namespace mgx

@@ -1,0 +1,301 @@
+"""Python binding of libmgx.so (ctypes; argument marshalling only).
+
+Every step of the radiative transfer path runs in the library's HIP kernels.
+PyTorch, when present, supplies the HIP stream (torch's current stream) and
+device tensors may be passed wherever the C ABI accepts host or device
+pointers.  There is no fallback: if the library is missing this module
+raises on import of the library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmgx.so")
+
+MGX_OK, MGX_EINVAL, MGX_ESTATE, MGX_ENOMEM, MGX_EHIP = 0, -1, -2, -3, -4
+MGX_ENOCONV, MGX_ESINGULAR, MGX_ENONFINITE = -5, -6, -7
+FP64, FP32 = 0, 1
+NG_NONE, NG_CLASSICAL, NG_ADAPTIVE = 0, 1, 2
+
+_STATUS = {0: "MGX_OK", -1: "MGX_EINVAL", -2: "MGX_ESTATE", -3: "MGX_ENOMEM", -4: "MGX_EHIP",
+           -5: "MGX_ENOCONV", -6: "MGX_ESINGULAR", -7: "MGX_ENONFINITE"}
+
+
+class MgxError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Options(C.Structure):
+    _fields_ = [("precision", C.c_int), ("branch_threshold", C.c_double),
+                ("tau_floor", C.c_double), ("chi_min", C.c_double), ("pop_floor", C.c_double)]
+
+
+class ModelStruct(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int), ("npoints", C.c_int), ("pos", C.c_void_p), ("vel", C.c_void_p),
+        ("nbs_off", C.c_void_p), ("nbs", C.c_void_p), ("bdy", C.c_void_p), ("T", C.c_void_p),
+        ("vturb2", C.c_void_p), ("nspec", C.c_void_p), ("ncoll", C.c_void_p),
+        ("nrays", C.c_int), ("ray_dir", C.c_void_p), ("ray_w", C.c_void_p),
+        ("antipode", C.c_void_p), ("mass", C.c_double), ("nlev", C.c_int), ("E", C.c_void_p),
+        ("g", C.c_void_p), ("nlines", C.c_int), ("up", C.c_void_p), ("lo", C.c_void_p),
+        ("A", C.c_void_p), ("nu", C.c_void_p), ("ncoll_tr", C.c_int), ("cu", C.c_void_p),
+        ("cl", C.c_void_p), ("K0", C.c_void_p), ("nbins", C.c_int), ("xmax", C.c_double),
+        ("Tcmb", C.c_double),
+    ]
+
+
+class Counters(C.Structure):
+    _fields_ = [("total_records", C.c_int64), ("holes", C.c_int64),
+                ("semi_segments", C.c_int64), ("masing", C.c_int64), ("singular", C.c_int64),
+                ("iterations", C.c_int), ("ng_applied", C.c_int), ("ng_rejected", C.c_int),
+                ("last_change", C.c_double), ("fs_launches", C.c_int64),
+                ("fs_ms_total", C.c_double), ("fs_ms_last", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libmgx.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built (run __graft_entry__.build())")
+    L = C.CDLL(LIB_PATH)
+    P, I, D, I64 = C.c_void_p, C.c_int, C.c_double, C.c_int64
+    sig = {
+        "mgx_default_options": (None, [P]),
+        "mgx_create": (I, [P, I, P, P]),
+        "mgx_destroy": (None, [P]),
+        "mgx_last_error": (C.c_char_p, [P]),
+        "mgx_load_model": (I, [P, P]),
+        "mgx_trace_rays": (I, [P, P]),
+        "mgx_get_trace": (I, [P, C.c_int32, C.c_int32, C.c_int32, P, P, P, P, P]),
+        "mgx_get_trace_offsets": (I, [P, P]),
+        "mgx_get_trace_records": (I, [P, I64, I64, P, P, P, P]),
+        "mgx_set_populations": (I, [P, P]),
+        "mgx_get_populations": (I, [P, P]),
+        "mgx_set_lte_populations": (I, [P]),
+        "mgx_formal_solve": (I, [P, P, P]),
+        "mgx_set_radiation": (I, [P, P, P]),
+        "mgx_update_populations": (I, [P, P]),
+        "mgx_ng_reset": (I, [P, I]),
+        "mgx_ng_accelerate": (I, [P, I, P, P]),
+        "mgx_iterate": (I, [P, D, I, I, I, P, P]),
+        "mgx_get_counters": (I, [P, P]),
+        "mgx_reset_timers": (I, [P]),
+        "mgx_render_image": (I, [P, P, I, I, D, D, I, P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _ptr(a) -> int:
+    """Address of a contiguous numpy array or torch tensor (host or device)."""
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        assert a.flags.c_contiguous
+        return a.ctypes.data
+    if hasattr(a, "data_ptr"):
+        assert a.is_contiguous()
+        return a.data_ptr()
+    raise TypeError(type(a))
+
+
+def _torch_stream(device: int):
+    try:
+        import torch
+    except ImportError:
+        return None
+    if not torch.cuda.is_available():
+        return None
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+class Context:
+    """One model on one GPU.  Mirrors the C ABI entry points by name."""
+
+    def __init__(self, device: int = 0, precision: int = FP32, stream: Optional[int] = None,
+                 use_torch_stream: bool = True, branch_threshold: float = 0.35,
+                 tau_floor: float = 1e-15, chi_min: float = 1e-30, pop_floor: float = 1e-12):
+        L = lib()
+        opt = Options()
+        L.mgx_default_options(C.byref(opt))
+        opt.precision = precision
+        opt.branch_threshold = branch_threshold
+        opt.tau_floor = tau_floor
+        opt.chi_min = chi_min
+        opt.pop_floor = pop_floor
+        if stream is None and use_torch_stream:
+            stream = _torch_stream(device)
+        h = C.c_void_p()
+        st = L.mgx_create(C.byref(h), device, stream, C.byref(opt))
+        if st != MGX_OK:
+            raise MgxError(st, L.mgx_last_error(None).decode())
+        self._h = h
+        self.precision = precision
+        self.model = None
+        self._keep = None
+
+    # -- plumbing -------------------------------------------------------------
+    def _check(self, st: int):
+        if st != MGX_OK:
+            raise MgxError(st, lib().mgx_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().mgx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- model ------------------------------------------------------------------
+    def load_model(self, m) -> None:
+        a = m.arrays()
+        s = ModelStruct()
+        s.dim, s.npoints = m.dim, m.npoints
+        for k in ("pos", "vel", "nbs_off", "nbs", "bdy", "T", "vturb2", "nspec", "ncoll",
+                  "ray_dir", "ray_w", "antipode", "E", "g", "up", "lo", "A", "nu", "cu", "cl",
+                  "K0"):
+            setattr(s, k, a[k].ctypes.data)
+        s.nrays, s.mass, s.nlev, s.nlines = m.nrays, m.mass, m.nlev, m.nlines
+        s.ncoll_tr = int(a["K0"].size)
+        s.nbins, s.xmax, s.Tcmb = m.nbins, m.xmax, m.Tcmb
+        self._check(lib().mgx_load_model(self._h, C.byref(s)))
+        self.model = m
+
+    def trace_rays(self) -> int:
+        n = C.c_int64()
+        self._check(lib().mgx_trace_rays(self._h, C.byref(n)))
+        return n.value
+
+    def get_trace(self, origin: int, ray: int):
+        n = C.c_int32()
+        self._check(lib().mgx_get_trace(self._h, origin, ray, 0, None, None, None, None,
+                                        C.byref(n)))
+        cap = max(n.value, 1)
+        idx = np.zeros(cap, np.int32)
+        Z = np.zeros(cap)
+        dv = np.zeros(cap)
+        semi = np.zeros(cap, np.uint8)
+        self._check(lib().mgx_get_trace(self._h, origin, ray, cap, _ptr(idx), _ptr(Z), _ptr(dv),
+                                        _ptr(semi), C.byref(n)))
+        k = n.value
+        return idx[:k], Z[:k], dv[:k], semi[:k]
+
+    def get_trace_offsets(self) -> np.ndarray:
+        m = self.model
+        off = np.zeros(m.npoints * m.nrays + 1, np.int64)
+        self._check(lib().mgx_get_trace_offsets(self._h, _ptr(off)))
+        return off
+
+    def get_trace_records(self, first: int, count: int):
+        idx = np.zeros(count, np.int32)
+        Z = np.zeros(count)
+        dv = np.zeros(count)
+        semi = np.zeros(count, np.uint8)
+        self._check(lib().mgx_get_trace_records(self._h, first, count, _ptr(idx), _ptr(Z),
+                                                _ptr(dv), _ptr(semi)))
+        return idx, Z, dv, semi
+
+    # -- populations / radiation ---------------------------------------------------
+    def set_populations(self, pops) -> None:
+        if isinstance(pops, np.ndarray):
+            pops = np.ascontiguousarray(pops, np.float64)
+        self._check(lib().mgx_set_populations(self._h, _ptr(pops)))
+
+    def get_populations(self, out=None):
+        m = self.model
+        if out is None:
+            out = np.zeros((m.npoints, m.nlev))
+        self._check(lib().mgx_get_populations(self._h, _ptr(out)))
+        return out
+
+    def set_lte_populations(self) -> None:
+        self._check(lib().mgx_set_lte_populations(self._h))
+
+    def formal_solve(self, J=None, L=None, copy: bool = True):
+        m = self.model
+        if copy and J is None:
+            J = np.zeros((m.npoints, m.nlines))
+            L = np.zeros((m.npoints, m.nlines))
+        self._check(lib().mgx_formal_solve(self._h, _ptr(J), _ptr(L)))
+        return J, L
+
+    def set_radiation(self, J, L) -> None:
+        J = np.ascontiguousarray(J, np.float64) if isinstance(J, np.ndarray) else J
+        L = np.ascontiguousarray(L, np.float64) if isinstance(L, np.ndarray) else L
+        self._check(lib().mgx_set_radiation(self._h, _ptr(J), _ptr(L)))
+
+    def update_populations(self) -> float:
+        ch = C.c_double()
+        self._check(lib().mgx_update_populations(self._h, C.byref(ch)))
+        return ch.value
+
+    def ng_reset(self, capacity: int) -> None:
+        self._check(lib().mgx_ng_reset(self._h, capacity))
+
+    def ng_accelerate(self, apply: bool = True):
+        st, pc = C.c_int(), C.c_double()
+        self._check(lib().mgx_ng_accelerate(self._h, int(apply), C.byref(st), C.byref(pc)))
+        return bool(st.value), pc.value
+
+    def iterate(self, tol: float = 1e-10, max_iter: int = 500, ng_mode: int = NG_NONE,
+                ng_param: int = 4, raise_on_noconv: bool = True):
+        it, ch = C.c_int(), C.c_double()
+        st = lib().mgx_iterate(self._h, tol, max_iter, ng_mode, ng_param, C.byref(it),
+                               C.byref(ch))
+        if st == MGX_ENOCONV and not raise_on_noconv:
+            return it.value, ch.value, False
+        self._check(st)
+        return it.value, ch.value, True
+
+    def counters(self) -> dict:
+        c = Counters()
+        self._check(lib().mgx_get_counters(self._h, C.byref(c)))
+        return {k: getattr(c, k) for k, _ in Counters._fields_}
+
+    def reset_timers(self) -> None:
+        self._check(lib().mgx_reset_timers(self._h))
+
+    def render_image(self, direction, npx: int, npy: int, f_min: float, f_max: float,
+                     nfreq: int, out=None):
+        d = (C.c_double * 3)(*[float(x) for x in direction])
+        if out is None:
+            out = np.zeros((npy, npx, nfreq), np.float32)
+        self._check(lib().mgx_render_image(self._h, d, npx, npy, f_min, f_max, nfreq,
+                                           _ptr(out)))
+        return out
+
+
+def header_functions(header_path: Optional[str] = None):
+    """Names of the functions declared in include/mgx.h."""
+    import re
+    if header_path is None:
+        header_path = os.path.join(os.path.dirname(HERE), "include", "mgx.h")
+    text = open(header_path).read()
+    return sorted(set(re.findall(r"\b(mgx_[a-z_]+)\s*\(", text)))

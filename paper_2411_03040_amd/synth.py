@@ -205,16 +205,18 @@ def knn_lists(pos: np.ndarray, k: int):
     """Directed k-nearest-neighbour lists, sorted by (distance, index)."""
     from scipy.spatial import cKDTree
     P = pos.T
+    N = P.shape[0]
     tree = cKDTree(P)
     dist, idx = tree.query(P, k=k + 1)
-    N = P.shape[0]
-    nbs = np.empty((N, k), dtype=np.int32)
-    for i in range(N):
-        m = idx[i] != i
-        ii = idx[i][m][: k + 1]
-        dd = dist[i][m][: k + 1]
-        order = np.lexsort((ii, dd))[:k]
-        nbs[i] = ii[order]
+    self_hit = idx == np.arange(N)[:, None]
+    # drop the point itself (or the farthest candidate if it was not returned)
+    drop = np.where(self_hit.any(axis=1), self_hit.argmax(axis=1), k)
+    keep = np.ones_like(self_hit)
+    keep[np.arange(N), drop] = False
+    idx = idx[keep].reshape(N, k)
+    dist = dist[keep].reshape(N, k)
+    order = np.lexsort((idx, dist), axis=1)
+    nbs = np.take_along_axis(idx, order, axis=1).astype(np.int32)
     off = np.arange(0, N * k + 1, k, dtype=np.int32)
     return off, nbs.reshape(-1)
 
@@ -256,9 +258,12 @@ def two_level_species(nu0=100e9, A=1e-5, gu=3.0, gl=1.0, K=1e-16, mass_amu=28.0)
 def rotor_species(nlev, rng, B=57.6e9, dipole_debye=0.11, K_base=3e-17, mass_amu=28.0):
     """Synthetic linear rotor: E_J = h B J(J+1), g = 2J+1, lines J -> J-1.
 
-    Einstein A from the rigid-rotor dipole formula; collisional
-    de-excitation coefficients K_ul = K_base * f_ul for every u > l with seeded
-    factors f_ul = 10^U(-0.5, 0.5) / (u - l).
+    Einstein A from the rigid-rotor dipole formula.  Collisional
+    de-excitation coefficients for every u > l fall off with the level jump,
+    K_ul = K_base * exp(-(u - l - 1)) * 10^U(-0.2, 0.2) (seeded scatter), at
+    100 K; the rate law scales them with sqrt(T / 100 K).  (Rates that do not
+    fall off with the jump pump the lowest, nearly thermal line into
+    inversion in warm gas.)
     """
     J = np.arange(nlev, dtype=np.float64)
     E = _H * B * J * (J + 1)
@@ -272,7 +277,7 @@ def rotor_species(nlev, rng, B=57.6e9, dipole_debye=0.11, K_base=3e-17, mass_amu
         for l in range(u):
             cu.append(u)
             cl.append(l)
-            K0.append(K_base * 10 ** rng.uniform(-0.5, 0.5) / (u - l))
+            K0.append(K_base * math.exp(-(u - l - 1)) * 10 ** rng.uniform(-0.2, 0.2))
     return dict(mass=mass_amu * _AMU, E=E, g=g, up=Ju.astype(np.int32),
                 lo=(Ju - 1).astype(np.int32), A=A, nu=nu,
                 cu=np.array(cu, np.int32), cl=np.array(cl, np.int32), K0=np.array(K0))
@@ -325,6 +330,7 @@ def outflow_3d(npoints: int = 50_000, seed: int = 2, k: int = 16, nside: int = 2
     v(r) = 15 km/s (1 - 1/r)^0.5 radial (floor 0.1 km/s), n_coll = n0 r^-2
     (v_inf / v) with n0 = 1e8 cm^-3, T = 2000 r^-0.7 K, abundance 1e-4,
     v_turb = 150 m/s, 10-level rotor, 48 HEALPix rays, 31 bins per line.
+    Rotor collision rates as in rotor_species (seeded).
     """
     rng = np.random.default_rng(seed)
     r0, r1 = 1.0, 20.0
@@ -386,7 +392,7 @@ def clumpy_cloud(npoints: int = 200_000, seed: int = 3, k: int = 16, nside: int 
 
 def tiny_cloud(npoints: int = 24, seed: int = 0, k: Optional[int] = None, nside: int = 1,
                nlev: int = 3, nbins: int = 11, vmax: float = 2e3, tau_scale: float = 1.0,
-               radius: float = 1e13) -> Model:
+               radius: float = 1e13, rotor_B: float = 57.6e9) -> Model:
     """Small random cloud for brute-force checks (complete or kNN lists)."""
     rng = np.random.default_rng(seed)
     p = _uniform_in_shell(rng, npoints, 0.0, 1.0)
@@ -403,7 +409,7 @@ def tiny_cloud(npoints: int = 24, seed: int = 0, k: Optional[int] = None, nside:
     if nlev == 2:
         sp = two_level_species(K=1e-10 * CM3)
     else:
-        sp = rotor_species(nlev, rng)
+        sp = rotor_species(nlev, rng, B=rotor_B)
     d, w, ap = rays_3d(nside)
     return Model(dim=3, pos=p * radius, vel=vel, nbs_off=off, nbs=nbs, bdy=bdy,
                  T=T, vturb2=np.full(npoints, 150.0 ** 2),

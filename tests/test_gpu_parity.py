@@ -1,0 +1,401 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle on
+identical seeded inputs.
+
+Bars: ray traces bit-exact (indices, projected distances, velocity
+differences, branch bits); J-bar, Lambda-bar* and populations to 1e-10
+relative in the FP64 path; the FP32-bulk path to 1e-5 on J-bar / Lambda* and
+1e-4 on converged populations.  Full-size workloads (3D outflow, 50k points;
+clumpy cloud, 200k points) are checked on seeded samples of origins the
+oracle computes one by one, in the same launch configuration the benchmark
+times.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2411_03040_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def mgx():
+    import torch
+    assert torch.cuda.is_available(), "GPU test on a host without a GPU"
+    from paper_2411_03040_amd import mgx as m
+    m.lib()
+    return m
+
+
+def make_ctx(mgx, model, precision):
+    c = mgx.Context(precision=precision)
+    c.load_model(model)
+    c.trace_rays()
+    return c
+
+
+def rel(a, b, floor=1e-300):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.max(np.abs(a - b) / np.maximum(np.abs(b), floor))) if a.size else 0.0
+
+
+def bits_equal(a, b):
+    a = np.ascontiguousarray(a, np.float64)
+    b = np.ascontiguousarray(b, np.float64)
+    return a.shape == b.shape and np.array_equal(a.view(np.int64), b.view(np.int64))
+
+
+# ---------------------------------------------------------------------------
+# Traces: bit-exact
+# ---------------------------------------------------------------------------
+
+def check_traces(ctx, model, pairs):
+    orc = oracle.Oracle(model)
+    off = ctx.get_trace_offsets()
+    total = int(off[-1])
+    idx, Z, dv, semi = ctx.get_trace_records(0, total)
+    R = model.nrays
+    nsemi = 0
+    for (o, r) in pairs:
+        w = o * R + r
+        a, b = int(off[w]), int(off[w + 1])
+        oi, oZ, odv, _ = orc.trace(o, r)
+        assert np.array_equal(idx[a:b], oi), (o, r)
+        assert bits_equal(Z[a:b], oZ), (o, r)
+        assert bits_equal(dv[a:b], odv), (o, r)
+        for k in range(b - a):
+            p0, dv0 = (o, 0.0) if k == 0 else (int(oi[k - 1]), float(odv[k - 1]))
+            exp = orc.use_semi_analytic(p0, dv0, int(oi[k]), float(odv[k]))
+            assert bool(semi[a + k]) == exp, (o, r, k)
+            nsemi += exp
+    return nsemi
+
+
+def all_pairs(model):
+    return [(o, r) for o in range(model.npoints) for r in range(model.nrays)]
+
+
+def test_trace_tiny_complete_lists(mgx):
+    m = synth.tiny_cloud(npoints=40, seed=21, nside=2, vmax=3e3)
+    say("trace tiny complete", m.npoints)
+    ctx = make_ctx(mgx, m, mgx.FP64)
+    n = check_traces(ctx, m, all_pairs(m))
+    assert n > 0
+
+
+def test_trace_knn_cloud(mgx):
+    m = synth.tiny_cloud(npoints=600, seed=22, k=12, nside=2, vmax=5e3)
+    say("trace knn cloud", m.npoints)
+    ctx = make_ctx(mgx, m, mgx.FP32)
+    check_traces(ctx, m, all_pairs(m))
+
+
+def test_trace_lattice_ties(mgx):
+    m = synth.cubic_lattice(n=6)
+    say("trace lattice", m.npoints)
+    ctx = make_ctx(mgx, m, mgx.FP32)
+    check_traces(ctx, m, all_pairs(m))
+
+
+@pytest.mark.parametrize("variant", ["a", "b"])
+def test_trace_spherical_shells(mgx, variant):
+    m = synth.spherical_shells(variant)
+    m.vel[0] = np.linspace(0, 3e3, m.npoints)   # radial velocity exercises dv
+    say("trace shells", variant)
+    ctx = make_ctx(mgx, m, mgx.FP64)
+    check_traces(ctx, m, all_pairs(m))
+
+
+@pytest.fixture(scope="module")
+def outflow():
+    return synth.config(1)
+
+
+@pytest.fixture(scope="module")
+def clumpy():
+    return synth.config(2)
+
+
+def test_trace_outflow_full_sampled(mgx, outflow):
+    m = outflow
+    say("trace outflow 50k sampled")
+    ctx = make_ctx(mgx, m, mgx.FP32)
+    rng = np.random.default_rng(31)
+    pairs = [(int(o), int(r)) for o, r in zip(rng.integers(0, m.npoints, 3000),
+                                              rng.integers(0, m.nrays, 3000))]
+    nsemi = check_traces(ctx, m, pairs)
+    assert nsemi > 0
+    c = ctx.counters()
+    assert c["total_records"] > 0
+
+
+def test_trace_clumpy_full_sampled(mgx, clumpy):
+    m = clumpy
+    say("trace clumpy 200k sampled")
+    ctx = make_ctx(mgx, m, mgx.FP32)
+    rng = np.random.default_rng(32)
+    pairs = [(int(o), int(r)) for o, r in zip(rng.integers(0, m.npoints, 1500),
+                                              rng.integers(0, m.nrays, 1500))]
+    nsemi = check_traces(ctx, m, pairs)
+    assert nsemi > 0
+
+
+# ---------------------------------------------------------------------------
+# Formal solution: J-bar and Lambda-bar*
+# ---------------------------------------------------------------------------
+
+def fs_compare(mgx, model, precision, origins=None, pops=None, tolJ=None, tolL=None):
+    orc = oracle.Oracle(model)
+    if pops is None:
+        pops = orc.lte()
+    ctx = make_ctx(mgx, model, precision)
+    ctx.set_populations(pops)
+    J, L = ctx.formal_solve()
+    Jo, Lo = orc.solve_origins(pops, origins)
+    sel = slice(None) if origins is None else np.asarray(origins)
+    eJ = rel(J[sel], Jo)
+    eL = float(np.max(np.abs(L[sel] - Lo)))
+    say(f"  {model.name} prec={precision} J rel {eJ:.3e} L abs {eL:.3e}")
+    if tolJ is not None:
+        assert eJ < tolJ
+    if tolL is not None:
+        assert eL < tolL
+    return ctx, J, L
+
+
+@pytest.mark.parametrize("variant", ["a", "b"])
+def test_formal_solve_shells_fp64(mgx, variant):
+    m = synth.spherical_shells(variant)
+    fs_compare(mgx, m, mgx.FP64, tolJ=1e-10, tolL=1e-10)
+
+
+@pytest.mark.parametrize("variant", ["a", "b"])
+def test_formal_solve_shells_fp32(mgx, variant):
+    m = synth.spherical_shells(variant)
+    fs_compare(mgx, m, mgx.FP32, tolJ=1e-5, tolL=1e-5)
+
+
+@pytest.mark.parametrize("prec,tolJ,tolL", [(0, 1e-10, 1e-10), (1, 1e-5, 1e-5)])
+def test_formal_solve_moving_cloud(mgx, prec, tolJ, tolL):
+    """Velocities large enough that many segments take the semi-analytic form."""
+    m = synth.tiny_cloud(npoints=300, seed=23, k=12, nside=2, nlev=4, nbins=15, vmax=6e3,
+                         tau_scale=20.0)
+    ctx, J, L = fs_compare(mgx, m, prec, tolJ=tolJ, tolL=tolL)
+    assert ctx.counters()["semi_segments"] > 0
+
+
+@pytest.mark.parametrize("prec,tolJ,tolL", [(0, 1e-10, 1e-10), (1, 1e-5, 1e-5)])
+def test_formal_solve_outflow_full_sampled(mgx, outflow, prec, tolJ, tolL):
+    origins = synth.origin_sample(outflow.npoints, 48, seed=41)
+    fs_compare(mgx, outflow, prec, origins=origins, tolJ=tolJ, tolL=tolL)
+
+
+@pytest.mark.parametrize("prec,tolJ,tolL", [(0, 1e-10, 1e-10), (1, 1e-5, 1e-5)])
+def test_formal_solve_clumpy_full_sampled(mgx, clumpy, prec, tolJ, tolL):
+    origins = synth.origin_sample(clumpy.npoints, 12, seed=42)
+    ctx, _, _ = fs_compare(mgx, clumpy, prec, origins=origins, tolJ=tolJ, tolL=tolL)
+    assert ctx.counters()["semi_segments"] > 0
+
+
+def test_formal_solve_many_line_chunks(mgx):
+    """nlines x nbins above one workgroup: lines split over chunks (ragged)."""
+    m = synth.tiny_cloud(npoints=60, seed=24, k=10, nside=1, nlev=21, nbins=63, vmax=2e3)
+    assert m.nlines * m.nbins > 1024
+    fs_compare(mgx, m, mgx.FP64, tolJ=1e-10, tolL=1e-10)
+    fs_compare(mgx, m, mgx.FP32, tolJ=1e-5, tolL=1e-5)
+
+
+def test_formal_solve_single_bin_and_boundary_only(mgx):
+    m = synth.tiny_cloud(npoints=20, seed=25, nside=1, nlev=2, nbins=1)
+    fs_compare(mgx, m, mgx.FP64, tolJ=1e-10, tolL=1e-10)
+    m2 = synth.tiny_cloud(npoints=12, seed=26, nside=1, nlev=3, nbins=5)
+    m2.bdy[:] = 1               # every walk ends after one step
+    fs_compare(mgx, m2, mgx.FP64, tolJ=1e-10, tolL=1e-10)
+
+
+def test_formal_solve_isolated_points_and_holes(mgx):
+    """Points without neighbours (isolated: both halves empty) and walks that
+    stop on interior points (holes)."""
+    m = synth.tiny_cloud(npoints=50, seed=27, k=6, nside=2, nlev=3, nbins=9)
+    off = m.nbs_off.copy()
+    lists = [list(m.nbs[off[i]:off[i + 1]]) for i in range(m.npoints)]
+    for i in (3, 17, 30):
+        lists[i] = []
+    m.nbs_off = np.concatenate([[0], np.cumsum([len(x) for x in lists])]).astype(np.int32)
+    m.nbs = np.array([j for x in lists for j in x], np.int32)
+    ctx, J, L = fs_compare(mgx, m, mgx.FP64, tolJ=1e-10, tolL=1e-10)
+    assert ctx.counters()["holes"] > 0
+    fs_compare(mgx, m, mgx.FP32, tolJ=1e-5, tolL=1e-5)
+
+
+def test_formal_solve_deterministic(mgx):
+    m = synth.tiny_cloud(npoints=400, seed=28, k=12, nside=2, nlev=5)
+    orc = oracle.Oracle(m)
+    ctx = make_ctx(mgx, m, mgx.FP32)
+    ctx.set_populations(orc.lte())
+    J1, L1 = ctx.formal_solve()
+    J2, L2 = ctx.formal_solve()
+    assert bits_equal(J1, J2) and bits_equal(L1, L2)
+
+
+# ---------------------------------------------------------------------------
+# Statistical equilibrium
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("nlev", [2, 10, 20, 64])
+def test_stateq_parity(mgx, nlev):
+    # small rotational constant for many levels, so every level is populated
+    m = synth.tiny_cloud(npoints=500, seed=29, k=8, nside=1, nlev=nlev, nbins=3,
+                         rotor_B=57.6e9 if nlev <= 20 else 2e9)
+    orc = oracle.Oracle(m)
+    pops = orc.lte()
+    rng = np.random.default_rng(30)
+    _, _, S, _ = orc.line_coeffs(pops)
+    J = S * rng.uniform(0.2, 1.5, S.shape)
+    # keep J_eff = J - L S positive, as a converged radiation field has it
+    L = rng.uniform(0.0, 0.95, S.shape) * np.minimum(1.0, J / S)
+    ctx = make_ctx(mgx, m, mgx.FP64)
+    ctx.set_populations(pops)
+    ctx.set_radiation(J, L)
+    change = ctx.update_populations()
+    got = ctx.get_populations()
+    st, exp = orc.stateq(J, L, S)
+    assert st == 0
+    # conditioning of the problem, measured on the oracle itself: output change
+    # under a relative input perturbation of a few ulps
+    d = 8 * 2.2e-16
+    _, exp2 = orc.stateq(J * (1 + d), L, S)
+    kappa = rel(exp2, exp, 1e-12) / d
+    bar = max(1e-10, 50 * kappa * 2.2e-16)
+    e = rel(got, exp, 1e-12)
+    say(f"  stateq nlev={nlev} rel {e:.3e} kappa {kappa:.2e} bar {bar:.1e}")
+    assert e < bar
+    assert bar < 1e-8
+    assert np.all(np.abs(got.sum(1) - 1) < 1e-13) and np.all(exp > 0)
+    assert abs(change / orc.rel_change(exp, pops) - 1) < 1e-8
+
+
+# ---------------------------------------------------------------------------
+# Lambda-iteration to convergence
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("variant", ["a", "b"])
+def test_iterate_shells_fp64_no_ng(mgx, variant):
+    m = synth.spherical_shells(variant)
+    orc = oracle.Oracle(m)
+    ref = orc.iterate(tol=1e-10, max_iter=1000)
+    ctx = make_ctx(mgx, m, mgx.FP64)
+    ctx.set_lte_populations()
+    it, ch, ok = ctx.iterate(tol=1e-10, max_iter=1000)
+    got = ctx.get_populations()
+    e = rel(got, ref["pops"], 1e-12)
+    say(f"  shells {variant} iters gpu {it} oracle {ref['iters']} rel {e:.3e}")
+    assert ok and it == ref["iters"]
+    assert e < 1e-10
+
+
+@pytest.mark.parametrize("variant,mode,param", [("a", 1, 4), ("b", 1, 4), ("a", 2, 8),
+                                                 ("b", 2, 8)])
+def test_iterate_shells_fp64_ng(mgx, variant, mode, param):
+    m = synth.spherical_shells(variant)
+    orc = oracle.Oracle(m)
+    ref = orc.iterate(tol=1e-13, max_iter=2000, ng_mode=mode, ng_param=param)
+    assert ref["status"] == 0
+    ctx = make_ctx(mgx, m, mgx.FP64)
+    ctx.set_lte_populations()
+    it, ch, ok = ctx.iterate(tol=1e-13, max_iter=2000, ng_mode=mode, ng_param=param)
+    got = ctx.get_populations()
+    e = rel(got, ref["pops"], 1e-12)
+    c = ctx.counters()
+    say(f"  shells {variant} ng {mode}/{param} iters gpu {it} oracle {ref['iters']} "
+        f"applied {c['ng_applied']} rel {e:.3e}")
+    assert ok and e < 1e-10
+    assert c["ng_applied"] > 0
+
+
+@pytest.mark.parametrize("variant", ["a", "b"])
+def test_iterate_shells_fp32_bulk(mgx, variant):
+    m = synth.spherical_shells(variant)
+    orc = oracle.Oracle(m)
+    ref = orc.iterate(tol=1e-12, max_iter=2000, ng_mode=1, ng_param=4)
+    ctx = make_ctx(mgx, m, mgx.FP32)
+    ctx.set_lte_populations()
+    it, ch, ok = ctx.iterate(tol=1e-7, max_iter=2000, ng_mode=1, ng_param=4)
+    got = ctx.get_populations()
+    e = rel(got, ref["pops"], 1e-12)
+    say(f"  shells {variant} fp32 iters {it} rel {e:.3e}")
+    assert ok and e < 1e-4
+
+
+def test_iterate_small_outflow_fp32_and_fp64(mgx):
+    """A reduced outflow (same physics as the 50k-point workload) converged by
+    the oracle, the FP64 path and the FP32-bulk path."""
+    m = synth.outflow_3d(npoints=600, seed=5, nside=1, nlev=6, nbins=15)
+    orc = oracle.Oracle(m)
+    ref = orc.iterate(tol=1e-12, max_iter=400, ng_mode=1, ng_param=4)
+    assert ref["status"] == 0
+    for prec, tol, bar in ((0, 1e-12, 1e-10), (1, 1e-7, 1e-4)):
+        ctx = make_ctx(mgx, m, prec)
+        ctx.set_lte_populations()
+        it, ch, ok = ctx.iterate(tol=tol, max_iter=400, ng_mode=1, ng_param=4)
+        got = ctx.get_populations()
+        e = rel(got, ref["pops"], 1e-12)
+        say(f"  small outflow prec {prec} iters {it} (oracle {ref['iters']}) rel {e:.3e}")
+        assert ok and e < bar
+
+
+# ---------------------------------------------------------------------------
+# Error handling through the ABI
+# ---------------------------------------------------------------------------
+
+def test_error_paths(mgx):
+    m = synth.tiny_cloud(npoints=10, seed=30)
+    c = mgx.Context(precision=mgx.FP32)
+    with pytest.raises(mgx.MgxError) as e:
+        c.trace_rays()
+    assert e.value.status == mgx.MGX_ESTATE
+    bad = m.copy()
+    bad.nbs = bad.nbs.copy()
+    bad.nbs[0] = 10_000
+    with pytest.raises(mgx.MgxError) as e:
+        c.load_model(bad)
+    assert e.value.status == mgx.MGX_EINVAL
+    bad = m.copy()
+    bad.T[3] = np.nan
+    with pytest.raises(mgx.MgxError) as e:
+        c.load_model(bad)
+    assert e.value.status == mgx.MGX_ENONFINITE
+    c.load_model(m)
+    with pytest.raises(mgx.MgxError) as e:
+        c.formal_solve()
+    assert e.value.status == mgx.MGX_ESTATE
+    c.trace_rays()
+    with pytest.raises(mgx.MgxError) as e:
+        c.formal_solve()      # no populations yet
+    assert e.value.status == mgx.MGX_ESTATE
+    with pytest.raises(mgx.MgxError) as e:
+        c.update_populations()
+    assert e.value.status == mgx.MGX_ESTATE
+    c.set_lte_populations()
+    c.formal_solve()
+    c.update_populations()
+    # singular statistical equilibrium: no radiative or collisional coupling
+    s = m.copy()
+    s.A[:] = 0.0
+    s.ncoll[:] = 0.0
+    c.load_model(s)
+    c.trace_rays()
+    c.set_lte_populations()
+    c.formal_solve()
+    with pytest.raises(mgx.MgxError) as e:
+        c.update_populations()
+    assert e.value.status == mgx.MGX_ESINGULAR
+    c.close()
