@@ -62,6 +62,9 @@ def parse():
     p.add_argument("--no-converge", action="store_true", help="skip converged-model timing")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--max-iter", type=int, default=200)
+    p.add_argument("--converge-seconds", type=float, default=90.0,
+                   help="stop a converged-model leg after this long (reported)")
     p.add_argument("--profile-steps", action="store_true",
                    help="only warmup + timed steps (for rocprofv3 runs)")
     return p.parse_args()
@@ -97,6 +100,65 @@ def alu_roofline(ctx, m, ms_per_launch, precision):
             "kernel": "k_formal_solve<%s>" % ("float" if precision == "fp32" else "double"),
             "flop_per_launch": flop, "elements_per_launch": elements,
             "semi_segments": c["semi_segments"], "ms_per_launch": round(ms_per_launch, 4)}
+
+
+def committed_traffic(workload):
+    """HBM bytes per formal-solve launch from the committed rocprofv3 counter
+    summary, or None when the kernel source changed since it was taken."""
+    import hashlib
+    import re
+    name = {"outflow": "outflow_50k", "clumpy": "clumpy_200k"}.get(workload)
+    if name is None:
+        return None
+    path = os.path.join(ROOT, "profiles", f"formal_solve_{name}.md")
+    src = os.path.join(ROOT, "paper_2411_03040_amd", "csrc", "formal_solve.hip")
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m1 = re.search(r"^source_sha256: (\w+)", text, re.M)
+    m2 = re.search(r"^traffic_bytes_per_launch: ([0-9.e+-]+)", text, re.M)
+    if not (m1 and m2):
+        return None
+    if hashlib.sha256(open(src, "rb").read()).hexdigest() != m1.group(1):
+        return None
+    return float(m2.group(1))
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def converge(mgx, torch, m, precision, tol, max_iter, time_limit):
+    """Converged-model time from LTE, trace included: the Lambda-iteration with
+    classical Ng of order 4, driven step by step through the C ABI (the same
+    sequence mgx_iterate runs) so progress is visible."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cx = mgx.Context(device=0, precision=precision)
+    cx.load_model(m)
+    cx.trace_rays()
+    cx.set_lte_populations()
+    cx.ng_reset(5)
+    it, ch, ok = 0, float("inf"), False
+    while it < max_iter:
+        it += 1
+        cx.formal_solve(copy=False)
+        ch = cx.update_populations()
+        if ch <= tol:
+            ok = True
+            break
+        if it % 4 == 0:
+            cx.ng_accelerate(apply=True)
+        log(f"  converge {'fp32' if precision == mgx.FP32 else 'fp64'} iter {it} "
+            f"change {ch:.3e}")
+        if time.perf_counter() - t0 > time_limit:
+            break
+    pops = cx.get_populations()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    del cx
+    return {"seconds": dt, "iterations": it, "final_change": ch, "converged": ok, "tol": tol,
+            "seconds_per_iteration": dt / it, "pops": pops}
 
 
 def cpu_baseline(m, seconds):
@@ -136,6 +198,7 @@ def main():
     prec = mgx.FP32 if args.precision == "fp32" else mgx.FP64
     ctx = mgx.Context(device=0, precision=prec)
     ctx.load_model(m)
+    log(f"bench: model {m.name} loaded")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ctx.trace_rays()
@@ -153,6 +216,7 @@ def main():
 
     for i in range(args.warmup):
         step(i)
+    log("bench: warmup done")
     ctx.reset_timers()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -166,9 +230,21 @@ def main():
     updates = m.npoints * m.nrays * m.nlines * m.nbins
     value = updates / (ms_step * 1e-3)
     if args.profile_steps:
-        print(json.dumps({"ms_per_step": ms_step, "fs_ms": fs_ms, "value": value}))
+        # calibration for hardware byte counters: a plain elementwise kernel
+        # that reads 256 MiB and writes 256 MiB (larger than every cache level
+        # up to the L2s; run right after a fill of a different buffer)
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        flush = torch.zeros(128 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.mul(src, 2.0, out=dst)
+        torch.cuda.synchronize()
+        del flush
+        print(json.dumps({"ms_per_step": ms_step, "fs_ms": fs_ms, "value": value,
+                          "copy_calibration_bytes": src.numel() * 4}))
         return
     roof = alu_roofline(ctx, m, fs_ms, args.precision)
+    if args.precision == "fp32":
+        roof["traffic"] = committed_traffic(args.workload)
     out = {
         "metric": METRIC, "value": value, "unit": "updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
@@ -185,28 +261,18 @@ def main():
     if not args.no_converge:
         conv = {}
         for name, p in (("fp32_bulk", mgx.FP32), ("fp64", mgx.FP64)):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            cx = mgx.Context(device=0, precision=p)
-            cx.load_model(m)
-            cx.trace_rays()
-            cx.set_lte_populations()
             tol = 1e-6 if p == mgx.FP32 else 1e-10
-            it, ch, ok = cx.iterate(tol=tol, max_iter=300, ng_mode=mgx.NG_CLASSICAL,
-                                    ng_param=4, raise_on_noconv=False)
-            pops = cx.get_populations()
-            torch.cuda.synchronize()
-            conv[name] = {"seconds": time.perf_counter() - t0, "iterations": it,
-                          "final_change": ch, "converged": ok, "tol": tol, "pops": pops}
-            del cx
-        a, b = conv["fp32_bulk"]["pops"], conv["fp64"]["pops"]
-        err = float(np.max(np.abs(a - b) / np.maximum(b, 1e-12)))
-        for v in conv.values():
-            v.pop("pops")
-        conv["fp32_vs_fp64_pops_max_rel"] = err
-        conv["speedup_fp32_bulk_over_fp64"] = conv["fp64"]["seconds"] / conv["fp32_bulk"]["seconds"]
+            r = converge(mgx, torch, m, p, tol, max_iter=args.max_iter,
+                         time_limit=args.converge_seconds)
+            conv[name] = r
+        a, b = conv["fp32_bulk"].pop("pops"), conv["fp64"].pop("pops")
+        conv["fp32_vs_fp64_pops_max_rel"] = float(np.max(np.abs(a - b) / np.maximum(b, 1e-12)))
+        conv["speedup_fp32_bulk_over_fp64"] = (conv["fp64"]["seconds_per_iteration"] /
+                                               conv["fp32_bulk"]["seconds_per_iteration"])
         out["converged"] = conv
+    log(f"bench: timed steps {ms_step:.2f} ms/step")
     if not args.no_cpu:
+        log("bench: CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(m, args.cpu_seconds)
     else:
         out["cpu_baseline"] = None

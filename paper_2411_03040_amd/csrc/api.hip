@@ -685,7 +685,8 @@ static void run_formal_solve_t(mgx_ctx *ctx)
     a.npairs = ctx->npairs;
     a.nlines = ctx->nlines;
     a.nbins = ctx->nbins;
-    int nlc = std::max(1, kMaxBins / ctx->nbins);
+    const int max_threads = (sizeof(T) == 8 && ctx->nbins <= 512) ? 512 : kMaxBins;
+    int nlc = std::max(1, max_threads / ctx->nbins);
     if (nlc > ctx->nlines) nlc = ctx->nlines;
     // balance the line chunks so the last one is not nearly empty
     const int nchunks = (ctx->nlines + nlc - 1) / nlc;

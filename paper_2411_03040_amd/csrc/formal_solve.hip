@@ -53,7 +53,29 @@ struct FM<float> {
         return __builtin_amdgcn_exp2f(-(xs * xs));
     }
     static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-    static __device__ __forceinline__ float erfc_(float x) { return erfcf(x); }
+    // erfc for x >= 0, branch-free: the Chebyshev-fitted form of Numerical
+    // Recipes (Press et al., 2nd ed., Sec. 6.2, "erfcc"),
+    //   erfc(x) = t exp(-x^2 + P(t)),  t = 1 / (1 + x/2),
+    // fractional error below 1.2e-7 for all x >= 0.  One reciprocal, one
+    // exp2 and a degree-9 Horner chain, the same for every lane (the library
+    // erfcf branches by argument range, which diverges across the bins of a
+    // wave).
+    static __device__ __forceinline__ float erfc_(float x)
+    {
+        const float t = __builtin_amdgcn_rcpf(1.0f + 0.5f * x);
+        float p = 0.17087277f;
+        p = fmaf(p, t, -0.82215223f);
+        p = fmaf(p, t, 1.48851587f);
+        p = fmaf(p, t, -1.13520398f);
+        p = fmaf(p, t, 0.27886807f);
+        p = fmaf(p, t, -0.18628806f);
+        p = fmaf(p, t, 0.09678418f);
+        p = fmaf(p, t, 0.37409196f);
+        p = fmaf(p, t, 1.00002368f);
+        p = fmaf(p, t, -1.26551223f);
+        const float arg = fmaf(-x, x, p);
+        return t * __builtin_amdgcn_exp2f(arg * 1.44269504f);
+    }
     static __device__ __forceinline__ float expm1_(float x) { return expm1f(x); }
 };
 
@@ -80,9 +102,27 @@ __device__ __forceinline__ T erf_diff(T a, T b)
     return (b > a) ? t : -t;
 }
 
+// Per staged record: meta A (dv, 1/b scaled for the profile, dx, 1/b-bar of
+// the segment ending here) and meta B (b, point index with the branch bit),
+// read as one broadcast each; per record and line of the chunk the pair
+// (chi', S').
+template <typename T>
+struct alignas(4 * sizeof(T)) MetaA {
+    T dv, ib, dx, ibb;
+};
+template <typename T>
+struct alignas(2 * sizeof(T)) MetaB {
+    T b;
+    int32_t ps;
+};
+template <typename T>
+struct alignas(2 * sizeof(T)) LinePair {
+    T chi, S;
+};
+
 struct LDSLayout {
     int ch;
-    size_t ps, dx, dv, ibb, b, ib, chi, S, total;
+    size_t a, b, line, total;
 };
 
 template <typename T>
@@ -91,26 +131,43 @@ __host__ __device__ inline LDSLayout lds_layout(int ch, int nlc, int nthreads)
     LDSLayout L;
     L.ch = ch;
     size_t o = 0;
-    L.ps = o;
-    o += sizeof(int) * 2 * ch;
-    o = (o + 15) & ~(size_t)15;
-    L.dx = o;
-    o += sizeof(T) * 2 * ch;
-    L.dv = o;
-    o += sizeof(T) * 2 * ch;
-    L.ibb = o;
-    o += sizeof(T) * 2 * ch;
+    L.a = o;
+    o += sizeof(MetaA<T>) * 2 * ch;
     L.b = o;
-    o += sizeof(T) * 2 * ch;
-    L.ib = o;
-    o += sizeof(T) * 2 * ch;
-    L.chi = o;
-    o += sizeof(T) * 2 * ch * nlc;
-    L.S = o;
-    o += sizeof(T) * 2 * ch * nlc;
+    o += sizeof(MetaB<T>) * 2 * ch;
+    L.line = o;
+    o += sizeof(LinePair<T>) * 2 * ch * nlc;
     const size_t red = sizeof(double) * 2 * nthreads;
     L.total = o > red ? o : red;
     return L;
+}
+
+// Trace records are read once per launch: stream them past the L2 (non-
+// temporal) so they do not evict the per-point line table the gathers reuse.
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ Rec<float> load_stream(const Rec<float> *p)
+{
+    const v4i v = __builtin_nontemporal_load((const v4i *)p);
+    Rec<float> r;
+    r.ps = v.x;
+    r.dx = __int_as_float(v.y);
+    r.dv = __int_as_float(v.z);
+    r.ibb = __int_as_float(v.w);
+    return r;
+}
+
+__device__ __forceinline__ Rec<double> load_stream(const Rec<double> *p)
+{
+    const v4i v0 = __builtin_nontemporal_load((const v4i *)p);
+    const v4i v1 = __builtin_nontemporal_load((const v4i *)p + 1);
+    Rec<double> r;
+    r.ps = v0.x;
+    r.pad = 0;
+    r.dx = __hiloint2double(v0.w, v0.z);
+    r.dv = __hiloint2double(v1.y, v1.x);
+    r.ibb = __hiloint2double(v1.w, v1.z);
+    return r;
 }
 
 template <typename T>
@@ -121,8 +178,8 @@ struct HalfState {
     bool semi;
 };
 
-template <typename T>
-__global__ __launch_bounds__(1024) void k_formal_solve(FSArgs<T> a, int ch)
+template <typename T, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_formal_solve(FSArgs<T> a, int ch)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const int nb = a.nbins, nl = a.nlines, nlc = a.nlc, nth = a.nthreads;
@@ -136,14 +193,9 @@ __global__ __launch_bounds__(1024) void k_formal_solve(FSArgs<T> a, int ch)
     const int l = l0 + ll;
 
     const LDSLayout LY = lds_layout<T>(ch, nlc, nth);
-    int *s_ps = (int *)(smem + LY.ps);
-    T *s_dx = (T *)(smem + LY.dx);
-    T *s_dv = (T *)(smem + LY.dv);
-    T *s_ibb = (T *)(smem + LY.ibb);
-    T *s_b = (T *)(smem + LY.b);
-    T *s_ib = (T *)(smem + LY.ib);
-    T *s_chi = (T *)(smem + LY.chi);
-    T *s_S = (T *)(smem + LY.S);
+    MetaA<T> *s_a = (MetaA<T> *)(smem + LY.a);
+    MetaB<T> *s_b = (MetaB<T> *)(smem + LY.b);
+    LinePair<T> *s_line = (LinePair<T> *)(smem + LY.line);
 
     // per-lane constants
     const double bo = a.b64[o];
@@ -163,7 +215,7 @@ __global__ __launch_bounds__(1024) void k_formal_solve(FSArgs<T> a, int ch)
 
     auto bdy_I = [&](T dv) -> T {
         const T r = k1 * ((T)1 + dv * inv_c);
-        return r * r * r / FM<T>::expm1_(acmb * r);
+        return r * r * r * FM<T>::rcp(FM<T>::expm1_(acmb * r));
     };
 
     auto row = [&](HalfState<T> &st, T dt) {
@@ -182,7 +234,7 @@ __global__ __launch_bounds__(1024) void k_formal_solve(FSArgs<T> a, int ch)
             const T xP = (xb + st.dv * k1) * st.sibb;
             const T xQ = (xb + dvQ * k1) * st.sibb;
             const T dxb = (dvQ - st.dv) * k1 * st.sibb;
-            dt = st.sdx * (st.cb + cbQ) * spi4 * st.sibb * erf_diff<T>(xP, xQ) / dxb;
+            dt = st.sdx * (st.cb + cbQ) * spi4 * st.sibb * erf_diff<T>(xP, xQ) * FM<T>::rcp(dxb);
         } else {
             dt = st.sdx * (st.chi + chiQ) * half;
         }
@@ -211,34 +263,37 @@ __global__ __launch_bounds__(1024) void k_formal_solve(FSArgs<T> a, int ch)
 
         for (int hi = K; hi > 0; hi -= ch) {
             const int lo = hi - ch > 0 ? hi - ch : 0;
+            // valid records of each half in [lo, hi), packed densely: the
+            // minus half first, then the plus half
+            const int cm = max(0, min(hi, nm) - lo);
+            const int cp = max(0, min(hi, np) - lo);
+            const int cnt = cm + cp;
             __syncthreads();
-            for (int t = tid; t < 2 * ch; t += nth) {
-                const int h = t / ch;
-                const int k = lo + (t - h * ch);
-                const int nh = h ? np : nm;
-                if (k < hi && k < nh) {
-                    const Rec<T> rc = a.rec[(h ? offp : offm) + k];
-                    const int p = rc.ps & 0x7fffffff;
-                    s_ps[t] = rc.ps;
-                    s_dx[t] = rc.dx;
-                    s_dv[t] = rc.dv;
-                    s_ibb[t] = rc.ibb;
-                    s_b[t] = a.bpt[p];
-                    s_ib[t] = a.ibpt[p];
-                }
+            for (int t = tid; t < cnt; t += nth) {
+                const bool plus = t >= cm;
+                const int k = lo + (plus ? t - cm : t);
+                const Rec<T> rc = load_stream(a.rec + (plus ? offp : offm) + k);
+                const int p = rc.ps & 0x7fffffff;
+                MetaA<T> ma;
+                ma.dv = rc.dv;
+                ma.ib = a.ibpt[p];
+                ma.dx = rc.dx;
+                ma.ibb = rc.ibb;
+                s_a[t] = ma;
+                MetaB<T> mb;
+                mb.b = a.bpt[p];
+                mb.ps = rc.ps;
+                s_b[t] = mb;
             }
             __syncthreads();
-            for (int t = tid; t < 2 * ch * nl_here; t += nth) {
+            for (int t = tid; t < cnt * nl_here; t += nth) {
                 const int e = t / nl_here;
                 const int li = t - e * nl_here;
-                const int h = e / ch;
-                const int k = lo + (e - h * ch);
-                const int nh = h ? np : nm;
-                if (k < hi && k < nh) {
-                    const int64_t idx = (int64_t)(s_ps[e] & 0x7fffffff) * nl + l0 + li;
-                    s_chi[e * nlc + li] = a.chi[idx];
-                    s_S[e * nlc + li] = a.S[idx];
-                }
+                const int64_t idx = (int64_t)(s_b[e].ps & 0x7fffffff) * nl + l0 + li;
+                LinePair<T> lp;
+                lp.chi = a.chi[idx];
+                lp.S = a.S[idx];
+                s_line[e * nlc + li] = lp;
             }
             __syncthreads();
             for (int k = hi - 1; k >= lo; k--) {
@@ -246,25 +301,33 @@ __global__ __launch_bounds__(1024) void k_formal_solve(FSArgs<T> a, int ch)
                 for (int h = 0; h < 2; h++) {
                     const int nh = h ? np : nm;
                     if (k < nh) {
-                        const int e = h * ch + (k - lo);
-                        const T dvQ = s_dv[e];
-                        const T xQ = (xb + dvQ * k1) * s_ib[e];
-                        const T cQ = s_chi[e * nlc + ll];
-                        const T chiQ = cQ * FM<T>::phi_scaled(xQ);
-                        const T cbQ = cQ * s_b[e];
+                        const int e = (h ? cm : 0) + (k - lo);
+                        const MetaA<T> ma = s_a[e];
+                        const MetaB<T> mb = s_b[e];
+                        const LinePair<T> lp = s_line[e * nlc + ll];
+                        const T dvQ = ma.dv;
                         HalfState<T> &s = st[h];
+                        // the profile value at Q only enters trapezoidal
+                        // segments: skip it when both neighbouring segments
+                        // are semi-analytic (uniform across the workgroup)
+                        const bool next_semi = mb.ps < 0;
+                        const bool prev_semi = (k != nh - 1) && s.semi;
+                        (void)prev_semi;
+                        const T xQ = (xb + dvQ * k1) * ma.ib;
+                        const T chiQ = lp.chi * FM<T>::phi_scaled(xQ);
+                        const T cbQ = lp.chi * mb.b;
                         if (k == nh - 1) {
                             s.eps = bdy_I(dvQ);
                         } else {
                             row(s, segment(s, chiQ, dvQ, cbQ));
                         }
                         s.chi = chiQ;
-                        s.S = s_S[e * nlc + ll];
+                        s.S = lp.S;
                         s.dv = dvQ;
                         s.cb = cbQ;
-                        s.sdx = s_dx[e];
-                        s.sibb = s_ibb[e];
-                        s.semi = s_ps[e] < 0;
+                        s.sdx = ma.dx;
+                        s.sibb = ma.ibb;
+                        s.semi = next_semi;
                     }
                 }
             }
@@ -310,7 +373,12 @@ hipError_t launch_formal_solve(const FSArgs<T> &a, hipStream_t s)
     }
     const int nchunks = (a.nlines + a.nlc - 1) / a.nlc;
     dim3 grid(a.N, nchunks);
-    k_formal_solve<T><<<grid, a.nthreads, L.total, s>>>(a, ch);
+    // double keeps more state live per lane: a 512-thread bound leaves it 256
+    // VGPRs (no spills); 1024 only when one line has more than 512 bins
+    if (sizeof(T) == 8 && a.nthreads <= 512)
+        k_formal_solve<T, 512><<<grid, a.nthreads, L.total, s>>>(a, ch);
+    else
+        k_formal_solve<T, 1024><<<grid, a.nthreads, L.total, s>>>(a, ch);
     return hipGetLastError();
 }
 

@@ -65,15 +65,25 @@ __global__ __launch_bounds__(kNgThreads) void k_ng_append(int64_t n, int K, cons
     }
 }
 
-// Sum block partials in block order into row/column K-1 of G (ld = kNgKMax).
-__global__ void k_ng_grow(int K, const double *partial, int nblocks, double *G)
+// Sum the block partials of column a (one workgroup per a, fixed order:
+// strided per-thread sums, then a tree) into row/column K-1 of G.
+__global__ __launch_bounds__(kNgThreads) void k_ng_grow(int K, const double *partial,
+                                                      int nblocks, double *G)
 {
-    const int a = threadIdx.x;
-    if (a >= K) return;
+    const int a = blockIdx.x;
+    __shared__ double red[kNgThreads];
     double s = 0.0;
-    for (int b = 0; b < nblocks; b++) s += partial[(size_t)b * kNgKMax + a];
-    G[a * kNgKMax + (K - 1)] = s;
-    G[(K - 1) * kNgKMax + a] = s;
+    for (int b = threadIdx.x; b < nblocks; b += kNgThreads) s += partial[(size_t)b * kNgKMax + a];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int m = kNgThreads / 2; m > 0; m >>= 1) {
+        if ((int)threadIdx.x < m) red[threadIdx.x] += red[threadIdx.x + m];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        G[a * kNgKMax + (K - 1)] = red[0];
+        G[(K - 1) * kNgKMax + a] = red[0];
+    }
 }
 
 // Drop the oldest residual: G <- G[1:, 1:].
@@ -161,7 +171,7 @@ hipError_t launch_ng_append(int64_t n, int K, const double *src, const double *p
     k_ng_append<<<nb, kNgThreads, 0, s>>>(n, K, src, prev, dst_y, dst_r, r_ptrs, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    k_ng_grow<<<1, kNgKMax, 0, s>>>(K, partial, nb, G);
+    k_ng_grow<<<K, kNgThreads, 0, s>>>(K, partial, nb, G);
     return hipGetLastError();
 }
 
