@@ -65,6 +65,8 @@ def parse():
     p.add_argument("--max-iter", type=int, default=200)
     p.add_argument("--converge-seconds", type=float, default=90.0,
                    help="stop a converged-model leg after this long (reported)")
+    p.add_argument("--ng-study", action="store_true",
+                   help="classical vs adaptive Ng iteration counts on the spherical shells")
     p.add_argument("--profile-steps", action="store_true",
                    help="only warmup + timed steps (for rocprofv3 runs)")
     return p.parse_args()
@@ -183,6 +185,32 @@ def cpu_baseline(m, seconds):
                       f"seeded origins of the same model from LTE populations, {t:.1f} s"}
 
 
+def ng_study(mgx, torch):
+    """Iterations to converge (1e-10, FP64) with no Ng, classical Ng of N_steps
+    and adaptive Ng with N_max, on the two spherical variants (moderate and
+    high optical depth): the comparison of the paper's Ng section."""
+    from paper_2411_03040_amd import synth
+    res = {}
+    for variant in ("a", "b"):
+        m = synth.spherical_shells(variant)
+        row = {}
+        for label, mode, param in ([("none", mgx.NG_NONE, 0)] +
+                                   [(f"classical_{n}", mgx.NG_CLASSICAL, n) for n in (2, 3, 4, 8)] +
+                                   [(f"adaptive_{n}", mgx.NG_ADAPTIVE, n) for n in (4, 8, 16, 32)]):
+            cx = mgx.Context(device=0, precision=mgx.FP64)
+            cx.load_model(m)
+            cx.trace_rays()
+            cx.set_lte_populations()
+            it, ch, ok = cx.iterate(tol=1e-10, max_iter=2000, ng_mode=mode, ng_param=param if mode else 4,
+                                    raise_on_noconv=False)
+            c = cx.counters()
+            row[label] = {"iterations": it, "converged": ok, "ng_applied": c["ng_applied"]}
+            log(f"  ng-study {variant} {label}: {it} iterations")
+            del cx
+        res[f"shells_{variant}"] = row
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -194,6 +222,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
+    if args.ng_study:
+        print(json.dumps({"ng_study": ng_study(mgx, torch)}), flush=True)
+        return
     m, desc = make_model(args.workload)
     prec = mgx.FP32 if args.precision == "fp32" else mgx.FP64
     ctx = mgx.Context(device=0, precision=prec)

@@ -76,6 +76,8 @@ def lib():
         L.orc_ng.argtypes = [C.c_int, C.c_int64, P, P, P]
         L.orc_iterate.argtypes = [P, P, C.c_double, C.c_int, C.c_int, C.c_int, P, P, P]
         L.orc_num_threads.restype = C.c_int
+        L.orc_render_pixel.argtypes = [P, P, P, P, C.c_int, C.c_int, C.c_double, C.c_double,
+                                       C.c_int, C.c_int, C.c_int, P, P, C.c_int, P]
         _lib = L
     return _lib
 
@@ -230,3 +232,20 @@ class Oracle:
                                C.byref(iters), C.byref(ch), _p(hist))
         return dict(status=st, pops=pops, iters=iters.value, change=ch.value,
                     history=hist[: iters.value].copy())
+
+    def render_pixels(self, pops, direction, npx, npy, f_min, f_max, nfreq, pixels):
+        """Intensities [len(pixels)][nfreq] and walks of the given (ix, iy) pixels."""
+        chi, _, S, _ = self.line_coeffs(pops)
+        d = np.ascontiguousarray(direction, np.float64)
+        out = np.zeros((len(pixels), nfreq))
+        walks = []
+        cap = self.model.npoints + 1
+        buf = np.zeros(cap, np.int32)
+        for i, (ix, iy) in enumerate(pixels):
+            I = np.zeros(nfreq)
+            nw = C.c_int()
+            lib().orc_render_pixel(self.ptr, _p(chi), _p(S), _p(d), npx, npy, f_min, f_max,
+                                   nfreq, ix, iy, _p(I), _p(buf), cap, C.byref(nw))
+            out[i] = I
+            walks.append(buf[:nw.value].copy())
+        return out, walks

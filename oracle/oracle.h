@@ -90,6 +90,16 @@ int orc_ng(int nhist, int64_t n, const double *hist, double *out, double *coeffs
 int orc_iterate(const orc_model *m, double *pops, double tol, int max_iter, int ng_mode,
                 int ng_param, int *iters_out, double *change_out, double *change_hist);
 
+/* Synthetic image (channel maps) along direction dir: npx x npy pixels over
+   the projected extent of the cloud, nfreq observer-frame frequencies
+   f_min..f_max.  Computes one pixel: intensity I[nfreq] and the walk (point
+   indices, at most cap; *nwalk its full length, 0 if the pixel misses the
+   cloud). */
+void orc_render_pixel(const orc_model *m, const double *chi_ij, const double *S,
+                      const double dir[3], int npx, int npy, double f_min, double f_max,
+                      int nfreq, int ix, int iy, double *I, int32_t *walk, int cap,
+                      int *nwalk);
+
 int orc_num_threads(void);
 
 #endif

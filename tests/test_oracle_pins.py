@@ -638,3 +638,88 @@ def test_converged_shells_no_masing_and_normalised():
         assert res["status"] == 0
         assert np.all(np.abs(res["pops"].sum(1) - 1) < 1e-13)
         assert o.line_coeffs(res["pops"])[3] == 0
+
+
+# ---------------------------------------------------------------------------
+# Synthetic images
+# ---------------------------------------------------------------------------
+
+def _planck(nu, T):
+    return 2 * H * nu ** 3 / C ** 2 / math.expm1(H * nu / (KB * T))
+
+
+def test_render_pixel_outside_cloud_is_cmb():
+    m = synth.tiny_cloud(npoints=2000, seed=40, k=12, nside=1, nlev=2, nbins=5)
+    o = oracle.Oracle(m)
+    f = np.linspace(100e9 * (1 - 3e-6), 100e9 * (1 + 3e-6), 7)
+    I, walks = o.render_pixels(o.lte(), [0.0, 0.0, 1.0], 21, 21, f[0], f[-1], 7,
+                               [(0, 0), (20, 20), (10, 10)])
+    for k in (0, 1):
+        assert walks[k].size == 0
+        assert np.allclose(I[k], [_planck(x, m.Tcmb) for x in f], rtol=1e-14, atol=0)
+    assert walks[2].size > 3
+
+
+def test_render_homogeneous_column_closed_form():
+    """Static uniform lattice viewed along +x: every interior pixel column is a
+    uniform slab, I = B_bg e^-tau + S (1 - e^-tau) with tau = L chi(nu)."""
+    n = 9
+    m = synth.cubic_lattice(n=n, nbins=5)
+    m.nspec[:] = 3e5
+    o = oracle.Oracle(m)
+    pops = o.lte()
+    chi, _, S, _ = o.line_coeffs(pops)
+    nu0 = m.nu[0]
+    b = math.sqrt(2 * KB * m.T[0] / m.mass + m.vturb2[0])
+    dnu = nu0 * b / C
+    f = nu0 + dnu * np.linspace(-3, 3, 11)
+    I, walks = o.render_pixels(pops, [1.0, 0.0, 0.0], n, n, f[0], f[-1], 11, [(4, 4), (2, 5)])
+    L = (n - 1) * 1e12
+    for k in range(2):
+        assert walks[k].size == n
+        for i, nu in enumerate(f):
+            tau = L * chi[0, 0] * math.exp(-((nu - nu0) / dnu) ** 2) / (dnu * math.sqrt(math.pi))
+            exp_I = _planck(nu, m.Tcmb) * math.exp(-tau) + S[0, 0] * (1 - math.exp(-tau))
+            assert abs(I[k, i] / exp_I - 1) < 1e-11
+    assert L * chi[0, 0] / (dnu * math.sqrt(math.pi)) > 1.0
+
+
+def test_render_uniform_velocity_is_a_doppler_shift():
+    m = synth.tiny_cloud(npoints=300, seed=41, k=12, nside=1, nlev=3, nbins=5, vmax=0.0,
+                         tau_scale=10.0)
+    m.T[:] = 80.0
+    o = oracle.Oracle(m)
+    pops = o.lte()
+    d = np.array([0.3, -0.5, 0.8])
+    d /= np.linalg.norm(d)
+    w = 1500.0
+    mv = m.copy()
+    mv.vel = np.tile((w * d)[:, None], (1, m.npoints))
+    ov = oracle.Oracle(mv)
+    nu0 = m.nu[0]
+    fa, fb = nu0 * (1 - 1e-5), nu0 * (1 + 1e-5)
+    pix = [(3, 4), (5, 5), (2, 6)]
+    Iv, wv = ov.render_pixels(pops, d, 8, 8, fa, fb, 9, pix)
+    s = 1 - w / C
+    Is, ws = o.render_pixels(pops, d, 8, 8, fa * s, fb * s, 9, pix)
+    for k in range(len(pix)):
+        assert np.array_equal(wv[k], ws[k]) and wv[k].size > 2
+    assert np.allclose(Iv, Is, rtol=1e-9, atol=0)
+
+
+def test_render_thin_limit_is_emission_integral():
+    n = 7
+    m = synth.cubic_lattice(n=n, nbins=5)
+    m.nspec[:] = 1e-6        # optical depth ~1e-12
+    o = oracle.Oracle(m)
+    pops = o.lte()
+    chi, eta, S, _ = o.line_coeffs(pops)
+    nu0 = m.nu[0]
+    b = math.sqrt(2 * KB * m.T[0] / m.mass + m.vturb2[0])
+    dnu = nu0 * b / C
+    I, _ = o.render_pixels(pops, [0.0, 1.0, 0.0], n, n, nu0, nu0, 1, [(3, 3)])
+    phi = 1 / (dnu * math.sqrt(math.pi))
+    Bg = _planck(nu0, m.Tcmb)
+    # emission minus absorption of the background, both linear in tau
+    net = (n - 1) * 1e12 * phi * (eta[0, 0] - chi[0, 0] * Bg)
+    assert abs((I[0, 0] - Bg) / net - 1) < 1e-6
