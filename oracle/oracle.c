@@ -917,22 +917,34 @@ void orc_render_pixel(const orc_model *m, const double *chi_ij, const double *S,
     /* integration */
     for (int f = 0; f < nfreq; f++) {
         const double nu = (nfreq == 1) ? f_min : f_min + (f_max - f_min) * f / (nfreq - 1);
-        double chi0 = 0.0, eta0 = 0.0, Icur = 0.0;
+        double S0 = 0.0, Icur = 0.0;
         for (int k = 0; k < n; k++) {
             const int p = pts[k];
             const double w = VEL(m, 0, p) * d[0] + VEL(m, 1, p) * d[1] + VEL(m, 2, p) * d[2];
             const double b = sqrt(doppler_b2(m, p));
-            double chi1 = 0.0, eta1 = 0.0, dt = 0.0;
+            /* source function S = eta / chi over all lines.  S is
+               the profile-weighted mean of the line source functions; the
+               weights are taken relative to the nearest line, exp(-(x_l^2 -
+               x_min^2)), so S keeps its value where every profile underflows
+               (large Doppler offsets) instead of becoming 0/0. */
+            double dt = 0.0, x2min = INFINITY;
             for (int l = 0; l < nl; l++) {
                 const double nul = m->nu[l];
                 /* offset of the comoving frequency nu (1 - w/c) from the line,
                    in widths, in velocity units */
                 const double x = (C_LIGHT * (nu - nul) / nul - (nu / nul) * w) / b;
-                const double dnu = nul * b / C_LIGHT;
-                const double ch = chi_ij[(int64_t)p * nl + l] * exp(-x * x) / (dnu * sqrt(PI));
-                chi1 += ch;
-                eta1 += ch * S[(int64_t)p * nl + l];
+                if (x * x < x2min) x2min = x * x;
             }
+            double sw = 0.0, sws = 0.0;
+            for (int l = 0; l < nl; l++) {
+                const double nul = m->nu[l];
+                const double x = (C_LIGHT * (nu - nul) / nul - (nu / nul) * w) / b;
+                const double dnu = nul * b / C_LIGHT;
+                const double wt = chi_ij[(int64_t)p * nl + l] * exp(-(x * x - x2min)) / dnu;
+                sw += wt;
+                sws += wt * S[(int64_t)p * nl + l];
+            }
+            const double S1 = sw > 0.0 ? sws / sw : 0.0;
             if (k == 0) {
                 Icur = orc_planck(nu * (1.0 - w / C_LIGHT), m->Tcmb);
             } else {
@@ -960,14 +972,11 @@ void orc_render_pixel(const orc_model *m, const double *chi_ij, const double *S,
                         dt += orc_dtau_trapezoid(dx, c0, c1);
                     }
                 }
-                const double S0 = chi0 > 0.0 ? eta0 / chi0 : 0.0;
-                const double S1 = chi1 > 0.0 ? eta1 / chi1 : 0.0;
                 double att, wa, wb;
                 linear_source_weights(dt, &att, &wa, &wb);
                 Icur = Icur * att + S0 * wa + S1 * wb;
             }
-            chi0 = chi1;
-            eta0 = eta1;
+            S0 = S1;
         }
         I[f] = Icur;
     }

@@ -723,3 +723,38 @@ def test_render_thin_limit_is_emission_integral():
     # emission minus absorption of the background, both linear in tau
     net = (n - 1) * 1e12 * phi * (eta[0, 0] - chi[0, 0] * Bg)
     assert abs((I[0, 0] - Bg) / net - 1) < 1e-6
+
+
+def test_render_steep_gradient_column_closed_form():
+    """Homogeneous column with a steep linear velocity gradient along the line
+    of sight: every segment takes the semi-analytic form, which is exact here
+    (constant chi^ij and width, offset linear along the path), and most point
+    profiles underflow at a given frequency; the source function stays the
+    line's.  Closed form I = B(nu'_entry) e^-tau + S (1 - e^-tau) with
+    tau = chi^ij L / (dnu sqrt(pi)) * (sqrt(pi)/2) (erf(x_L) - erf(x_0)) / (x_L - x_0)."""
+    from scipy.special import erf
+    n = 9
+    m = synth.cubic_lattice(n=n, nbins=5)
+    m.nspec[:] = 3e5
+    sp = 1e12
+    grad = 40e3 / ((n - 1) * sp)          # 40 km/s across the column
+    m.vel[0] = grad * m.pos[0]
+    o = oracle.Oracle(m)
+    pops = o.lte()
+    chi, _, S, _ = o.line_coeffs(pops)
+    nu0 = m.nu[0]
+    b = math.sqrt(2 * KB * m.T[0] / m.mass + m.vturb2[0])
+    assert grad * sp / b > 20                # shift per segment in widths
+    dnu = nu0 * b / C
+    f = nu0 * (1 - np.linspace(0, 1.2e-4, 13))
+    I, walks = o.render_pixels(pops, [1.0, 0.0, 0.0], n, n, f[-1], f[0], 13, [(4, 4)])
+    L = (n - 1) * sp
+    for i, nu in enumerate(np.sort(f)):
+        x0 = (C * (nu - nu0) / nu0 - (nu / nu0) * 0.0) / b
+        xL = (C * (nu - nu0) / nu0 - (nu / nu0) * grad * L) / b
+        tau = chi[0, 0] / (dnu * math.sqrt(math.pi)) * L * (math.sqrt(math.pi) / 2) * \
+            (erf(xL) - erf(x0)) / (xL - x0)
+        Bg = _planck(nu * (1 - 0.0 / C), m.Tcmb)
+        exp_I = Bg * math.exp(-tau) + S[0, 0] * (1 - math.exp(-tau))
+        assert abs(I[0, i] / exp_I - 1) < 1e-9, (i, I[0, i], exp_I, tau)
+    assert max(walks[0].size for _ in [0]) == n
