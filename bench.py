@@ -273,6 +273,20 @@ def main():
         print(json.dumps({"ms_per_step": ms_step, "fs_ms": fs_ms, "value": value,
                           "copy_calibration_bytes": src.numel() * 4}))
         return
+    # synthetic image as the serving workload asks for it: 256 x 256 pixels x 63
+    # bins around the second line at a seeded inclination
+    rng = np.random.default_rng(7)
+    th = rng.uniform(0, np.pi)
+    view = [np.sin(th), 0.0, np.cos(th)]
+    nu_r = m.nu[min(1, m.nlines - 1)]
+    ctx.render_image(view, 256, 256, nu_r * (1 - 5e-5), nu_r * (1 + 5e-5), 63)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nrep = 3
+    for _ in range(nrep):
+        ctx.render_image(view, 256, 256, nu_r * (1 - 5e-5), nu_r * (1 + 5e-5), 63)
+    torch.cuda.synchronize()
+    render_ms = (time.perf_counter() - t0) / nrep * 1e3
     roof = alu_roofline(ctx, m, fs_ms, args.precision)
     if args.precision == "fp32":
         roof["traffic"] = committed_traffic(args.workload)
@@ -285,6 +299,10 @@ def main():
                    "lines": m.nlines, "bins": m.nbins, "levels": m.nlev,
                    "formal_solve": args.precision, "stateq": "f64", "ng": "classical order 4"},
         "formal_solve_ms": fs_ms, "trace_ms": trace_ms,
+        "render": {"pixels": 256 * 256, "bins": 63, "ms": render_ms,
+                   "pixel_bins_per_s": 256 * 256 * 63 / (render_ms * 1e-3),
+                   "includes": "line coefficients, pixel entry search, walks, integration, "
+                               "copy of the float image to the host"},
         "ray_pair_solves_per_s": value / 2.0,
         "roofline": roof,
     }

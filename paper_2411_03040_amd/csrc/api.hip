@@ -126,6 +126,8 @@ struct mgx_ctx {
     std::vector<DMem *> ng_y, ng_r;
     std::vector<DMem *> ng_pool;
     DMem ng_G, ng_coef, ng_status, ng_partial, ng_pred, ng_prev, ng_bits;
+    // images
+    DMem rg_proj, rg_pix, rg_off, rg_walk, rg_img;
     // diagnostics
     mgx_counters host_cnt{};
     hipEvent_t ev_fs0 = nullptr, ev_fs1 = nullptr;
@@ -1039,11 +1041,128 @@ extern "C" mgx_status mgx_reset_timers(mgx_ctx *ctx)
     API_END(ctx)
 }
 
+// Image basis: d = dir / |dir|, e1 = unit(a x d) with a = z (x when
+// |d_z| > 0.9), e2 = d x e1; plain double arithmetic, no contraction.
+static void render_basis(const double dir[3], double d[3], double e1[3], double e2[3])
+{
+#pragma clang fp contract(off)
+    const double n = sqrt(dir[0] * dir[0] + dir[1] * dir[1] + dir[2] * dir[2]);
+    d[0] = dir[0] / n;
+    d[1] = dir[1] / n;
+    d[2] = dir[2] / n;
+    double a[3] = {0.0, 0.0, 1.0};
+    if (fabs(d[2]) > 0.9) {
+        a[0] = 1.0;
+        a[2] = 0.0;
+    }
+    const double c[3] = {a[1] * d[2] - a[2] * d[1], a[2] * d[0] - a[0] * d[2],
+                         a[0] * d[1] - a[1] * d[0]};
+    const double cn = sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+    e1[0] = c[0] / cn;
+    e1[1] = c[1] / cn;
+    e1[2] = c[2] / cn;
+    e2[0] = d[1] * e1[2] - d[2] * e1[1];
+    e2[1] = d[2] * e1[0] - d[0] * e1[2];
+    e2[2] = d[0] * e1[1] - d[1] * e1[0];
+}
+
 extern "C" mgx_status mgx_render_image(mgx_ctx *ctx, const double dir[3], int npx, int npy,
                                        double f_min, double f_max, int nfreq, float *img)
 {
     API_BEGIN(ctx)
-    (void)dir; (void)npx; (void)npy; (void)f_min; (void)f_max; (void)nfreq; (void)img;
-    throw Err{MGX_EINVAL, "mgx_render_image: not available in this build"};
+    REQUIRE(ctx->loaded && ctx->have_pops, MGX_ESTATE, "mgx_render_image needs a model and populations");
+    REQUIRE(ctx->dim == 3, MGX_EINVAL, "mgx_render_image supports point clouds (dim 3)");
+    REQUIRE(dir && img, MGX_EINVAL, "dir / img is NULL");
+    REQUIRE(std::isfinite(dir[0]) && std::isfinite(dir[1]) && std::isfinite(dir[2]) &&
+                (dir[0] != 0.0 || dir[1] != 0.0 || dir[2] != 0.0),
+            MGX_EINVAL, "dir must be finite and non-zero");
+    REQUIRE(npx >= 1 && npy >= 1 && (int64_t)npx * npy <= (1 << 26), MGX_EINVAL,
+            "pixel counts out of range");
+    REQUIRE(nfreq >= 1 && nfreq <= 1024, MGX_EINVAL, "nfreq must be 1..1024");
+    REQUIRE(f_min > 0 && f_max >= f_min && std::isfinite(f_max), MGX_EINVAL,
+            "need 0 < f_min <= f_max");
+    run_line_coeffs(ctx);
+    const int N = ctx->N;
+    const int64_t npix = (int64_t)npx * npy;
+    RenderGeom g{};
+    g.N = N;
+    g.npx = npx;
+    g.npy = npy;
+    render_basis(dir, g.d, g.e1, g.e2);
+    g.h = ctx->L_unit;
+    const double *pos = ctx->pos.as<double>(), *vel = ctx->vel.as<double>();
+    g.x = pos;
+    g.y = pos + N;
+    g.z = pos + 2 * (size_t)N;
+    g.vx = vel;
+    g.vy = vel + N;
+    g.vz = vel + 2 * (size_t)N;
+    g.nbs_off = ctx->nbs_off.as<int32_t>();
+    g.nbs = ctx->nbs.as<int32_t>();
+    g.bdy = ctx->bdy.as<uint8_t>();
+    ctx->rg_proj.ensure(sizeof(double) * 4 * (size_t)N + sizeof(double) * 4);
+    g.u = ctx->rg_proj.as<double>();
+    g.v = g.u + N;
+    g.Z = g.v + N;
+    g.w = g.Z + N;
+    g.ext = g.w + N;
+    ctx->rg_pix.ensure((sizeof(unsigned long long) + sizeof(int32_t)) * npix + 16);
+    g.key = ctx->rg_pix.as<unsigned long long>();
+    g.entry = (int32_t *)(g.key + npix);
+    ctx->rg_off.ensure(sizeof(int64_t) * 2 * (npix + 1));
+    g.counts = ctx->rg_off.as<int64_t>();
+    int64_t *off = g.counts + (npix + 1);
+    HIPCHK(hipMemsetAsync(g.counts, 0, sizeof(int64_t) * (npix + 1), ctx->stream));
+    HIPCHK(launch_render_geometry(g, ctx->stream));
+    HIPCHK(launch_render_walk(g, false, ctx->stream));
+    HIPCHK(mgx_internal_scan(g.counts, off, npix + 1, &ctx->scan_tmp, &ctx->scan_tmp_bytes,
+                             ctx->stream));
+    int64_t total = 0;
+    HIPCHK(hipMemcpyAsync(&total, off + npix, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
+    ctx->sync();
+    ctx->rg_walk.ensure(sizeof(int32_t) * (size_t)(total > 0 ? total : 1));
+    g.off = off;
+    g.walk = ctx->rg_walk.as<int32_t>();
+    HIPCHK(launch_render_walk(g, true, ctx->stream));
+    ctx->rg_img.ensure(sizeof(float) * (size_t)npix * nfreq);
+    const double I_img = 2.0 * kH * pow(0.5 * (f_min + f_max), 3) / (kC * kC);
+    auto fill_args = [&](auto &ra) {
+        ra.npx = npx;
+        ra.npy = npy;
+        ra.nfreq = nfreq;
+        ra.nlines = ctx->nlines;
+        ra.off = off;
+        ra.walk = g.walk;
+        ra.Z = g.Z;
+        ra.w = g.w;
+        ra.b = ctx->bd.as<double>();
+        ra.ib = ctx->ibd.as<double>();
+        ra.nu_line = ctx->nu.as<double>();
+        ra.Iref = ctx->Iref.as<double>();
+        ra.inv_L = 1.0 / ctx->L_unit;
+        ra.f_min = f_min;
+        ra.f_max = f_max;
+        ra.Tcmb = ctx->Tcmb;
+        ra.I_img = I_img;
+        ra.thr = ctx->opt.branch_threshold;
+        ra.b2 = ctx->b2.as<double>();
+        ra.img = ctx->rg_img.as<float>();
+    };
+    if (ctx->fp32()) {
+        RenderArgs<float> ra{};
+        fill_args(ra);
+        ra.chi = (const float *)ctx->chiT.p;
+        ra.S = (const float *)ctx->ST.p;
+        HIPCHK(launch_render_integrate<float>(ra, ctx->stream));
+    } else {
+        RenderArgs<double> ra{};
+        fill_args(ra);
+        ra.chi = (const double *)ctx->chiT.p;
+        ra.S = (const double *)ctx->ST.p;
+        HIPCHK(launch_render_integrate<double>(ra, ctx->stream));
+    }
+    HIPCHK(hipMemcpyAsync(img, ctx->rg_img.p, sizeof(float) * (size_t)npix * nfreq,
+                          hipMemcpyDefault, ctx->stream));
+    ctx->sync();
     API_END(ctx)
 }

@@ -132,6 +132,43 @@ hipError_t launch_line_table(int nlines, int nlev, const double *A, const double
                              hipStream_t s);
 hipError_t launch_copy(int64_t n, const double *src, double *dst, hipStream_t s);
 
+// Synthetic images.  Geometry in FP64 without contraction (bit-exact pixel
+// walks); integration in the solve precision.
+struct RenderGeom {
+    int N, npx, npy;
+    double d[3], e1[3], e2[3];
+    double h;                  // length scale (bbox diagonal / N^(1/3))
+    const double *x, *y, *z, *vx, *vy, *vz;
+    const int32_t *nbs_off, *nbs;
+    const uint8_t *bdy;
+    double *u, *v, *Z, *w;     // [N] projections and d.v
+    double *ext;               // [4] umin, umax, vmin, vmax (after reduce)
+    unsigned long long *key;   // [npx npy] entry search scratch
+    int32_t *entry;            // [npx npy]
+    int64_t *counts;           // [npx npy + 1]
+    const int64_t *off;        // [npx npy + 1]
+    int32_t *walk;             // records
+};
+hipError_t launch_render_geometry(RenderGeom &g, hipStream_t s);  // project + extent + entry
+hipError_t launch_render_walk(const RenderGeom &g, bool fill, hipStream_t s);
+
+template <typename T>
+struct RenderArgs {
+    int npx, npy, nfreq, nlines;
+    const int64_t *off;
+    const int32_t *walk;
+    const double *Z, *w;       // [N] (double; scaled inside)
+    const T *chi, *S;          // [N][nlines] scaled opacity factor and S / Iref
+    const double *b, *ib;      // [N] b and 1/b
+    const double *nu_line, *Iref;  // [nlines]
+    double inv_L, f_min, f_max, Tcmb, I_img;
+    double thr;                // branch threshold (widths)
+    const double *b2;          // [N] squared Doppler speed (branch rule in FP64)
+    float *img;                // [npy][npx][nfreq]
+};
+template <typename T>
+hipError_t launch_render_integrate(const RenderArgs<T> &a, hipStream_t s);
+
 // Ng: incremental Gram matrix, solve, combine.  Pointer tables are passed by
 // value (kernel arguments), entry k is residual r_k or iterate y_{k+1}.
 struct PtrTable {

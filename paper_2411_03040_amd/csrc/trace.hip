@@ -275,6 +275,205 @@ hipError_t launch_pack_trace(int64_t n, const int32_t *idx, const uint8_t *semi,
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Image geometry: projections on the image basis, the projected extent, the
+// entry point of every pixel ray and the pixel walks.  The same products and
+// sums in the same order as the CPU definition.
+// ---------------------------------------------------------------------------
+__global__ void k_render_project(RenderGeom g)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= g.N) return;
+    const double xj = g.x[j], yj = g.y[j], zj = g.z[j];
+    g.u[j] = (xj * g.e1[0] + yj * g.e1[1]) + zj * g.e1[2];
+    g.v[j] = (xj * g.e2[0] + yj * g.e2[1]) + zj * g.e2[2];
+    g.Z[j] = (xj * g.d[0] + yj * g.d[1]) + zj * g.d[2];
+    g.w[j] = (g.vx[j] * g.d[0] + g.vy[j] * g.d[1]) + g.vz[j] * g.d[2];
+}
+
+// min / max of u and v (exact operations: any order gives the same result)
+__global__ void k_render_extent(int N, const double *u, const double *v, double *ext)
+{
+    __shared__ double r[4][256];
+    double a = INFINITY, b = -INFINITY, c = INFINITY, d = -INFINITY;
+    for (int j = threadIdx.x; j < N; j += 256) {
+        a = fmin(a, u[j]);
+        b = fmax(b, u[j]);
+        c = fmin(c, v[j]);
+        d = fmax(d, v[j]);
+    }
+    r[0][threadIdx.x] = a;
+    r[1][threadIdx.x] = b;
+    r[2][threadIdx.x] = c;
+    r[3][threadIdx.x] = d;
+    __syncthreads();
+    for (int m = 128; m > 0; m >>= 1) {
+        if ((int)threadIdx.x < m) {
+            r[0][threadIdx.x] = fmin(r[0][threadIdx.x], r[0][threadIdx.x + m]);
+            r[1][threadIdx.x] = fmax(r[1][threadIdx.x], r[1][threadIdx.x + m]);
+            r[2][threadIdx.x] = fmin(r[2][threadIdx.x], r[2][threadIdx.x + m]);
+            r[3][threadIdx.x] = fmax(r[3][threadIdx.x], r[3][threadIdx.x + m]);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x < 4) ext[threadIdx.x] = r[threadIdx.x][0];
+}
+
+struct PixGrid {
+    double umin, vmin, du, dv, R2;
+};
+
+__device__ __forceinline__ PixGrid pix_grid(const RenderGeom &g)
+{
+    PixGrid p;
+    p.umin = g.ext[0];
+    p.vmin = g.ext[2];
+    p.du = (g.ext[1] - g.ext[0]) / g.npx;
+    p.dv = (g.ext[3] - g.ext[2]) / g.npy;
+    double R = p.du > p.dv ? p.du : p.dv;
+    if (g.h > R) R = g.h;
+    p.R2 = R * R;
+    return p;
+}
+
+// order-preserving map of a double to unsigned 64 bits
+__device__ __forceinline__ unsigned long long ordered(double x)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    return (b & 0x8000000000000000ull) ? ~b : (b | 0x8000000000000000ull);
+}
+
+// Entry search, scattered from the boundary points: every boundary point
+// offers its Z to the pixels whose line passes within R of it (exact test
+// as in the CPU definition); pass 0 keeps the smallest Z per pixel, pass 1
+// the smallest point index among those with exactly that Z.
+__global__ void k_render_entry(RenderGeom g, int pass)
+{
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= g.N || !g.bdy[j]) return;
+    const PixGrid P = pix_grid(g);
+    const double uj = g.u[j], vj = g.v[j], Zj = g.Z[j];
+    const double R = sqrt(P.R2);
+    int ix0 = (int)floor((uj - R - P.umin) / P.du - 0.5) - 1;
+    int ix1 = (int)floor((uj + R - P.umin) / P.du - 0.5) + 1;
+    int iy0 = (int)floor((vj - R - P.vmin) / P.dv - 0.5) - 1;
+    int iy1 = (int)floor((vj + R - P.vmin) / P.dv - 0.5) + 1;
+    ix0 = max(ix0, 0);
+    iy0 = max(iy0, 0);
+    ix1 = min(ix1, g.npx - 1);
+    iy1 = min(iy1, g.npy - 1);
+    const unsigned long long kz = ordered(Zj);
+    for (int iy = iy0; iy <= iy1; iy++) {
+        const double vc = P.vmin + (iy + 0.5) * P.dv;
+        for (int ix = ix0; ix <= ix1; ix++) {
+            const double uc = P.umin + (ix + 0.5) * P.du;
+            const double a = uj - uc, b = vj - vc;
+            const double r2 = a * a + b * b;
+            if (!(r2 <= P.R2)) continue;
+            const int pix = iy * g.npx + ix;
+            if (pass == 0)
+                atomicMin(&g.key[pix], kz);
+            else if (g.key[pix] == kz)
+                atomicMin(&g.entry[pix], j);
+        }
+    }
+}
+
+__global__ void k_render_entry_init(int npix, unsigned long long *key, int32_t *entry)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= npix) return;
+    key[i] = ~0ull;
+    entry[i] = 0x7fffffff;
+}
+
+hipError_t launch_render_geometry(RenderGeom &g, hipStream_t s)
+{
+    const int npix = g.npx * g.npy;
+    k_render_project<<<(g.N + 255) / 256, 256, 0, s>>>(g);
+    k_render_extent<<<1, 256, 0, s>>>(g.N, g.u, g.v, g.ext);
+    k_render_entry_init<<<(npix + 255) / 256, 256, 0, s>>>(npix, g.key, g.entry);
+    k_render_entry<<<(g.N + 255) / 256, 256, 0, s>>>(g, 0);
+    k_render_entry<<<(g.N + 255) / 256, 256, 0, s>>>(g, 1);
+    return hipGetLastError();
+}
+
+// Pixel walk: 16 lanes per pixel as in the ray trace, distances measured
+// from the pixel line; the entry point is the first record.
+template <bool FILL>
+__global__ __launch_bounds__(256) void k_render_walk(RenderGeom g)
+{
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t pix = gid >> 4;
+    const int l16 = threadIdx.x & 15;
+    const int npix = g.npx * g.npy;
+    if (pix >= npix) return;
+    const int e = g.entry[pix];
+    int64_t n = 0;
+    if (e != 0x7fffffff) {
+        const PixGrid P = pix_grid(g);
+        const int ix = (int)(pix % g.npx), iy = (int)(pix / g.npx);
+        const double uc = P.umin + (ix + 0.5) * P.du, vc = P.vmin + (iy + 0.5) * P.dv;
+        const int64_t base = FILL ? g.off[pix] : 0;
+        if (FILL && l16 == 0) g.walk[base] = e;
+        n = 1;
+        int c = e;
+        double Zc = g.Z[e];
+        for (;;) {
+            const int q0 = g.nbs_off[c], q1 = g.nbs_off[c + 1];
+            double bd = INFINITY, bZ = 0.0;
+            int bq = 0x7fffffff, bj = -1;
+            for (int qb = q0; qb < q1; qb += 16) {
+                const int q = qb + l16;
+                if (q < q1) {
+                    const int j = g.nbs[q];
+                    const double Zj = g.Z[j];
+                    if (Zj > Zc) {
+                        const double a = g.u[j] - uc, b = g.v[j] - vc;
+                        const double r2 = a * a + b * b;
+                        if (r2 < bd) {
+                            bd = r2;
+                            bq = q;
+                            bj = j;
+                            bZ = Zj;
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int m = 8; m >= 1; m >>= 1) {
+                const double od = __shfl_xor(bd, m, 16);
+                const int oq = __shfl_xor(bq, m, 16);
+                const int oj = __shfl_xor(bj, m, 16);
+                const double oZ = __shfl_xor(bZ, m, 16);
+                if (od < bd || (od == bd && oq < bq)) {
+                    bd = od;
+                    bq = oq;
+                    bj = oj;
+                    bZ = oZ;
+                }
+            }
+            if (bj < 0) break;
+            if (FILL && l16 == 0) g.walk[base + n] = bj;
+            n++;
+            c = bj;
+            Zc = bZ;
+        }
+    }
+    if (!FILL && l16 == 0) g.counts[pix] = n;
+}
+
+hipError_t launch_render_walk(const RenderGeom &g, bool fill, hipStream_t s)
+{
+    const int64_t npix = (int64_t)g.npx * g.npy;
+    const int64_t blocks = (npix * 16 + 255) / 256;
+    if (fill)
+        k_render_walk<true><<<blocks, 256, 0, s>>>(g);
+    else
+        k_render_walk<false><<<blocks, 256, 0, s>>>(g);
+    return hipGetLastError();
+}
+
 }  // namespace mgx
 
 // Exclusive scan of walk lengths into record offsets (hipCUB device scan).

@@ -70,6 +70,12 @@ def lib():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built (run __graft_entry__.build())")
+    # torch ships its own HIP runtime; loading it first lets libmgx.so bind to
+    # that same runtime (same soname) so one process never holds two.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(LIB_PATH)
     P, I, D, I64 = C.c_void_p, C.c_int, C.c_double, C.c_int64
     sig = {

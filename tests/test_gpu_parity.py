@@ -399,3 +399,91 @@ def test_error_paths(mgx):
         c.update_populations()
     assert e.value.status == mgx.MGX_ESINGULAR
     c.close()
+
+
+# ---------------------------------------------------------------------------
+# Synthetic images
+# ---------------------------------------------------------------------------
+
+def render_compare(mgx, model, prec, direction, npx, npy, f_min, f_max, nfreq, pixels, tol,
+                   pops=None):
+    orc = oracle.Oracle(model)
+    if pops is None:
+        pops = orc.lte()
+    ctx = mgx.Context(precision=prec)
+    ctx.load_model(model)
+    ctx.set_populations(pops)
+    img = ctx.render_image(direction, npx, npy, f_min, f_max, nfreq)
+    assert img.shape == (npy, npx, nfreq) and np.all(np.isfinite(img))
+    Io, walks = orc.render_pixels(pops, direction, npx, npy, f_min, f_max, nfreq, pixels)
+    got = np.array([img[iy, ix] for ix, iy in pixels])
+    e = rel(got, Io)
+    say(f"  render {model.name} prec={prec} rel {e:.3e}  walks {[len(w) for w in walks[:6]]}")
+    assert e < tol
+    return img, walks
+
+
+# The image is float32 (the API's output type), so the FP64 path is checked
+# to float resolution; the FP32 path to the bulk-precision bar.
+@pytest.mark.parametrize("prec,tol", [(0, 2e-7), (1, 2e-5)])
+def test_render_moving_cloud_all_pixels(mgx, prec, tol):
+    m = synth.tiny_cloud(npoints=500, seed=50, k=12, nside=1, nlev=3, nbins=5, vmax=4e3,
+                         tau_scale=20.0)
+    nu0 = m.nu[0]
+    pix = [(ix, iy) for ix in range(12) for iy in range(10)]
+    img, walks = render_compare(mgx, m, prec, [0.2, -0.4, 0.9], 12, 10, nu0 * (1 - 2e-5),
+                                nu0 * (1 + 2e-5), 21, pix, tol)
+    assert max(len(w) for w in walks) > 5
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 2e-7), (1, 2e-5)])
+def test_render_outflow_full_sampled(mgx, outflow, prec, tol):
+    m = outflow
+    nu0 = m.nu[1]
+    rng = np.random.default_rng(51)
+    pix = [(int(a), int(b)) for a, b in zip(rng.integers(0, 64, 24), rng.integers(0, 64, 24))]
+    pix += [(0, 0), (63, 63)]           # corners: off the projected shell
+    img, walks = render_compare(mgx, m, prec, [0.0, 0.6, 0.8], 64, 64, nu0 * (1 - 8e-5),
+                                nu0 * (1 + 8e-5), 63, pix, tol)
+    assert len(walks[-1]) == 0 and len(walks[-2]) == 0
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 2e-7), (1, 2e-5)])
+def test_render_clumpy_full_sampled(mgx, clumpy, prec, tol):
+    """Large velocity gradients: offsets of tens of widths, profiles underflow."""
+    m = clumpy
+    nu0 = m.nu[2]
+    rng = np.random.default_rng(53)
+    pix = [(int(a), int(b)) for a, b in zip(rng.integers(0, 48, 12), rng.integers(0, 48, 12))]
+    render_compare(mgx, m, prec, [0.5, 0.5, 0.7071], 48, 48, nu0 * (1 - 6e-5),
+                   nu0 * (1 + 6e-5), 31, pix, tol)
+
+
+def test_render_steep_gradient_column(mgx):
+    n = 9
+    m = synth.cubic_lattice(n=n, nbins=5)
+    m.nspec[:] = 3e5
+    m.vel[0] = 40e3 / ((n - 1) * 1e12) * m.pos[0]
+    nu0 = m.nu[0]
+    pix = [(ix, iy) for ix in range(n) for iy in range(n)]
+    for prec, tol in ((0, 2e-7), (1, 2e-5)):
+        render_compare(mgx, m, prec, [1.0, 0.0, 0.0], n, n, nu0 * (1 - 1.2e-4), nu0, 13, pix, tol)
+
+
+def test_render_errors(mgx):
+    m = synth.spherical_shells("a")
+    c = mgx.Context()
+    c.load_model(m)
+    c.set_lte_populations()
+    with pytest.raises(mgx.MgxError) as e:
+        c.render_image([0, 0, 1], 8, 8, 1e11, 1e11, 3)
+    assert e.value.status == mgx.MGX_EINVAL
+    m3 = synth.tiny_cloud(npoints=30, seed=52)
+    c.load_model(m3)
+    c.set_lte_populations()
+    with pytest.raises(mgx.MgxError) as e:
+        c.render_image([0, 0, 0], 8, 8, 1e11, 1e11, 3)
+    assert e.value.status == mgx.MGX_EINVAL
+    with pytest.raises(mgx.MgxError) as e:
+        c.render_image([0, 0, 1], 8, 8, 1e11, 1e11, 2000)
+    assert e.value.status == mgx.MGX_EINVAL
