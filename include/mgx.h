@@ -251,6 +251,66 @@ mgx_status mgx_get_counters(mgx_ctx *ctx, mgx_counters *out);
 mgx_status mgx_render_image(mgx_ctx *ctx, const double dir[3], int npx, int npy,
                             double f_min, double f_max, int nfreq, float *img);
 
+/* ------------------------------------------------------------------------
+ * Batches: many independent models (grids of medium-sized models, the
+ * use the paper's limitations section names) solved together on one GPU.
+ * Each model keeps its own state; every Lambda-iteration of the batch is one
+ * replay of a captured HIP graph: line coefficients of every model, one
+ * persistent formal-solution launch per lane class (models grouped by
+ * lines x bins; work items (model, origin, line chunk) ordered longest first
+ * and pulled from an atomic queue), statistical equilibrium of every model.
+ * Converged models are masked on the device; classical Ng runs per model
+ * between replays.  Per-model results equal those of a lone context with the
+ * same options, bit for bit.
+ * ---------------------------------------------------------------------- */
+typedef struct mgx_batch mgx_batch;
+
+typedef struct {
+    int models;               /* models in the batch                            */
+    int active;               /* models not yet converged                       */
+    int iterations;           /* graph replays in the last mgx_batch_iterate    */
+    int lane_classes;         /* persistent launches per iteration              */
+    int64_t work_items;       /* (model, origin, line chunk) items              */
+    int class_threads[5];     /* workgroup size of each lane class              */
+    int class_chunk[5];       /* tuned LDS records per half, per class          */
+    int class_grid[5];        /* tuned persistent grid size, per class          */
+    double tune_seconds;      /* time spent tuning the schedule                  */
+    double iterate_seconds;   /* wall time of the last mgx_batch_iterate        */
+} mgx_batch_stats;
+
+/* Create an empty batch on `device` with options for all models.  `stream`
+   must be a created (capturable) stream; NULL makes the batch create and own
+   a non-blocking one.  Sub-models share it. */
+mgx_status mgx_batch_create(mgx_batch **out, int device, void *stream, const mgx_options *opt);
+void mgx_batch_destroy(mgx_batch *b);
+const char *mgx_batch_last_error(const mgx_batch *b);
+
+/* Copy a model into the batch (same validation as mgx_load_model); its
+   index in the batch goes to *id_out.  Not after mgx_batch_prepare. */
+mgx_status mgx_batch_add_model(mgx_batch *b, const mgx_model *m, int *id_out);
+
+/* Trace every model and build the work tables.  Errors: MGX_ESTATE (empty
+   batch), MGX_ENOMEM. */
+mgx_status mgx_batch_prepare(mgx_batch *b);
+
+/* LTE populations for every model / populations of one model (host or
+   device pointers, [N][nlev]). */
+mgx_status mgx_batch_set_lte_populations(mgx_batch *b);
+mgx_status mgx_batch_set_populations(mgx_batch *b, int id, const double *pops);
+mgx_status mgx_batch_get_populations(mgx_batch *b, int id, double *pops);
+
+/* Lambda-iterate every model until its max relative change is <= tol (each
+   model stops on its own), at most max_iter replays, classical Ng of order
+   ng_order per model (0: none).  The first call tunes the schedule and
+   captures the iteration graph.  iters[M], changes[M] (host, may be NULL)
+   receive per-model iteration counts and last changes; *converged_out the
+   number of converged models.  Errors: MGX_ENOCONV if any model did not
+   converge, MGX_ESINGULAR / MGX_ENONFINITE as for mgx_iterate. */
+mgx_status mgx_batch_iterate(mgx_batch *b, double tol, int max_iter, int ng_order, int *iters,
+                             double *changes, int *converged_out);
+
+mgx_status mgx_batch_get_stats(mgx_batch *b, mgx_batch_stats *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -678,8 +678,10 @@ static void run_line_coeffs(mgx_ctx *ctx)
     HIPCHK(launch_line_coeffs(la, ctx->stream));
 }
 
+// Launch shape of one model's formal solution: lines per chunk (balanced)
+// and threads per workgroup (a multiple of 64 covering nlc * nbins).
 template <typename T>
-static void run_formal_solve_t(mgx_ctx *ctx)
+static FSArgs<T> fs_args(mgx_ctx *ctx)
 {
     FSArgs<T> a{};
     a.N = ctx->N;
@@ -717,6 +719,13 @@ static void run_formal_solve_t(mgx_ctx *ctx)
     a.tau_floor = ctx->opt.tau_floor;
     a.J = ctx->J.as<double>();
     a.L = ctx->L.as<double>();
+    return a;
+}
+
+template <typename T>
+static void run_formal_solve_t(mgx_ctx *ctx)
+{
+    FSArgs<T> a = fs_args<T>(ctx);
     if (ctx->fs_pending) ctx->sync();  // previous launch's events must be read first
     HIPCHK(hipEventRecord(ctx->ev_fs0, ctx->stream));
     HIPCHK(launch_formal_solve<T>(a, ctx->stream));
@@ -808,7 +817,7 @@ static void ng_restart(mgx_ctx *ctx)
     ctx->ng_have_prev = false;
 }
 
-static mgx_status update_populations(mgx_ctx *ctx, double *change_out)
+static StateqArgs stateq_args(mgx_ctx *ctx)
 {
     StateqArgs s{};
     s.N = ctx->N;
@@ -836,6 +845,14 @@ static mgx_status update_populations(mgx_ctx *ctx, double *change_out)
     s.pops_new = ctx->pops_new.as<double>();
     s.pop_floor = ctx->opt.pop_floor;
     s.cnt = ctx->counters.as<Counters>();
+    s.active = nullptr;
+    s.model = 0;
+    return s;
+}
+
+static mgx_status update_populations(mgx_ctx *ctx, double *change_out)
+{
+    StateqArgs s = stateq_args(ctx);
     HIPCHK(launch_reset_counters(ctx->counters.as<Counters>(), ctx->stream));
     HIPCHK(launch_stateq(s, ctx->stream));
     std::swap(ctx->pops.p, ctx->pops_new.p);
@@ -1165,4 +1182,442 @@ extern "C" mgx_status mgx_render_image(mgx_ctx *ctx, const double dir[3], int np
                           hipMemcpyDefault, ctx->stream));
     ctx->sync();
     API_END(ctx)
+}
+
+// ---------------------------------------------------------------------------
+// Batches
+// ---------------------------------------------------------------------------
+
+struct mgx_batch {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    mgx_options opt{};
+    std::string err;
+    std::vector<mgx_ctx *> m;
+    bool prepared = false, tuned = false;
+    // device tables
+    DMem descs, active, changes, cnt_ptrs, queue;
+    DMem items[5];
+    int nclass = 0;
+    int class_threads[5] = {0, 0, 0, 0, 0};
+    int class_nitems[5] = {0, 0, 0, 0, 0};
+    int class_nlc_max[5] = {0, 0, 0, 0, 0};
+    int class_ch[5] = {64, 64, 64, 64, 64};
+    int class_grid[5] = {0, 0, 0, 0, 0};
+    int64_t work_items = 0;
+    std::vector<int> host_active;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    mgx_batch_stats st{};
+
+    ~mgx_batch()
+    {
+        if (stream) (void)hipStreamSynchronize(stream);
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        for (mgx_ctx *c : m) delete c;
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+    }
+    bool fp32() const { return opt.precision == MGX_FP32; }
+    void sync() { HIPCHK(hipStreamSynchronize(stream)); }
+};
+
+#define BATCH_BEGIN(b)                                                                    \
+    if (!(b)) return MGX_EINVAL;                                                          \
+    try {                                                                                 \
+        DeviceGuard dg_((b)->device);                                                     \
+        (b)->err.clear();
+
+#define BATCH_END(b)                                                                      \
+    }                                                                                     \
+    catch (const Err &e)                                                                  \
+    {                                                                                     \
+        (b)->err = e.msg;                                                                 \
+        return e.st;                                                                      \
+    }                                                                                     \
+    catch (const std::bad_alloc &)                                                        \
+    {                                                                                     \
+        (b)->err = "host allocation failed";                                              \
+        return MGX_ENOMEM;                                                                \
+    }                                                                                     \
+    catch (...)                                                                           \
+    {                                                                                     \
+        (b)->err = "unexpected internal error";                                           \
+        return MGX_EHIP;                                                                  \
+    }                                                                                     \
+    return MGX_OK;
+
+static void check_sub(mgx_batch *b, mgx_ctx *c, mgx_status st)
+{
+    if (st != MGX_OK) throw Err{st, c->err};
+    (void)b;
+}
+
+extern "C" mgx_status mgx_batch_create(mgx_batch **out, int device, void *stream,
+                                       const mgx_options *opt)
+{
+    g_create_error.clear();
+    if (!out) return MGX_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+        g_create_error = "no such HIP device";
+        return MGX_EINVAL;
+    }
+    mgx_options o;
+    mgx_default_options(&o);
+    if (opt) o = *opt;
+    mgx_batch *b = new (std::nothrow) mgx_batch();
+    if (!b) return MGX_ENOMEM;
+    b->device = device;
+    b->opt = o;
+    try {
+        DeviceGuard dg(device);
+        if (stream) {
+            b->stream = (hipStream_t)stream;
+        } else {
+            HIPCHK(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+            b->own_stream = true;
+        }
+        HIPCHK(hipEventCreate(&b->ev0));
+        HIPCHK(hipEventCreate(&b->ev1));
+    } catch (const Err &e) {
+        g_create_error = e.msg;
+        delete b;
+        return e.st;
+    }
+    *out = b;
+    return MGX_OK;
+}
+
+extern "C" void mgx_batch_destroy(mgx_batch *b)
+{
+    if (!b) return;
+    int prev = -1;
+    (void)hipGetDevice(&prev);
+    (void)hipSetDevice(b->device);
+    delete b;
+    if (prev >= 0) (void)hipSetDevice(prev);
+}
+
+extern "C" const char *mgx_batch_last_error(const mgx_batch *b)
+{
+    if (!b) return g_create_error.c_str();
+    return b->err.c_str();
+}
+
+extern "C" mgx_status mgx_batch_add_model(mgx_batch *b, const mgx_model *model, int *id_out)
+{
+    BATCH_BEGIN(b)
+    REQUIRE(!b->prepared, MGX_ESTATE, "mgx_batch_add_model after mgx_batch_prepare");
+    mgx_ctx *c = nullptr;
+    const mgx_status st = mgx_create(&c, b->device, b->stream, &b->opt);
+    if (st != MGX_OK) throw Err{st, g_create_error};
+    const mgx_status ls = mgx_load_model(c, model);
+    if (ls != MGX_OK) {
+        Err e{ls, c->err};
+        delete c;
+        throw e;
+    }
+    b->m.push_back(c);
+    if (id_out) *id_out = (int)b->m.size() - 1;
+    BATCH_END(b)
+}
+
+static const int kClassCaps[5] = {64, 128, 256, 512, 1024};
+
+template <typename T>
+static void batch_build_tables(mgx_batch *b)
+{
+    const int M = (int)b->m.size();
+    std::vector<FSArgs<T>> d(M);
+    std::vector<std::vector<std::pair<int64_t, int4>>> cls(5);
+    DMem cost;
+    for (int k = 0; k < 5; k++) {
+        b->class_threads[k] = kClassCaps[k];
+        b->class_nlc_max[k] = 0;
+    }
+    for (int i = 0; i < M; i++) {
+        mgx_ctx *c = b->m[i];
+        d[i] = fs_args<T>(c);
+        int k = 0;
+        while (kClassCaps[k] < d[i].nthreads) k++;
+        b->class_nlc_max[k] = std::max(b->class_nlc_max[k], d[i].nlc);
+        cost.ensure(sizeof(int64_t) * c->N);
+        HIPCHK(launch_origin_cost(c->N, c->R, c->offsets.as<int64_t>(), cost.as<int64_t>(),
+                                  b->stream));
+        std::vector<int64_t> hc(c->N);
+        HIPCHK(hipMemcpyAsync(hc.data(), cost.p, sizeof(int64_t) * c->N, hipMemcpyDeviceToHost,
+                              b->stream));
+        b->sync();
+        const int nchunks = (c->nlines + d[i].nlc - 1) / d[i].nlc;
+        const int64_t lanes = (int64_t)d[i].nlc * c->nbins;
+        for (int o = 0; o < c->N; o++)
+            for (int ch = 0; ch < nchunks; ch++)
+                cls[k].push_back({(hc[o] + c->npairs) * lanes, make_int4(i, o, ch, 0)});
+    }
+    upload(b->m[0], b->descs, d.data(), d.size());
+    b->work_items = 0;
+    b->nclass = 0;
+    for (int k = 0; k < 5; k++) {
+        auto &v = cls[k];
+        std::stable_sort(v.begin(), v.end(),
+                         [](const std::pair<int64_t, int4> &x, const std::pair<int64_t, int4> &y) {
+                             return x.first > y.first;
+                         });
+        std::vector<int4> it(v.size());
+        for (size_t j = 0; j < v.size(); j++) it[j] = v[j].second;
+        b->class_nitems[k] = (int)it.size();
+        b->work_items += (int64_t)it.size();
+        if (!it.empty()) b->nclass++;
+        upload(b->m[0], b->items[k], it.data(), it.size());
+    }
+    b->sync();
+}
+
+extern "C" mgx_status mgx_batch_prepare(mgx_batch *b)
+{
+    BATCH_BEGIN(b)
+    REQUIRE(!b->m.empty(), MGX_ESTATE, "mgx_batch_prepare on an empty batch");
+    REQUIRE(!b->prepared, MGX_ESTATE, "batch already prepared");
+    const int M = (int)b->m.size();
+    for (mgx_ctx *c : b->m) check_sub(b, c, mgx_trace_rays(c, nullptr));
+    if (b->fp32())
+        batch_build_tables<float>(b);
+    else
+        batch_build_tables<double>(b);
+    std::vector<Counters *> cp(M);
+    for (int i = 0; i < M; i++) cp[i] = b->m[i]->counters.as<Counters>();
+    upload(b->m[0], b->cnt_ptrs, cp.data(), cp.size());
+    b->host_active.assign(M, 1);
+    upload(b->m[0], b->active, b->host_active.data(), (size_t)M);
+    b->changes.ensure(sizeof(double) * 2 * M);
+    b->queue.ensure(sizeof(unsigned int) * 8);
+    b->sync();
+    b->prepared = true;
+    BATCH_END(b)
+}
+
+extern "C" mgx_status mgx_batch_set_lte_populations(mgx_batch *b)
+{
+    BATCH_BEGIN(b)
+    for (mgx_ctx *c : b->m) check_sub(b, c, mgx_set_lte_populations(c));
+    BATCH_END(b)
+}
+
+extern "C" mgx_status mgx_batch_set_populations(mgx_batch *b, int id, const double *pops)
+{
+    BATCH_BEGIN(b)
+    REQUIRE(id >= 0 && id < (int)b->m.size(), MGX_EINVAL, "model id out of range");
+    check_sub(b, b->m[id], mgx_set_populations(b->m[id], pops));
+    BATCH_END(b)
+}
+
+extern "C" mgx_status mgx_batch_get_populations(mgx_batch *b, int id, double *pops)
+{
+    BATCH_BEGIN(b)
+    REQUIRE(id >= 0 && id < (int)b->m.size(), MGX_EINVAL, "model id out of range");
+    check_sub(b, b->m[id], mgx_get_populations(b->m[id], pops));
+    BATCH_END(b)
+}
+
+template <typename T>
+static void batch_launch_class(mgx_batch *b, int k, int nitems, int ch, int grid)
+{
+    const size_t lds = formal_solve_lds<T>(ch, b->class_nlc_max[k], b->class_threads[k]);
+    unsigned int *q = b->queue.as<unsigned int>() + k;
+    HIPCHK(launch_queue_reset(q, 1, b->stream));
+    HIPCHK(launch_formal_solve_batch<T>((const FSArgs<T> *)b->descs.p, b->items[k].as<int4>(),
+                                        nitems, q, b->active.as<int>(), ch,
+                                        b->class_threads[k], lds, grid, b->stream));
+}
+
+// Schedule tuning: per lane class, time the LDS chunk size and the persistent
+// grid size on the leading (heaviest) items and keep the fastest.
+template <typename T>
+static void batch_tune(mgx_batch *b)
+{
+    int ncu = 256;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, b->device) == hipSuccess && prop.multiProcessorCount > 0)
+        ncu = prop.multiProcessorCount;
+    for (int k = 0; k < 5; k++) {
+        const int n = b->class_nitems[k];
+        if (n == 0) continue;
+        const int ntune = std::min(n, std::max(2048, n / 8));
+        const int nlc = b->class_nlc_max[k], nth = b->class_threads[k];
+        // the largest chunk that fits 60 KB (at least 8, as the single-model
+        // launch does) and every smaller candidate
+        int chmax = 64;
+        while (formal_solve_lds<T>(chmax, nlc, nth) > 60 * 1024 && chmax > 8) chmax /= 2;
+        REQUIRE(formal_solve_lds<T>(chmax, nlc, nth) <= 160 * 1024, MGX_EINVAL,
+                "line chunk does not fit the LDS");
+        float best = INFINITY;
+        for (int ch : {8, 16, 32, 64}) {
+            if (ch > chmax || (ch == 8 && chmax > 8)) continue;
+            for (int bpc : {2, 4, 8}) {
+                const int grid = std::max(1, std::min(ntune, ncu * bpc));
+                HIPCHK(hipEventRecord(b->ev0, b->stream));
+                batch_launch_class<T>(b, k, ntune, ch, grid);
+                HIPCHK(hipEventRecord(b->ev1, b->stream));
+                b->sync();
+                float ms = 0.f;
+                HIPCHK(hipEventElapsedTime(&ms, b->ev0, b->ev1));
+                if (ms < best) {
+                    best = ms;
+                    b->class_ch[k] = ch;
+                    b->class_grid[k] = std::max(1, std::min(n, ncu * bpc));
+                }
+            }
+        }
+    }
+}
+
+// One Lambda-iteration of every model, captured once as a HIP graph.
+template <typename T>
+static void batch_capture(mgx_batch *b)
+{
+    const int M = (int)b->m.size();
+    HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    try {
+        for (mgx_ctx *c : b->m) run_line_coeffs(c);
+        for (int k = 0; k < 5; k++)
+            if (b->class_nitems[k])
+                batch_launch_class<T>(b, k, b->class_nitems[k], b->class_ch[k], b->class_grid[k]);
+        for (int i = 0; i < M; i++) {
+            mgx_ctx *c = b->m[i];
+            StateqArgs s = stateq_args(c);
+            s.active = b->active.as<int>();
+            s.model = i;
+            HIPCHK(launch_reset_counters(c->counters.as<Counters>(), b->stream));
+            HIPCHK(launch_stateq(s, b->stream));
+            HIPCHK(launch_copy_if_active(c->npop(), c->pops_new.as<double>(), c->pops.as<double>(),
+                                         b->active.as<int>(), i, b->stream));
+        }
+        HIPCHK(launch_gather_changes(M, b->cnt_ptrs.as<Counters *>(), b->changes.as<double>(),
+                                     b->stream));
+    } catch (...) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(b->stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+    }
+    HIPCHK(hipStreamEndCapture(b->stream, &b->graph));
+    HIPCHK(hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0));
+}
+
+extern "C" mgx_status mgx_batch_iterate(mgx_batch *b, double tol, int max_iter, int ng_order,
+                                        int *iters, double *changes, int *converged_out)
+{
+    BATCH_BEGIN(b)
+    REQUIRE(b->prepared, MGX_ESTATE, "mgx_batch_iterate before mgx_batch_prepare");
+    REQUIRE(max_iter >= 1 && tol >= 0, MGX_EINVAL, "max_iter >= 1 and tol >= 0 required");
+    REQUIRE(ng_order >= 0 && ng_order + 1 <= kNgMaxHist, MGX_EINVAL, "Ng order must be 0..31");
+    const int M = (int)b->m.size();
+    for (mgx_ctx *c : b->m) REQUIRE(c->have_pops, MGX_ESTATE, "batch model without populations");
+    auto wall = []() {
+        struct timespec ts;
+        clock_gettime(CLOCK_MONOTONIC, &ts);
+        return ts.tv_sec + 1e-9 * ts.tv_nsec;
+    };
+    if (!b->tuned) {
+        const double t0 = wall();
+        for (mgx_ctx *c : b->m) run_line_coeffs(c);
+        if (b->fp32())
+            batch_tune<float>(b);
+        else
+            batch_tune<double>(b);
+        b->st.tune_seconds = wall() - t0;
+        if (b->fp32())
+            batch_capture<float>(b);
+        else
+            batch_capture<double>(b);
+        b->tuned = true;
+    }
+    const double t0 = wall();
+    for (mgx_ctx *c : b->m) {
+        c->ng_active = false;
+        if (ng_order > 0) ng_reset(c, ng_order + 1);
+    }
+    b->host_active.assign(M, 1);
+    HIPCHK(hipMemcpyAsync(b->active.p, b->host_active.data(), sizeof(int) * M,
+                          hipMemcpyHostToDevice, b->stream));
+    std::vector<double> ch(M, INFINITY);
+    std::vector<int> its(M, 0);
+    int n_active = M, it = 0;
+    mgx_status result = MGX_OK;
+    for (it = 1; it <= max_iter && n_active > 0; it++) {
+        HIPCHK(hipGraphLaunch(b->gexec, b->stream));
+        std::vector<double> hc(2 * M);
+        HIPCHK(hipMemcpyAsync(hc.data(), b->changes.p, sizeof(double) * 2 * M,
+                              hipMemcpyDeviceToHost, b->stream));
+        b->sync();
+        bool mask_changed = false;
+        for (int i = 0; i < M; i++) {
+            if (!b->host_active[i]) continue;
+            its[i] = it;
+            ch[i] = hc[i];
+            const bool failed = hc[M + i] != 0.0 || !std::isfinite(hc[i]);
+            if (failed && result == MGX_OK) {
+                const bool sing = hc[M + i] == 1.0;
+                result = sing ? MGX_ESINGULAR : MGX_ENONFINITE;
+                b->err = std::string(sing ? "singular statistical equilibrium"
+                                          : "non-finite populations") +
+                         " in model " + std::to_string(i);
+            }
+            if (hc[i] <= tol || failed) {
+                b->host_active[i] = 0;
+                mask_changed = true;
+                n_active--;
+                continue;
+            }
+            if (ng_order > 0) {
+                mgx_ctx *c = b->m[i];
+                ng_append(c);
+                if (c->ng_nh == ng_order + 1) {
+                    double pc;
+                    ng_apply(c, ng_predict(c, &pc) != 0);
+                }
+            }
+        }
+        if (mask_changed)
+            HIPCHK(hipMemcpyAsync(b->active.p, b->host_active.data(), sizeof(int) * M,
+                                  hipMemcpyHostToDevice, b->stream));
+    }
+    b->sync();
+    for (mgx_ctx *c : b->m) c->ng_active = false;
+    b->st.iterate_seconds = wall() - t0;
+    b->st.iterations = it - 1;
+    b->st.active = n_active;
+    if (iters)
+        for (int i = 0; i < M; i++) iters[i] = its[i];
+    if (changes)
+        for (int i = 0; i < M; i++) changes[i] = ch[i];
+    if (converged_out) *converged_out = M - n_active;
+    if (result == MGX_OK && n_active > 0) {
+        result = MGX_ENOCONV;
+        b->err = std::to_string(n_active) + " model(s) did not converge within max_iter";
+    }
+    if (result != MGX_OK) return result;
+    BATCH_END(b)
+}
+
+extern "C" mgx_status mgx_batch_get_stats(mgx_batch *b, mgx_batch_stats *out)
+{
+    BATCH_BEGIN(b)
+    REQUIRE(out, MGX_EINVAL, "out is NULL");
+    b->st.models = (int)b->m.size();
+    b->st.lane_classes = b->nclass;
+    b->st.work_items = b->work_items;
+    for (int k = 0; k < 5; k++) {
+        b->st.class_threads[k] = b->class_nitems[k] ? b->class_threads[k] : 0;
+        b->st.class_chunk[k] = b->class_nitems[k] ? b->class_ch[k] : 0;
+        b->st.class_grid[k] = b->class_nitems[k] ? b->class_grid[k] : 0;
+    }
+    *out = b->st;
+    BATCH_END(b)
 }

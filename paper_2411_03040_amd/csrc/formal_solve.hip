@@ -178,13 +178,15 @@ struct HalfState {
     bool semi;
 };
 
-template <typename T, int MAXT>
-__global__ __launch_bounds__(MAXT) void k_formal_solve(FSArgs<T> a, int ch)
+// One origin x line chunk, executed by the whole workgroup (blockDim.x
+// threads, at least nlc * nbins).  Shared by the single-model launch and the
+// persistent batched launch, so both give bit-identical results.
+template <typename T>
+__device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, const int chunk,
+                                             const int ch, unsigned char *smem)
 {
-    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    const int nb = a.nbins, nl = a.nlines, nlc = a.nlc, nth = a.nthreads;
-    const int o = blockIdx.x;
-    const int l0 = blockIdx.y * nlc;
+    const int nb = a.nbins, nl = a.nlines, nlc = a.nlc, nth = blockDim.x;
+    const int l0 = chunk * nlc;
     const int nl_here = min(nlc, nl - l0);
     const int tid = threadIdx.x;
     const bool active = tid < nl_here * nb;
@@ -360,6 +362,92 @@ __global__ __launch_bounds__(MAXT) void k_formal_solve(FSArgs<T> a, int ch)
         a.J[out] = a.Iref[l0 + tid] * sj;
         a.L[out] = sl;
     }
+}
+
+template <typename T, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_formal_solve(FSArgs<T> a, int ch)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    solve_origin<T>(a, blockIdx.x, blockIdx.y, ch, smem);
+}
+
+// Persistent batched launch: a fixed grid pulls work items (model, origin,
+// line chunk), ordered longest first, from an atomic queue; items of
+// converged (inactive) models are skipped.
+template <typename T, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_formal_solve_batch(const FSArgs<T> *__restrict__ descs,
+                                                             const int4 *__restrict__ items,
+                                                             int nitems, unsigned int *queue,
+                                                             const int *__restrict__ active,
+                                                             int ch)
+{
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    __shared__ int s_item;
+    for (;;) {
+        __syncthreads();  // everyone has read the previous item
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(queue, 1u);
+        __syncthreads();
+        const int it = s_item;
+        if (it >= nitems) break;
+        const int4 w = items[it];
+        if (!active[w.x]) continue;
+        const FSArgs<T> a = descs[w.x];
+        solve_origin<T>(a, w.y, w.z, ch, smem);
+    }
+}
+
+__global__ void k_queue_reset(unsigned int *q, int n)
+{
+    if ((int)threadIdx.x < n) q[threadIdx.x] = 0u;
+}
+
+hipError_t launch_queue_reset(unsigned int *q, int n, hipStream_t s)
+{
+    k_queue_reset<<<1, 64, 0, s>>>(q, n);
+    return hipGetLastError();
+}
+
+template <typename T>
+size_t formal_solve_lds(int ch, int nlc, int nthreads)
+{
+    return lds_layout<T>(ch, nlc, nthreads).total;
+}
+template size_t formal_solve_lds<float>(int, int, int);
+template size_t formal_solve_lds<double>(int, int, int);
+
+template <typename T>
+hipError_t launch_formal_solve_batch(const FSArgs<T> *descs, const int4 *items, int nitems,
+                                     unsigned int *queue, const int *active, int ch, int nthreads,
+                                     size_t lds, int grid, hipStream_t s)
+{
+    if (nitems == 0) return hipSuccess;
+    if (sizeof(T) == 8 && nthreads <= 512)
+        k_formal_solve_batch<T, 512><<<grid, nthreads, lds, s>>>(descs, items, nitems, queue,
+                                                                 active, ch);
+    else
+        k_formal_solve_batch<T, 1024><<<grid, nthreads, lds, s>>>(descs, items, nitems, queue,
+                                                                  active, ch);
+    return hipGetLastError();
+}
+template hipError_t launch_formal_solve_batch<float>(const FSArgs<float> *, const int4 *, int,
+                                                     unsigned int *, const int *, int, int,
+                                                     size_t, int, hipStream_t);
+template hipError_t launch_formal_solve_batch<double>(const FSArgs<double> *, const int4 *, int,
+                                                      unsigned int *, const int *, int, int,
+                                                      size_t, int, hipStream_t);
+
+// Per-origin cost (trace records over all rays) for ordering batched work.
+__global__ void k_origin_cost(int N, int R, const int64_t *off, int64_t *cost)
+{
+    const int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= N) return;
+    cost[o] = off[(int64_t)o * R + R] - off[(int64_t)o * R];
+}
+
+hipError_t launch_origin_cost(int N, int R, const int64_t *off, int64_t *cost, hipStream_t s)
+{
+    k_origin_cost<<<(N + 255) / 256, 256, 0, s>>>(N, R, off, cost);
+    return hipGetLastError();
 }
 
 template <typename T>

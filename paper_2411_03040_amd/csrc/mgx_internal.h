@@ -105,6 +105,8 @@ struct StateqArgs {
     double *pops_new;
     double pop_floor;
     Counters *cnt;
+    const int *active;     // batched use: skip when active[model] == 0 (may be NULL)
+    int model;
 };
 
 // Launch wrappers (return hipError_t of the launch).
@@ -118,6 +120,18 @@ hipError_t launch_pack_trace(int64_t n, const int32_t *idx, const uint8_t *semi,
 hipError_t launch_line_coeffs(const LineArgs &a, hipStream_t s);
 template <typename T>
 hipError_t launch_formal_solve(const FSArgs<T> &a, hipStream_t s);
+// batched: persistent grid over (model, origin, chunk) items from a queue
+template <typename T>
+size_t formal_solve_lds(int ch, int nlc, int nthreads);
+template <typename T>
+hipError_t launch_formal_solve_batch(const FSArgs<T> *descs, const int4 *items, int nitems,
+                                     unsigned int *queue, const int *active, int ch, int nthreads,
+                                     size_t lds, int grid, hipStream_t s);
+hipError_t launch_queue_reset(unsigned int *q, int n, hipStream_t s);
+hipError_t launch_origin_cost(int N, int R, const int64_t *off, int64_t *cost, hipStream_t s);
+hipError_t launch_copy_if_active(int64_t n, const double *src, double *dst, const int *active,
+                                 int model, hipStream_t s);
+hipError_t launch_gather_changes(int M, Counters *const *cnt, double *out, hipStream_t s);
 hipError_t launch_lte(int N, int nlev, const double *T, const double *E, const double *g,
                       double *pops, hipStream_t s);
 hipError_t launch_stateq(const StateqArgs &a, hipStream_t s);

@@ -75,6 +75,7 @@ __device__ __forceinline__ double wave_max(double v)
 __global__ __launch_bounds__(256) void k_stateq(StateqArgs a)
 {
     extern __shared__ double sm[];
+    if (a.active && !a.active[a.model]) return;  // uniform over the grid
     const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int L = a.nlev, L1 = L + 1;
     double *M = sm + (size_t)wid * L * L1;
@@ -219,6 +220,42 @@ hipError_t launch_copy(int64_t n, const double *src, double *dst, hipStream_t s)
     if (blocks > 4096) blocks = 4096;
     if (blocks < 1) blocks = 1;
     k_copy<<<blocks, 256, 0, s>>>(n, src, dst);
+    return hipGetLastError();
+}
+
+__global__ void k_copy_if_active(int64_t n, const double *src, double *dst, const int *active,
+                                 int model)
+{
+    if (!active[model]) return;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+hipError_t launch_copy_if_active(int64_t n, const double *src, double *dst, const int *active,
+                                 int model, hipStream_t s)
+{
+    int blocks = (int)((n + 255) / 256);
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    k_copy_if_active<<<blocks, 256, 0, s>>>(n, src, dst, active, model);
+    return hipGetLastError();
+}
+
+// per-model max relative change (IEEE bits in each model's counters) -> out[m],
+// and a failure flag -> out[M + m]: 1 singular system, 2 non-finite result
+__global__ void k_gather_changes(int M, Counters *const *cnt, double *out)
+{
+    const int m = blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M) return;
+    const Counters *c = cnt[m];
+    out[m] = __longlong_as_double((long long)c->change_bits);
+    out[M + m] = c->singular ? 1.0 : (c->nonfinite ? 2.0 : 0.0);
+}
+
+hipError_t launch_gather_changes(int M, Counters *const *cnt, double *out, hipStream_t s)
+{
+    k_gather_changes<<<(M + 255) / 256, 256, 0, s>>>(M, cnt, out);
     return hipGetLastError();
 }
 

@@ -52,6 +52,14 @@ class ModelStruct(C.Structure):
     ]
 
 
+class BatchStats(C.Structure):
+    _fields_ = [("models", C.c_int), ("active", C.c_int), ("iterations", C.c_int),
+                ("lane_classes", C.c_int), ("work_items", C.c_int64),
+                ("class_threads", C.c_int * 5), ("class_chunk", C.c_int * 5),
+                ("class_grid", C.c_int * 5), ("tune_seconds", C.c_double),
+                ("iterate_seconds", C.c_double)]
+
+
 class Counters(C.Structure):
     _fields_ = [("total_records", C.c_int64), ("holes", C.c_int64),
                 ("semi_segments", C.c_int64), ("masing", C.c_int64), ("singular", C.c_int64),
@@ -100,6 +108,16 @@ def lib():
         "mgx_get_counters": (I, [P, P]),
         "mgx_reset_timers": (I, [P]),
         "mgx_render_image": (I, [P, P, I, I, D, D, I, P]),
+        "mgx_batch_create": (I, [P, I, P, P]),
+        "mgx_batch_destroy": (None, [P]),
+        "mgx_batch_last_error": (C.c_char_p, [P]),
+        "mgx_batch_add_model": (I, [P, P, P]),
+        "mgx_batch_prepare": (I, [P]),
+        "mgx_batch_set_lte_populations": (I, [P]),
+        "mgx_batch_set_populations": (I, [P, I, P]),
+        "mgx_batch_get_populations": (I, [P, I, P]),
+        "mgx_batch_iterate": (I, [P, D, I, I, P, P, P]),
+        "mgx_batch_get_stats": (I, [P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -132,6 +150,32 @@ def _torch_stream(device: int):
     return torch.cuda.current_stream(device).cuda_stream
 
 
+def _options(precision, branch_threshold, tau_floor, chi_min, pop_floor) -> Options:
+    opt = Options()
+    lib().mgx_default_options(C.byref(opt))
+    opt.precision = precision
+    opt.branch_threshold = branch_threshold
+    opt.tau_floor = tau_floor
+    opt.chi_min = chi_min
+    opt.pop_floor = pop_floor
+    return opt
+
+
+def _model_struct(m):
+    """mgx_model view of a synthetic model; the arrays must outlive the call."""
+    a = m.arrays()
+    s = ModelStruct()
+    s.dim, s.npoints = m.dim, m.npoints
+    for k in ("pos", "vel", "nbs_off", "nbs", "bdy", "T", "vturb2", "nspec", "ncoll",
+              "ray_dir", "ray_w", "antipode", "E", "g", "up", "lo", "A", "nu", "cu", "cl",
+              "K0"):
+        setattr(s, k, a[k].ctypes.data)
+    s.nrays, s.mass, s.nlev, s.nlines = m.nrays, m.mass, m.nlev, m.nlines
+    s.ncoll_tr = int(a["K0"].size)
+    s.nbins, s.xmax, s.Tcmb = m.nbins, m.xmax, m.Tcmb
+    return s, a
+
+
 class Context:
     """One model on one GPU.  Mirrors the C ABI entry points by name."""
 
@@ -139,13 +183,7 @@ class Context:
                  use_torch_stream: bool = True, branch_threshold: float = 0.35,
                  tau_floor: float = 1e-15, chi_min: float = 1e-30, pop_floor: float = 1e-12):
         L = lib()
-        opt = Options()
-        L.mgx_default_options(C.byref(opt))
-        opt.precision = precision
-        opt.branch_threshold = branch_threshold
-        opt.tau_floor = tau_floor
-        opt.chi_min = chi_min
-        opt.pop_floor = pop_floor
+        opt = _options(precision, branch_threshold, tau_floor, chi_min, pop_floor)
         if stream is None and use_torch_stream:
             stream = _torch_stream(device)
         h = C.c_void_p()
@@ -181,17 +219,9 @@ class Context:
 
     # -- model ------------------------------------------------------------------
     def load_model(self, m) -> None:
-        a = m.arrays()
-        s = ModelStruct()
-        s.dim, s.npoints = m.dim, m.npoints
-        for k in ("pos", "vel", "nbs_off", "nbs", "bdy", "T", "vturb2", "nspec", "ncoll",
-                  "ray_dir", "ray_w", "antipode", "E", "g", "up", "lo", "A", "nu", "cu", "cl",
-                  "K0"):
-            setattr(s, k, a[k].ctypes.data)
-        s.nrays, s.mass, s.nlev, s.nlines = m.nrays, m.mass, m.nlev, m.nlines
-        s.ncoll_tr = int(a["K0"].size)
-        s.nbins, s.xmax, s.Tcmb = m.nbins, m.xmax, m.Tcmb
+        s, keep = _model_struct(m)
         self._check(lib().mgx_load_model(self._h, C.byref(s)))
+        del keep
         self.model = m
 
     def trace_rays(self) -> int:
@@ -295,6 +325,93 @@ class Context:
             out = np.zeros((npy, npx, nfreq), np.float32)
         self._check(lib().mgx_render_image(self._h, d, npx, npy, f_min, f_max, nfreq,
                                            _ptr(out)))
+        return out
+
+
+class Batch:
+    """Many models iterated together on one GPU (mgx_batch_* entry points)."""
+
+    def __init__(self, device: int = 0, precision: int = FP32, stream: Optional[int] = None,
+                 branch_threshold: float = 0.35, tau_floor: float = 1e-15,
+                 chi_min: float = 1e-30, pop_floor: float = 1e-12):
+        # stream None: the library creates its own (graph capture cannot use
+        # the legacy default stream)
+        L = lib()
+        opt = _options(precision, branch_threshold, tau_floor, chi_min, pop_floor)
+        h = C.c_void_p()
+        st = L.mgx_batch_create(C.byref(h), device, stream, C.byref(opt))
+        if st != MGX_OK:
+            raise MgxError(st, L.mgx_batch_last_error(None).decode())
+        self._h = h
+        self.precision = precision
+        self.models = []
+
+    def _check(self, st: int):
+        if st != MGX_OK:
+            raise MgxError(st, lib().mgx_batch_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().mgx_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def add_model(self, m) -> int:
+        s, keep = _model_struct(m)
+        i = C.c_int()
+        self._check(lib().mgx_batch_add_model(self._h, C.byref(s), C.byref(i)))
+        del keep
+        self.models.append(m)
+        return i.value
+
+    def prepare(self) -> None:
+        self._check(lib().mgx_batch_prepare(self._h))
+
+    def set_lte_populations(self) -> None:
+        self._check(lib().mgx_batch_set_lte_populations(self._h))
+
+    def set_populations(self, i: int, pops) -> None:
+        pops = np.ascontiguousarray(pops, np.float64) if isinstance(pops, np.ndarray) else pops
+        self._check(lib().mgx_batch_set_populations(self._h, i, _ptr(pops)))
+
+    def get_populations(self, i: int, out=None):
+        m = self.models[i]
+        if out is None:
+            out = np.empty((m.npoints, m.nlev), np.float64)
+        self._check(lib().mgx_batch_get_populations(self._h, i, _ptr(out)))
+        return out
+
+    def iterate(self, tol: float = 1e-10, max_iter: int = 500, ng_order: int = 0,
+                raise_on_noconv: bool = True):
+        M = len(self.models)
+        its = np.zeros(M, np.int32)
+        chg = np.zeros(M, np.float64)
+        nconv = C.c_int()
+        st = lib().mgx_batch_iterate(self._h, tol, max_iter, ng_order, _ptr(its), _ptr(chg),
+                                     C.byref(nconv))
+        if st == MGX_ENOCONV and not raise_on_noconv:
+            return its, chg, nconv.value
+        self._check(st)
+        return its, chg, nconv.value
+
+    def stats(self) -> dict:
+        s = BatchStats()
+        self._check(lib().mgx_batch_get_stats(self._h, C.byref(s)))
+        out = {}
+        for k, _ in BatchStats._fields_:
+            v = getattr(s, k)
+            out[k] = list(v) if not isinstance(v, (int, float)) else v
         return out
 
 

@@ -1,0 +1,163 @@
+"""GPU parity of batched execution: many uneven models iterated together in
+persistent lane-class launches replayed from one captured graph.
+
+Each model's populations must equal those of a lone context with the same
+options bit for bit (same arithmetic, only the schedule differs), and match
+the FP64 oracle to the single-model bars (1e-10 FP64, 1e-4 FP32 bulk).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2411_03040_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def mgx():
+    import torch
+    assert torch.cuda.is_available(), "GPU test on a host without a GPU"
+    from paper_2411_03040_amd import mgx as m
+    m.lib()
+    return m
+
+
+def rel(a, b, floor=1e-12):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return float(np.max(np.abs(a - b) / np.maximum(np.abs(b), floor))) if a.size else 0.0
+
+
+def bits_equal(a, b):
+    a = np.ascontiguousarray(a, np.float64)
+    b = np.ascontiguousarray(b, np.float64)
+    return a.shape == b.shape and np.array_equal(a.view(np.int64), b.view(np.int64))
+
+
+def uneven_models():
+    """Mixed sizes, level counts, bin counts, ray sets and dimensions: every
+    lane class from 64 to 1024 threads appears."""
+    return [
+        synth.outflow_3d(npoints=300, seed=5, nside=1, nlev=4, nbins=15),      # 45 -> 64
+        synth.outflow_3d(npoints=600, seed=6, nside=1, nlev=6, nbins=15),      # 75 -> 128
+        synth.outflow_3d(npoints=150, seed=7, nside=2, nlev=3, nbins=31),      # 62 -> 64
+        synth.outflow_3d(npoints=250, seed=8, nside=1, nlev=8, nbins=63),      # 441 -> 512
+        synth.outflow_3d(npoints=200, seed=9, nside=1, nlev=5, nbins=63),      # 252 -> 256
+        synth.outflow_3d(npoints=120, seed=10, nside=1, nlev=12, nbins=90),    # 990 -> 1024
+        synth.spherical_shells("a"),
+        synth.spherical_shells("b", npoints=40, nbins=21),
+    ]
+
+
+def single(mgx, m, prec, tol, ng):
+    c = mgx.Context(precision=prec)
+    c.load_model(m)
+    c.trace_rays()
+    c.set_lte_populations()
+    it, ch, ok = c.iterate(tol=tol, max_iter=800, ng_mode=1 if ng else 0, ng_param=ng or 4)
+    return it, c.get_populations()
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-7)])
+def test_batch_equals_single_context(mgx, prec, tol):
+    models = uneven_models()
+    say(f"batch of {len(models)} models, precision {prec}")
+    b = mgx.Batch(precision=prec)
+    for i, m in enumerate(models):
+        assert b.add_model(m) == i
+    b.prepare()
+    b.set_lte_populations()
+    its, chg, nconv = b.iterate(tol=tol, max_iter=800, ng_order=4)
+    st = b.stats()
+    say(f"  iters {its.tolist()} classes {st['lane_classes']} threads {st['class_threads']} "
+        f"chunk {st['class_chunk']} grid {st['class_grid']} tune {st['tune_seconds']:.2f}s")
+    assert nconv == len(models)
+    assert st["lane_classes"] >= 4
+    assert st["iterations"] == int(its.max())
+    for i, m in enumerate(models):
+        it1, p1 = single(mgx, m, prec, tol, 4)
+        got = b.get_populations(i)
+        assert its[i] == it1, (i, its[i], it1)
+        assert bits_equal(got, p1), (i, rel(got, p1))
+
+
+@pytest.mark.parametrize("prec,tol,bar", [(0, 1e-12, 1e-10), (1, 1e-7, 1e-4)])
+def test_batch_against_oracle(mgx, prec, tol, bar):
+    models = [synth.outflow_3d(npoints=300, seed=5, nside=1, nlev=4, nbins=15),
+              synth.spherical_shells("a"),
+              synth.outflow_3d(npoints=150, seed=7, nside=2, nlev=3, nbins=31)]
+    refs = []
+    for m in models:
+        r = oracle.Oracle(m).iterate(tol=1e-12, max_iter=800, ng_mode=1, ng_param=4)
+        assert r["status"] == 0
+        refs.append(r)
+    b = mgx.Batch(precision=prec)
+    for m in models:
+        b.add_model(m)
+    b.prepare()
+    b.set_lte_populations()
+    its, chg, nconv = b.iterate(tol=tol, max_iter=800, ng_order=4)
+    assert nconv == len(models)
+    for i, r in enumerate(refs):
+        e = rel(b.get_populations(i), r["pops"])
+        say(f"  model {i} iters {its[i]} (oracle {r['iters']}) rel {e:.3e}")
+        assert e < bar
+
+
+def test_batch_replay_reuse_and_masking(mgx):
+    """A second iterate reuses the tuned graph and reproduces the first; a
+    model started from its converged state stops after one replay while the
+    others continue (its populations are then left alone)."""
+    models = uneven_models()[:4]
+    b = mgx.Batch(precision=0)
+    for m in models:
+        b.add_model(m)
+    b.prepare()
+    b.set_lte_populations()
+    its1, _, _ = b.iterate(tol=1e-10, max_iter=800, ng_order=0)
+    first = [b.get_populations(i) for i in range(len(models))]
+    b.set_lte_populations()
+    b.set_populations(2, first[2])
+    its2, chg2, nconv = b.iterate(tol=1e-10, max_iter=800, ng_order=0)
+    say(f"  first {its1.tolist()} second {its2.tolist()}")
+    assert nconv == len(models)
+    assert its2[2] == 1 and chg2[2] <= 1e-10
+    for i in (0, 1, 3):
+        assert its2[i] == its1[i]
+        assert bits_equal(b.get_populations(i), first[i])
+    # one more Lambda-iteration of an already converged model
+    assert rel(b.get_populations(2), first[2]) <= 1e-10
+    assert b.stats()["tune_seconds"] > 0
+
+
+def test_batch_noconv_and_errors(mgx):
+    m = synth.outflow_3d(npoints=150, seed=7, nside=1, nlev=3, nbins=15)
+    b = mgx.Batch(precision=1)
+    with pytest.raises(mgx.MgxError) as e:
+        b.prepare()
+    assert e.value.status == mgx.MGX_ESTATE
+    b.add_model(m)
+    with pytest.raises(mgx.MgxError) as e:
+        b.iterate(tol=1e-8, max_iter=5)
+    assert e.value.status == mgx.MGX_ESTATE
+    b.prepare()
+    with pytest.raises(mgx.MgxError) as e:
+        b.add_model(m)
+    assert e.value.status == mgx.MGX_ESTATE
+    with pytest.raises(mgx.MgxError) as e:
+        b.set_populations(3, np.ones((m.npoints, m.nlev)))
+    assert e.value.status == mgx.MGX_EINVAL
+    b.set_lte_populations()
+    its, chg, nconv = b.iterate(tol=0.0, max_iter=3, raise_on_noconv=False)
+    assert nconv == 0 and its[0] == 3 and chg[0] > 0
+    with pytest.raises(mgx.MgxError) as e:
+        b.iterate(tol=0.0, max_iter=2)
+    assert e.value.status == mgx.MGX_ENOCONV
