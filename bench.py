@@ -57,7 +57,10 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
-    p.add_argument("--workload", choices=["outflow", "clumpy", "shells"], default="outflow")
+    p.add_argument("--workload", choices=["outflow", "clumpy", "shells", "batch"],
+                   default="outflow")
+    p.add_argument("--batch-models", type=int, default=256,
+                   help="models in the batch workload (the recipe's first K)")
     p.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     p.add_argument("--no-converge", action="store_true", help="skip converged-model timing")
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -211,6 +214,95 @@ def ng_study(mgx, torch):
     return res
 
 
+def bench_batch(args, mgx, torch):
+    """Many uneven models iterated together: a step is one iteration of every
+    model (three graph replays: line coefficients, formal solution, statistical
+    equilibrium), all models active; then the whole batch converged from LTE."""
+    from paper_2411_03040_amd import synth
+    t0 = time.perf_counter()
+    spec = synth.batch_spec(args.batch_models)
+    prec = mgx.FP32 if args.precision == "fp32" else mgx.FP64
+    b = mgx.Batch(device=0, precision=prec)
+    for i, kw in enumerate(spec):
+        b.add_model(synth.outflow_3d(**kw))
+        if i % 32 == 31:
+            log(f"bench batch: {i + 1} models generated and loaded")
+    gen_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    b.prepare()
+    prep_s = time.perf_counter() - t0
+    log(f"bench batch: traced and prepared in {prep_s:.1f} s")
+    b.set_lte_populations()
+    b.iterate(tol=0.0, max_iter=max(1, args.warmup), raise_on_noconv=False)
+    log("bench batch: tuned, captured, warmed up")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.iterate(tol=0.0, max_iter=args.steps, raise_on_noconv=False)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = b.stats()
+    ms_step = dt / args.steps * 1e3
+    fs_ms = st["fs_ms_total"] / max(st["fs_launches"], 1)
+    upd = st["updates_per_iteration"]
+    value = upd / (ms_step * 1e-3)
+    flop = (st["lane_records"] * FLOP_PER_ELEMENT + st["lane_semi"] * FLOP_PER_SEMI +
+            st["lane_origin_pairs"] * FLOP_PER_ORIGIN_ROW)
+    peak = PEAK_FP32_TFLOPS if prec == mgx.FP32 else PEAK_FP64_TFLOPS
+    achieved = flop / (fs_ms * 1e-3) / 1e12
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+            "frac": round(achieved / peak, 4), "traffic": None,
+            "kernel": "k_formal_solve_batch (all lane classes of one iteration)",
+            "flop_per_launch": flop, "ms_per_launch": round(fs_ms, 4)}
+    log(f"bench batch: {ms_step:.1f} ms/step, formal solution {fs_ms:.1f} ms")
+    # converged from LTE (FP32-bulk formal solution, FP64 statistical
+    # equilibrium, classical Ng of order 4), each model stopping on its own
+    b.set_lte_populations()
+    tol = 1e-6 if prec == mgx.FP32 else 1e-10
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its, chg, nconv = b.iterate(tol=tol, max_iter=args.max_iter, ng_order=4,
+                                raise_on_noconv=False)
+    torch.cuda.synchronize()
+    conv_s = time.perf_counter() - t0
+    log(f"bench batch: converged {nconv}/{len(spec)} in {conv_s:.1f} s")
+    stuck = [{"model": i, "npoints": spec[i]["npoints"], "levels": spec[i]["nlev"],
+              "rays": 12 if spec[i]["nside"] == 1 else 48, "last_change": float(chg[i])}
+             for i in range(len(spec)) if not chg[i] <= tol]
+    npts = [kw["npoints"] for kw in spec]
+    out = {
+        "metric": METRIC, "value": value, "unit": "updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if prec == mgx.FP32 else "f64", "data": "synthetic",
+        "config": {"workload": f"batch of {len(spec)} outflow models: points log-uniform "
+                               f"1e3-1e5 (total {sum(npts)}), 2-20 levels, 12 or 48 rays, "
+                               "31 bins/line",
+                   "models": len(spec), "total_points": int(sum(npts)),
+                   "formal_solve": args.precision, "stateq": "f64", "ng": "classical order 4"},
+        "formal_solve_ms": fs_ms, "updates_per_step": upd,
+        "schedule": {"lane_classes": st["lane_classes"], "work_items": st["work_items"],
+                     "tune_seconds": st["tune_seconds"],
+                     "classes": [{"threads": st["class_threads"][k],
+                                  "items": st["class_items"][k],
+                                  "chunk": st["class_chunk"][k]}
+                                 for k in range(16) if st["class_items"][k]]},
+        "generate_seconds": gen_s, "prepare_seconds": prep_s,
+        "converged": {"seconds": conv_s, "models_converged": nconv, "tol": tol,
+                      "replays": int(its.max()), "iterations_median": float(np.median(its)),
+                      "iterations_max": int(its.max()), "not_converged": stuck},
+        "roofline": roof,
+    }
+    if not args.no_cpu:
+        # the oracle on a sample of origins of one mid-sized model of the batch
+        j = int(np.argsort(npts)[len(npts) // 2])
+        log(f"bench batch: CPU oracle baseline on model {j}")
+        out["cpu_baseline"] = cpu_baseline(synth.outflow_3d(**spec[j]), args.cpu_seconds)
+        out["cpu_baseline"]["sample"] += f" (batch model {j}, {npts[j]} points)"
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -224,6 +316,9 @@ def main():
     torch.cuda.set_device(0)
     if args.ng_study:
         print(json.dumps({"ng_study": ng_study(mgx, torch)}), flush=True)
+        return
+    if args.workload == "batch":
+        bench_batch(args, mgx, torch)
         return
     m, desc = make_model(args.workload)
     prec = mgx.FP32 if args.precision == "fp32" else mgx.FP64

@@ -254,28 +254,42 @@ mgx_status mgx_render_image(mgx_ctx *ctx, const double dir[3], int npx, int npy,
 /* ------------------------------------------------------------------------
  * Batches: many independent models (grids of medium-sized models, the
  * use the paper's limitations section names) solved together on one GPU.
- * Each model keeps its own state; every Lambda-iteration of the batch is one
- * replay of a captured HIP graph: line coefficients of every model, one
- * persistent formal-solution launch per lane class (models grouped by
- * lines x bins; work items (model, origin, line chunk) ordered longest first
- * and pulled from an atomic queue), statistical equilibrium of every model.
- * Converged models are masked on the device; classical Ng runs per model
- * between replays.  Per-model results equal those of a lone context with the
- * same options, bit for bit.
+ * Each model keeps its own state; every Lambda-iteration of the batch is a
+ * replay of captured HIP graphs: line coefficients of every model, one
+ * formal-solution launch per lane class (models grouped by workgroup size;
+ * one workgroup per work item (model, origin, line chunk), items ordered
+ * longest first), statistical equilibrium of every model.  Converged models
+ * are masked on the device and their work items compacted away; classical Ng
+ * runs per model between replays.  Per-model results equal those of a lone
+ * context with the same options, bit for bit.
  * ---------------------------------------------------------------------- */
 typedef struct mgx_batch mgx_batch;
+
+/* Lane classes: class k holds the models whose workgroup (lines of one chunk
+   x bins, rounded up to whole waves) has 64 (k + 1) threads. */
+#define MGX_BATCH_CLASSES 16
 
 typedef struct {
     int models;               /* models in the batch                            */
     int active;               /* models not yet converged                       */
     int iterations;           /* graph replays in the last mgx_batch_iterate    */
-    int lane_classes;         /* persistent launches per iteration              */
+    int lane_classes;         /* formal-solution launches per iteration         */
     int64_t work_items;       /* (model, origin, line chunk) items              */
-    int class_threads[5];     /* workgroup size of each lane class              */
-    int class_chunk[5];       /* tuned LDS records per half, per class          */
-    int class_grid[5];        /* tuned persistent grid size, per class          */
+    int class_items[MGX_BATCH_CLASSES];    /* work items per lane class (0: unused) */
+    int class_threads[MGX_BATCH_CLASSES];  /* workgroup size of each used class     */
+    int class_chunk[MGX_BATCH_CLASSES];    /* tuned LDS records per half            */
     double tune_seconds;      /* time spent tuning the schedule                  */
     double iterate_seconds;   /* wall time of the last mgx_batch_iterate        */
+    /* work of one iteration over all models (lanes = lines x bins of a model) */
+    int64_t updates_per_iteration;  /* sum of N x rays x lanes                  */
+    int64_t lane_records;           /* sum of lanes x trace records             */
+    int64_t lane_semi;              /* sum of lanes x semi-analytic segments    */
+    int64_t lane_origin_pairs;      /* sum of lanes x N x ray pairs             */
+    /* formal-solution launches of the last mgx_batch_iterate, timed with
+       events around them on the batch stream */
+    int64_t fs_launches;
+    double fs_ms_total;
+    double fs_ms_last;
 } mgx_batch_stats;
 
 /* Create an empty batch on `device` with options for all models.  `stream`

@@ -11,7 +11,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libmgx.so")
-SOURCES = ["trace.hip", "formal_solve.hip", "stateq.hip", "ng.hip", "render.hip", "api.hip"]
+SOURCES = ["trace.hip", "formal_solve.hip", "stateq.hip", "ng.hip", "render.hip", "schedule.hip",
+           "api.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",

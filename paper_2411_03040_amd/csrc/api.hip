@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <functional>
 #include <new>
 #include <string>
 #include <utility>
@@ -1197,29 +1198,40 @@ struct mgx_batch {
     std::vector<mgx_ctx *> m;
     bool prepared = false, tuned = false;
     // device tables
-    DMem descs, active, changes, cnt_ptrs, queue;
-    DMem items[5];
+    DMem descs, active, changes, cnt_ptrs, counts, tune_count;
+    // work items per class: every item in longest-first order, and the items
+    // of the models still iterating (same order; *counts[k] of them)
+    DMem items_all[MGX_BATCH_CLASSES], items[MGX_BATCH_CLASSES];
+    DMem sample[MGX_BATCH_CLASSES];  // strided sample of the items, for tuning
+    int class_nsample[MGX_BATCH_CLASSES] = {};
+    void *select_tmp = nullptr;
+    size_t select_tmp_bytes = 0;
     int nclass = 0;
-    int class_threads[5] = {0, 0, 0, 0, 0};
-    int class_nitems[5] = {0, 0, 0, 0, 0};
-    int class_nlc_max[5] = {0, 0, 0, 0, 0};
-    int class_ch[5] = {64, 64, 64, 64, 64};
-    int class_grid[5] = {0, 0, 0, 0, 0};
+    // lane class k: workgroups of 64 (k + 1) threads
+    int class_threads[MGX_BATCH_CLASSES] = {};
+    int class_nitems[MGX_BATCH_CLASSES] = {};
+    int class_nlc_max[MGX_BATCH_CLASSES] = {};
+    int class_ch[MGX_BATCH_CLASSES] = {};
     int64_t work_items = 0;
     std::vector<int> host_active;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;
+    // one iteration as three captured graphs: line coefficients, formal
+    // solution (timed with events between the launches), populations
+    hipGraph_t graph[3] = {nullptr, nullptr, nullptr};
+    hipGraphExec_t gexec[3] = {nullptr, nullptr, nullptr};
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     mgx_batch_stats st{};
 
     ~mgx_batch()
     {
         if (stream) (void)hipStreamSynchronize(stream);
-        if (gexec) (void)hipGraphExecDestroy(gexec);
-        if (graph) (void)hipGraphDestroy(graph);
+        for (int i = 0; i < 3; i++) {
+            if (gexec[i]) (void)hipGraphExecDestroy(gexec[i]);
+            if (graph[i]) (void)hipGraphDestroy(graph[i]);
+        }
         for (mgx_ctx *c : m) delete c;
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
+        if (select_tmp) (void)hipFree(select_tmp);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
     }
     bool fp32() const { return opt.precision == MGX_FP32; }
@@ -1328,24 +1340,23 @@ extern "C" mgx_status mgx_batch_add_model(mgx_batch *b, const mgx_model *model, 
     BATCH_END(b)
 }
 
-static const int kClassCaps[5] = {64, 128, 256, 512, 1024};
-
 template <typename T>
 static void batch_build_tables(mgx_batch *b)
 {
     const int M = (int)b->m.size();
     std::vector<FSArgs<T>> d(M);
-    std::vector<std::vector<std::pair<int64_t, int4>>> cls(5);
+    std::vector<std::vector<std::pair<int64_t, int4>>> cls(MGX_BATCH_CLASSES);
     DMem cost;
-    for (int k = 0; k < 5; k++) {
-        b->class_threads[k] = kClassCaps[k];
+    for (int k = 0; k < MGX_BATCH_CLASSES; k++) {
+        b->class_threads[k] = 64 * (k + 1);
         b->class_nlc_max[k] = 0;
+        b->class_ch[k] = 64;
     }
     for (int i = 0; i < M; i++) {
         mgx_ctx *c = b->m[i];
         d[i] = fs_args<T>(c);
-        int k = 0;
-        while (kClassCaps[k] < d[i].nthreads) k++;
+        // a model's workgroup size is a multiple of 64 up to 1024
+        const int k = d[i].nthreads / 64 - 1;
         b->class_nlc_max[k] = std::max(b->class_nlc_max[k], d[i].nlc);
         cost.ensure(sizeof(int64_t) * c->N);
         HIPCHK(launch_origin_cost(c->N, c->R, c->offsets.as<int64_t>(), cost.as<int64_t>(),
@@ -1361,9 +1372,18 @@ static void batch_build_tables(mgx_batch *b)
                 cls[k].push_back({(hc[o] + c->npairs) * lanes, make_int4(i, o, ch, 0)});
     }
     upload(b->m[0], b->descs, d.data(), d.size());
+    b->st.updates_per_iteration = b->st.lane_records = b->st.lane_semi = 0;
+    b->st.lane_origin_pairs = 0;
+    for (mgx_ctx *c : b->m) {
+        const int64_t lanes = (int64_t)c->nlines * c->nbins;
+        b->st.updates_per_iteration += (int64_t)c->N * c->R * lanes;
+        b->st.lane_records += lanes * c->host_cnt.total_records;
+        b->st.lane_semi += lanes * c->host_cnt.semi_segments;
+        b->st.lane_origin_pairs += lanes * c->N * c->npairs;
+    }
     b->work_items = 0;
     b->nclass = 0;
-    for (int k = 0; k < 5; k++) {
+    for (int k = 0; k < MGX_BATCH_CLASSES; k++) {
         auto &v = cls[k];
         std::stable_sort(v.begin(), v.end(),
                          [](const std::pair<int64_t, int4> &x, const std::pair<int64_t, int4> &y) {
@@ -1374,8 +1394,16 @@ static void batch_build_tables(mgx_batch *b)
         b->class_nitems[k] = (int)it.size();
         b->work_items += (int64_t)it.size();
         if (!it.empty()) b->nclass++;
-        upload(b->m[0], b->items[k], it.data(), it.size());
+        upload(b->m[0], b->items_all[k], it.data(), it.size());
+        b->items[k].ensure(sizeof(int4) * std::max<size_t>(1, it.size()));
+        const size_t stride = it.size() >= 32768 ? 8 : 1;
+        std::vector<int4> smp;
+        for (size_t j = 0; j < it.size(); j += stride) smp.push_back(it[j]);
+        b->class_nsample[k] = (int)smp.size();
+        upload(b->m[0], b->sample[k], smp.data(), smp.size());
     }
+    b->counts.ensure(sizeof(int) * MGX_BATCH_CLASSES);
+    b->tune_count.ensure(sizeof(int));
     b->sync();
 }
 
@@ -1385,7 +1413,17 @@ extern "C" mgx_status mgx_batch_prepare(mgx_batch *b)
     REQUIRE(!b->m.empty(), MGX_ESTATE, "mgx_batch_prepare on an empty batch");
     REQUIRE(!b->prepared, MGX_ESTATE, "batch already prepared");
     const int M = (int)b->m.size();
-    for (mgx_ctx *c : b->m) check_sub(b, c, mgx_trace_rays(c, nullptr));
+    for (mgx_ctx *c : b->m) {
+        check_sub(b, c, mgx_trace_rays(c, nullptr));
+        // iterations read only the packed records: drop the raw trace
+        c->r_idx.release();
+        c->r_semi.release();
+        c->r_Z.release();
+        c->r_dv.release();
+        c->r_dx.release();
+        c->r_ibb.release();
+        c->counts.release();
+    }
     if (b->fp32())
         batch_build_tables<float>(b);
     else
@@ -1396,7 +1434,6 @@ extern "C" mgx_status mgx_batch_prepare(mgx_batch *b)
     b->host_active.assign(M, 1);
     upload(b->m[0], b->active, b->host_active.data(), (size_t)M);
     b->changes.ensure(sizeof(double) * 2 * M);
-    b->queue.ensure(sizeof(unsigned int) * 8);
     b->sync();
     b->prepared = true;
     BATCH_END(b)
@@ -1425,30 +1462,49 @@ extern "C" mgx_status mgx_batch_get_populations(mgx_batch *b, int id, double *po
     BATCH_END(b)
 }
 
-template <typename T>
-static void batch_launch_class(mgx_batch *b, int k, int nitems, int ch, int grid)
+// All items of every class in play again (start of an iterate call).
+static void batch_restore_items(mgx_batch *b)
 {
-    const size_t lds = formal_solve_lds<T>(ch, b->class_nlc_max[k], b->class_threads[k]);
-    unsigned int *q = b->queue.as<unsigned int>() + k;
-    HIPCHK(launch_queue_reset(q, 1, b->stream));
-    HIPCHK(launch_formal_solve_batch<T>((const FSArgs<T> *)b->descs.p, b->items[k].as<int4>(),
-                                        nitems, q, b->active.as<int>(), ch,
-                                        b->class_threads[k], lds, grid, b->stream));
+    for (int k = 0; k < MGX_BATCH_CLASSES; k++)
+        if (b->class_nitems[k])
+            HIPCHK(hipMemcpyAsync(b->items[k].p, b->items_all[k].p,
+                                  sizeof(int4) * b->class_nitems[k], hipMemcpyDeviceToDevice,
+                                  b->stream));
+    HIPCHK(hipMemcpyAsync(b->counts.p, b->class_nitems, sizeof(int) * MGX_BATCH_CLASSES,
+                          hipMemcpyHostToDevice, b->stream));
+    b->sync();
 }
 
-// Schedule tuning: per lane class, time the LDS chunk size and the persistent
-// grid size on the leading (heaviest) items and keep the fastest.
+// Keep only the items of models still iterating (after the mask changed).
+static void batch_compact_items(mgx_batch *b)
+{
+    for (int k = 0; k < MGX_BATCH_CLASSES; k++)
+        if (b->class_nitems[k])
+            HIPCHK(launch_compact_items(b->items_all[k].as<int4>(), b->class_nitems[k],
+                                        b->items[k].as<int4>(), b->counts.as<int>() + k,
+                                        b->active.as<int>(), &b->select_tmp,
+                                        &b->select_tmp_bytes, b->stream));
+}
+
+template <typename T>
+static void batch_launch_class(mgx_batch *b, int k, const int4 *items, const int *count,
+                               int blocks, int ch)
+{
+    const size_t lds = formal_solve_lds<T>(ch, b->class_nlc_max[k], b->class_threads[k]);
+    HIPCHK(launch_formal_solve_batch<T>((const FSArgs<T> *)b->descs.p, items, count, blocks,
+                                        b->active.as<int>(), ch, b->class_threads[k], lds,
+                                        b->stream));
+}
+
+// Schedule tuning: per lane class, time each LDS chunk size (records staged
+// per half-ray) on a strided sample of the class's items and keep the
+// fastest.
 template <typename T>
 static void batch_tune(mgx_batch *b)
 {
-    int ncu = 256;
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, b->device) == hipSuccess && prop.multiProcessorCount > 0)
-        ncu = prop.multiProcessorCount;
-    for (int k = 0; k < 5; k++) {
+    for (int k = 0; k < MGX_BATCH_CLASSES; k++) {
         const int n = b->class_nitems[k];
         if (n == 0) continue;
-        const int ntune = std::min(n, std::max(2048, n / 8));
         const int nlc = b->class_nlc_max[k], nth = b->class_threads[k];
         // the largest chunk that fits 60 KB (at least 8, as the single-model
         // launch does) and every smaller candidate
@@ -1456,38 +1512,56 @@ static void batch_tune(mgx_batch *b)
         while (formal_solve_lds<T>(chmax, nlc, nth) > 60 * 1024 && chmax > 8) chmax /= 2;
         REQUIRE(formal_solve_lds<T>(chmax, nlc, nth) <= 160 * 1024, MGX_EINVAL,
                 "line chunk does not fit the LDS");
+        const int ns = b->class_nsample[k];
+        HIPCHK(hipMemcpyAsync(b->tune_count.p, &ns, sizeof(int), hipMemcpyHostToDevice,
+                              b->stream));
         float best = INFINITY;
         for (int ch : {8, 16, 32, 64}) {
             if (ch > chmax || (ch == 8 && chmax > 8)) continue;
-            for (int bpc : {2, 4, 8}) {
-                const int grid = std::max(1, std::min(ntune, ncu * bpc));
-                HIPCHK(hipEventRecord(b->ev0, b->stream));
-                batch_launch_class<T>(b, k, ntune, ch, grid);
-                HIPCHK(hipEventRecord(b->ev1, b->stream));
-                b->sync();
-                float ms = 0.f;
-                HIPCHK(hipEventElapsedTime(&ms, b->ev0, b->ev1));
-                if (ms < best) {
-                    best = ms;
-                    b->class_ch[k] = ch;
-                    b->class_grid[k] = std::max(1, std::min(n, ncu * bpc));
-                }
+            HIPCHK(hipEventRecord(b->ev0, b->stream));
+            batch_launch_class<T>(b, k, b->sample[k].as<int4>(), b->tune_count.as<int>(), ns, ch);
+            HIPCHK(hipEventRecord(b->ev1, b->stream));
+            b->sync();
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, b->ev0, b->ev1));
+            if (ms < best) {
+                best = ms;
+                b->class_ch[k] = ch;
             }
         }
     }
 }
 
-// One Lambda-iteration of every model, captured once as a HIP graph.
+// One Lambda-iteration of every model, captured once as three HIP graphs.
+static void batch_capture_part(mgx_batch *b, int part, const std::function<void()> &body)
+{
+    HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    try {
+        body();
+    } catch (...) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(b->stream, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+    }
+    HIPCHK(hipStreamEndCapture(b->stream, &b->graph[part]));
+    HIPCHK(hipGraphInstantiate(&b->gexec[part], b->graph[part], nullptr, nullptr, 0));
+}
+
 template <typename T>
 static void batch_capture(mgx_batch *b)
 {
     const int M = (int)b->m.size();
-    HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-    try {
+    batch_capture_part(b, 0, [&]() {
         for (mgx_ctx *c : b->m) run_line_coeffs(c);
-        for (int k = 0; k < 5; k++)
+    });
+    batch_capture_part(b, 1, [&]() {
+        for (int k = 0; k < MGX_BATCH_CLASSES; k++)
             if (b->class_nitems[k])
-                batch_launch_class<T>(b, k, b->class_nitems[k], b->class_ch[k], b->class_grid[k]);
+                batch_launch_class<T>(b, k, b->items[k].as<int4>(), b->counts.as<int>() + k,
+                                      b->class_nitems[k], b->class_ch[k]);
+    });
+    batch_capture_part(b, 2, [&]() {
         for (int i = 0; i < M; i++) {
             mgx_ctx *c = b->m[i];
             StateqArgs s = stateq_args(c);
@@ -1500,14 +1574,7 @@ static void batch_capture(mgx_batch *b)
         }
         HIPCHK(launch_gather_changes(M, b->cnt_ptrs.as<Counters *>(), b->changes.as<double>(),
                                      b->stream));
-    } catch (...) {
-        hipGraph_t g = nullptr;
-        (void)hipStreamEndCapture(b->stream, &g);
-        if (g) (void)hipGraphDestroy(g);
-        throw;
-    }
-    HIPCHK(hipStreamEndCapture(b->stream, &b->graph));
-    HIPCHK(hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0));
+    });
 }
 
 extern "C" mgx_status mgx_batch_iterate(mgx_batch *b, double tol, int max_iter, int ng_order,
@@ -1524,6 +1591,7 @@ extern "C" mgx_status mgx_batch_iterate(mgx_batch *b, double tol, int max_iter, 
         clock_gettime(CLOCK_MONOTONIC, &ts);
         return ts.tv_sec + 1e-9 * ts.tv_nsec;
     };
+    batch_restore_items(b);
     if (!b->tuned) {
         const double t0 = wall();
         for (mgx_ctx *c : b->m) run_line_coeffs(c);
@@ -1539,6 +1607,8 @@ extern "C" mgx_status mgx_batch_iterate(mgx_batch *b, double tol, int max_iter, 
         b->tuned = true;
     }
     const double t0 = wall();
+    b->st.fs_launches = 0;
+    b->st.fs_ms_total = b->st.fs_ms_last = 0.0;
     for (mgx_ctx *c : b->m) {
         c->ng_active = false;
         if (ng_order > 0) ng_reset(c, ng_order + 1);
@@ -1551,11 +1621,20 @@ extern "C" mgx_status mgx_batch_iterate(mgx_batch *b, double tol, int max_iter, 
     int n_active = M, it = 0;
     mgx_status result = MGX_OK;
     for (it = 1; it <= max_iter && n_active > 0; it++) {
-        HIPCHK(hipGraphLaunch(b->gexec, b->stream));
+        HIPCHK(hipGraphLaunch(b->gexec[0], b->stream));
+        HIPCHK(hipEventRecord(b->ev0, b->stream));
+        HIPCHK(hipGraphLaunch(b->gexec[1], b->stream));
+        HIPCHK(hipEventRecord(b->ev1, b->stream));
+        HIPCHK(hipGraphLaunch(b->gexec[2], b->stream));
         std::vector<double> hc(2 * M);
         HIPCHK(hipMemcpyAsync(hc.data(), b->changes.p, sizeof(double) * 2 * M,
                               hipMemcpyDeviceToHost, b->stream));
         b->sync();
+        float fs_ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&fs_ms, b->ev0, b->ev1));
+        b->st.fs_ms_last = fs_ms;
+        b->st.fs_ms_total += fs_ms;
+        b->st.fs_launches++;
         bool mask_changed = false;
         for (int i = 0; i < M; i++) {
             if (!b->host_active[i]) continue;
@@ -1584,9 +1663,11 @@ extern "C" mgx_status mgx_batch_iterate(mgx_batch *b, double tol, int max_iter, 
                 }
             }
         }
-        if (mask_changed)
+        if (mask_changed) {
             HIPCHK(hipMemcpyAsync(b->active.p, b->host_active.data(), sizeof(int) * M,
                                   hipMemcpyHostToDevice, b->stream));
+            if (n_active > 0) batch_compact_items(b);
+        }
     }
     b->sync();
     for (mgx_ctx *c : b->m) c->ng_active = false;
@@ -1613,10 +1694,10 @@ extern "C" mgx_status mgx_batch_get_stats(mgx_batch *b, mgx_batch_stats *out)
     b->st.models = (int)b->m.size();
     b->st.lane_classes = b->nclass;
     b->st.work_items = b->work_items;
-    for (int k = 0; k < 5; k++) {
+    for (int k = 0; k < MGX_BATCH_CLASSES; k++) {
+        b->st.class_items[k] = b->class_nitems[k];
         b->st.class_threads[k] = b->class_nitems[k] ? b->class_threads[k] : 0;
         b->st.class_chunk[k] = b->class_nitems[k] ? b->class_ch[k] : 0;
-        b->st.class_grid[k] = b->class_nitems[k] ? b->class_grid[k] : 0;
     }
     *out = b->st;
     BATCH_END(b)

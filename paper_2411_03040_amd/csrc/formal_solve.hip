@@ -146,9 +146,28 @@ __host__ __device__ inline LDSLayout lds_layout(int ch, int nlc, int nthreads)
 // temporal) so they do not evict the per-point line table the gathers reuse.
 typedef int v4i __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ Rec<float> load_stream(const Rec<float> *p)
+// Global-memory pointers.  Every table the formal solution reads lives in
+// global memory; pointers loaded from device memory (the batched launch's
+// descriptors) are generic to the compiler and would otherwise become flat
+// accesses, which also wait on LDS traffic.
+template <typename X>
+using gptr = const __attribute__((address_space(1))) X *;
+template <typename X>
+using gptr_mut = __attribute__((address_space(1))) X *;
+template <typename X>
+__device__ __forceinline__ gptr<X> glob(const X *p)
 {
-    const v4i v = __builtin_nontemporal_load((const v4i *)p);
+    return (gptr<X>)p;
+}
+template <typename X>
+__device__ __forceinline__ gptr_mut<X> glob_mut(X *p)
+{
+    return (gptr_mut<X>)p;
+}
+
+__device__ __forceinline__ Rec<float> load_stream(gptr<Rec<float>> p)
+{
+    const v4i v = __builtin_nontemporal_load((gptr<v4i>)p);
     Rec<float> r;
     r.ps = v.x;
     r.dx = __int_as_float(v.y);
@@ -157,10 +176,10 @@ __device__ __forceinline__ Rec<float> load_stream(const Rec<float> *p)
     return r;
 }
 
-__device__ __forceinline__ Rec<double> load_stream(const Rec<double> *p)
+__device__ __forceinline__ Rec<double> load_stream(gptr<Rec<double>> p)
 {
-    const v4i v0 = __builtin_nontemporal_load((const v4i *)p);
-    const v4i v1 = __builtin_nontemporal_load((const v4i *)p + 1);
+    const v4i v0 = __builtin_nontemporal_load((gptr<v4i>)p);
+    const v4i v1 = __builtin_nontemporal_load((gptr<v4i>)p + 1);
     Rec<double> r;
     r.ps = v0.x;
     r.pad = 0;
@@ -194,23 +213,31 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
     const int f = tid % nb;
     const int l = l0 + ll;
 
+    const gptr<int64_t> off = glob(a.off);
+    const gptr<Rec<T>> rec = glob(a.rec);
+    const gptr<int32_t> pair_r = glob(a.pair_r), pair_a = glob(a.pair_a);
+    const gptr<double> pair_w = glob(a.pair_w), b64 = glob(a.b64), xf = glob(a.xf);
+    const gptr<double> W = glob(a.W), acmb_l = glob(a.acmb), Iref = glob(a.Iref);
+    const gptr<T> chi = glob(a.chi), S = glob(a.S), bpt = glob(a.bpt), ibpt = glob(a.ibpt);
+    const gptr_mut<double> Jout = glob_mut(a.J), Lout = glob_mut(a.L);
+
     const LDSLayout LY = lds_layout<T>(ch, nlc, nth);
     MetaA<T> *s_a = (MetaA<T> *)(smem + LY.a);
     MetaB<T> *s_b = (MetaB<T> *)(smem + LY.b);
     LinePair<T> *s_line = (LinePair<T> *)(smem + LY.line);
 
     // per-lane constants
-    const double bo = a.b64[o];
-    const double xfd = a.xf[f];
+    const double bo = b64[o];
+    const double xfd = xf[f];
     const double xbd = xfd * bo;
     const T xb = (T)xbd;
     const T k1 = (T)(1.0 + xbd / kC);
     const T inv_c = (T)(1.0 / kC);
-    const T acmb = (T)a.acmb[l];
+    const T acmb = (T)acmb_l[l];
     const int64_t ol = (int64_t)o * nl + l;
-    const T chi_o = a.chi[ol] * (T)exp(-xfd * xfd);
-    const T S_o = a.S[ol];
-    const T cb_o = a.chi[ol] * a.bpt[o];
+    const T chi_o = chi[ol] * (T)exp(-xfd * xfd);
+    const T S_o = S[ol];
+    const T cb_o = chi[ol] * bpt[o];
     const T tau_floor = (T)a.tau_floor;
     const T half = (T)0.5;
     const T spi4 = (T)(kSqrtPi / 4.0);
@@ -246,11 +273,11 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
     double accJ = 0.0, accL = 0.0;
     const int64_t R = a.R;
     for (int pi = 0; pi < a.npairs; pi++) {
-        const int rp = a.pair_r[pi], rm = a.pair_a[pi];
-        const int64_t offp = a.off[(int64_t)o * R + rp];
-        const int np = (int)(a.off[(int64_t)o * R + rp + 1] - offp);
-        const int64_t offm = a.off[(int64_t)o * R + rm];
-        const int nm = (int)(a.off[(int64_t)o * R + rm + 1] - offm);
+        const int rp = pair_r[pi], rm = pair_a[pi];
+        const int64_t offp = off[(int64_t)o * R + rp];
+        const int np = (int)(off[(int64_t)o * R + rp + 1] - offp);
+        const int64_t offm = off[(int64_t)o * R + rm];
+        const int nm = (int)(off[(int64_t)o * R + rm + 1] - offm);
         const int K = max(np, nm);
 
         HalfState<T> st[2];
@@ -274,16 +301,16 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
             for (int t = tid; t < cnt; t += nth) {
                 const bool plus = t >= cm;
                 const int k = lo + (plus ? t - cm : t);
-                const Rec<T> rc = load_stream(a.rec + (plus ? offp : offm) + k);
+                const Rec<T> rc = load_stream(rec + (plus ? offp : offm) + k);
                 const int p = rc.ps & 0x7fffffff;
                 MetaA<T> ma;
                 ma.dv = rc.dv;
-                ma.ib = a.ibpt[p];
+                ma.ib = ibpt[p];
                 ma.dx = rc.dx;
                 ma.ibb = rc.ibb;
                 s_a[t] = ma;
                 MetaB<T> mb;
-                mb.b = a.bpt[p];
+                mb.b = bpt[p];
                 mb.ps = rc.ps;
                 s_b[t] = mb;
             }
@@ -293,8 +320,8 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
                 const int li = t - e * nl_here;
                 const int64_t idx = (int64_t)(s_b[e].ps & 0x7fffffff) * nl + l0 + li;
                 LinePair<T> lp;
-                lp.chi = a.chi[idx];
-                lp.S = a.S[idx];
+                lp.chi = chi[idx];
+                lp.S = S[idx];
                 s_line[e * nlc + li] = lp;
             }
             __syncthreads();
@@ -341,14 +368,14 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
         const T inv_den = FM<T>::rcp(Do + st[0].g + st[1].g);
         const T u = (Do * S_o + st[0].eps + st[1].eps) * inv_den;
         const T lam = Do * inv_den;
-        const double w = a.pair_w[pi];
+        const double w = pair_w[pi];
         accJ += w * (double)u;
         accL += w * (double)lam;
     }
 
     __syncthreads();
     double *s_red = (double *)smem;
-    const double Wf = a.W[f];
+    const double Wf = W[f];
     s_red[tid] = active ? Wf * accJ : 0.0;
     s_red[nth + tid] = active ? Wf * accL : 0.0;
     __syncthreads();
@@ -359,8 +386,8 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
             sl += s_red[nth + tid * nb + ff];
         }
         const int64_t out = (int64_t)o * nl + l0 + tid;
-        a.J[out] = a.Iref[l0 + tid] * sj;
-        a.L[out] = sl;
+        Jout[out] = Iref[l0 + tid] * sj;
+        Lout[out] = sl;
     }
 }
 
@@ -371,40 +398,24 @@ __global__ __launch_bounds__(MAXT) void k_formal_solve(FSArgs<T> a, int ch)
     solve_origin<T>(a, blockIdx.x, blockIdx.y, ch, smem);
 }
 
-// Persistent batched launch: a fixed grid pulls work items (model, origin,
-// line chunk), ordered longest first, from an atomic queue; items of
-// converged (inactive) models are skipped.
+// Batched launch: one workgroup per work item (model, origin, line chunk) of
+// one lane class, items ordered longest first so the dispatcher hands out the
+// heavy ones early; workgroups past the live item count or of converged
+// (inactive) models return at once.  The descriptor of the item's model
+// replaces the kernel-argument descriptor of the single-model launch.
 template <typename T, int MAXT>
 __global__ __launch_bounds__(MAXT) void k_formal_solve_batch(const FSArgs<T> *__restrict__ descs,
                                                              const int4 *__restrict__ items,
-                                                             int nitems, unsigned int *queue,
+                                                             const int *__restrict__ count,
                                                              const int *__restrict__ active,
                                                              int ch)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    __shared__ int s_item;
-    for (;;) {
-        __syncthreads();  // everyone has read the previous item
-        if (threadIdx.x == 0) s_item = (int)atomicAdd(queue, 1u);
-        __syncthreads();
-        const int it = s_item;
-        if (it >= nitems) break;
-        const int4 w = items[it];
-        if (!active[w.x]) continue;
-        const FSArgs<T> a = descs[w.x];
-        solve_origin<T>(a, w.y, w.z, ch, smem);
-    }
-}
-
-__global__ void k_queue_reset(unsigned int *q, int n)
-{
-    if ((int)threadIdx.x < n) q[threadIdx.x] = 0u;
-}
-
-hipError_t launch_queue_reset(unsigned int *q, int n, hipStream_t s)
-{
-    k_queue_reset<<<1, 64, 0, s>>>(q, n);
-    return hipGetLastError();
+    const int it = blockIdx.x;
+    if (it >= *count) return;
+    const int4 w = items[it];
+    if (!active[w.x]) return;
+    solve_origin<T>(descs[w.x], w.y, w.z, ch, smem);
 }
 
 template <typename T>
@@ -416,39 +427,25 @@ template size_t formal_solve_lds<float>(int, int, int);
 template size_t formal_solve_lds<double>(int, int, int);
 
 template <typename T>
-hipError_t launch_formal_solve_batch(const FSArgs<T> *descs, const int4 *items, int nitems,
-                                     unsigned int *queue, const int *active, int ch, int nthreads,
-                                     size_t lds, int grid, hipStream_t s)
+hipError_t launch_formal_solve_batch(const FSArgs<T> *descs, const int4 *items, const int *count,
+                                     int blocks, const int *active, int ch, int nthreads,
+                                     size_t lds, hipStream_t s)
 {
-    if (nitems == 0) return hipSuccess;
+    if (blocks <= 0) return hipSuccess;
     if (sizeof(T) == 8 && nthreads <= 512)
-        k_formal_solve_batch<T, 512><<<grid, nthreads, lds, s>>>(descs, items, nitems, queue,
-                                                                 active, ch);
+        k_formal_solve_batch<T, 512><<<blocks, nthreads, lds, s>>>(descs, items, count, active,
+                                                                   ch);
     else
-        k_formal_solve_batch<T, 1024><<<grid, nthreads, lds, s>>>(descs, items, nitems, queue,
-                                                                  active, ch);
+        k_formal_solve_batch<T, 1024><<<blocks, nthreads, lds, s>>>(descs, items, count, active,
+                                                                    ch);
     return hipGetLastError();
 }
-template hipError_t launch_formal_solve_batch<float>(const FSArgs<float> *, const int4 *, int,
-                                                     unsigned int *, const int *, int, int,
-                                                     size_t, int, hipStream_t);
-template hipError_t launch_formal_solve_batch<double>(const FSArgs<double> *, const int4 *, int,
-                                                      unsigned int *, const int *, int, int,
-                                                      size_t, int, hipStream_t);
-
-// Per-origin cost (trace records over all rays) for ordering batched work.
-__global__ void k_origin_cost(int N, int R, const int64_t *off, int64_t *cost)
-{
-    const int o = blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= N) return;
-    cost[o] = off[(int64_t)o * R + R] - off[(int64_t)o * R];
-}
-
-hipError_t launch_origin_cost(int N, int R, const int64_t *off, int64_t *cost, hipStream_t s)
-{
-    k_origin_cost<<<(N + 255) / 256, 256, 0, s>>>(N, R, off, cost);
-    return hipGetLastError();
-}
+template hipError_t launch_formal_solve_batch<float>(const FSArgs<float> *, const int4 *,
+                                                     const int *, int, const int *, int, int,
+                                                     size_t, hipStream_t);
+template hipError_t launch_formal_solve_batch<double>(const FSArgs<double> *, const int4 *,
+                                                      const int *, int, const int *, int, int,
+                                                      size_t, hipStream_t);
 
 template <typename T>
 hipError_t launch_formal_solve(const FSArgs<T> &a, hipStream_t s)

@@ -124,11 +124,14 @@ hipError_t launch_formal_solve(const FSArgs<T> &a, hipStream_t s);
 template <typename T>
 size_t formal_solve_lds(int ch, int nlc, int nthreads);
 template <typename T>
-hipError_t launch_formal_solve_batch(const FSArgs<T> *descs, const int4 *items, int nitems,
-                                     unsigned int *queue, const int *active, int ch, int nthreads,
-                                     size_t lds, int grid, hipStream_t s);
-hipError_t launch_queue_reset(unsigned int *q, int n, hipStream_t s);
+hipError_t launch_formal_solve_batch(const FSArgs<T> *descs, const int4 *items, const int *count,
+                                     int blocks, const int *active, int ch, int nthreads,
+                                     size_t lds, hipStream_t s);
 hipError_t launch_origin_cost(int N, int R, const int64_t *off, int64_t *cost, hipStream_t s);
+// order-preserving selection of the items whose model is active; *count on
+// the device receives the number kept (tmp: cached scratch, grown as needed)
+hipError_t launch_compact_items(const int4 *in, int n, int4 *out, int *count, const int *active,
+                                void **tmp, size_t *tmp_bytes, hipStream_t s);
 hipError_t launch_copy_if_active(int64_t n, const double *src, double *dst, const int *active,
                                  int model, hipStream_t s);
 hipError_t launch_gather_changes(int M, Counters *const *cnt, double *out, hipStream_t s);

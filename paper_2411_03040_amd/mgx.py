@@ -55,9 +55,13 @@ class ModelStruct(C.Structure):
 class BatchStats(C.Structure):
     _fields_ = [("models", C.c_int), ("active", C.c_int), ("iterations", C.c_int),
                 ("lane_classes", C.c_int), ("work_items", C.c_int64),
-                ("class_threads", C.c_int * 5), ("class_chunk", C.c_int * 5),
-                ("class_grid", C.c_int * 5), ("tune_seconds", C.c_double),
-                ("iterate_seconds", C.c_double)]
+                ("class_items", C.c_int * 16), ("class_threads", C.c_int * 16),
+                ("class_chunk", C.c_int * 16),
+                ("tune_seconds", C.c_double),
+                ("iterate_seconds", C.c_double), ("updates_per_iteration", C.c_int64),
+                ("lane_records", C.c_int64), ("lane_semi", C.c_int64),
+                ("lane_origin_pairs", C.c_int64), ("fs_launches", C.c_int64),
+                ("fs_ms_total", C.c_double), ("fs_ms_last", C.c_double)]
 
 
 class Counters(C.Structure):

@@ -471,6 +471,28 @@ def config(i: int, **kw) -> Model:
     raise ValueError(i)
 
 
+def batch_spec(count: int = 256, seed: int = 4):
+    """Seeded recipe of a grid of independent models of uneven size: point
+    counts log-uniform in [1e3, 1e5], 2-20 rotor levels, 12 or 48 rays, 31
+    bins; each an outflow (as outflow_3d) with its own seed.  Returns a list
+    of keyword dicts for outflow_3d."""
+    out = []
+    for i in range(count):
+        rng = np.random.default_rng([seed, i])
+        out.append(dict(npoints=int(round(10 ** rng.uniform(3.0, 5.0))),
+                        nlev=int(rng.integers(2, 21)),
+                        nside=1 if rng.random() < 0.5 else 2,
+                        nbins=31, seed=10_000 + i))
+    return out
+
+
+def batch_models(count: int = 256, seed: int = 4, subset=None):
+    """The models of batch_spec (all, or the listed indices)."""
+    spec = batch_spec(count, seed)
+    idx = range(count) if subset is None else subset
+    return [outflow_3d(**spec[i]) for i in idx]
+
+
 def origin_sample(N: int, count: int, seed: int = 12345) -> np.ndarray:
     """Seeded sorted sample of origin points (for sampled parity / timing)."""
     rng = np.random.default_rng(seed)

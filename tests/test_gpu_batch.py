@@ -77,10 +77,16 @@ def test_batch_equals_single_context(mgx, prec, tol):
     b.set_lte_populations()
     its, chg, nconv = b.iterate(tol=tol, max_iter=800, ng_order=4)
     st = b.stats()
-    say(f"  iters {its.tolist()} classes {st['lane_classes']} threads {st['class_threads']} "
-        f"chunk {st['class_chunk']} grid {st['class_grid']} tune {st['tune_seconds']:.2f}s")
+    used = [k for k in range(16) if st["class_items"][k]]
+    say(f"  iters {its.tolist()} classes {[st['class_threads'][k] for k in used]} "
+        f"items {[st['class_items'][k] for k in used]} "
+        f"chunk {[st['class_chunk'][k] for k in used]} "
+        f"tune {st['tune_seconds']:.2f}s")
     assert nconv == len(models)
-    assert st["lane_classes"] >= 4
+    assert st["lane_classes"] == len(used) >= 5
+    assert sum(st["class_items"]) == st["work_items"] == sum(
+        m.npoints * -(-m.nlines // max(1, min(m.nlines, (512 if prec == 0 else 1024) // m.nbins)))
+        for m in models)
     assert st["iterations"] == int(its.max())
     for i, m in enumerate(models):
         it1, p1 = single(mgx, m, prec, tol, 4)
@@ -161,3 +167,49 @@ def test_batch_noconv_and_errors(mgx):
     with pytest.raises(mgx.MgxError) as e:
         b.iterate(tol=0.0, max_iter=2)
     assert e.value.status == mgx.MGX_ENOCONV
+
+
+def test_batch_workload_subset_fixed_point(mgx):
+    """Eight seeded models of the 256-model batch recipe at their full sizes
+    (1e3-1e5 points, 2-20 levels, 12 or 48 rays), converged as a batch in the
+    benchmark's launch configuration (FP32 formal solution, Ng order 4,
+    tol 1e-6).  At sampled points the oracle's own Lambda-iteration step from
+    the GPU's converged populations (its J-bar and Lambda* from all rays, then
+    its statistical equilibrium) must return those populations to 1e-4; two of
+    the models are also run alone and must agree bit for bit."""
+    idx = sorted(int(i) for i in np.random.default_rng(8).choice(256, 8, replace=False))
+    spec = synth.batch_spec()
+    models = synth.batch_models(subset=idx)
+    say("batch subset", idx, [m.npoints for m in models])
+    b = mgx.Batch(precision=mgx.FP32)
+    for m in models:
+        b.add_model(m)
+    b.prepare()
+    b.set_lte_populations()
+    its, chg, nconv = b.iterate(tol=1e-6, max_iter=300, ng_order=4)
+    say(f"  iters {its.tolist()}")
+    assert nconv == len(models)
+    worst = 0.0
+    for i, m in enumerate(models):
+        pops = b.get_populations(i)
+        orc = oracle.Oracle(m)
+        origins = synth.origin_sample(m.npoints, 6, seed=100 + idx[i])
+        J, L = orc.solve_origins(pops, origins)
+        _, _, S, _ = orc.line_coeffs(pops)
+        for k, p in enumerate(origins):
+            st, new = orc.stateq_point(int(p), J[k], L[k], S[p])
+            assert st == 0
+            e = rel(new, pops[p])
+            worst = max(worst, e)
+            assert e < 1e-4, (idx[i], int(p), e)
+    say(f"  worst fixed-point residual {worst:.3e}")
+    for i in (0, len(models) - 1):
+        kw = spec[idx[i]]
+        assert models[i].npoints == kw["npoints"]
+        c = mgx.Context(precision=mgx.FP32)
+        c.load_model(models[i])
+        c.trace_rays()
+        c.set_lte_populations()
+        it, _, ok = c.iterate(tol=1e-6, max_iter=300, ng_mode=1, ng_param=4)
+        assert ok and it == its[i]
+        assert bits_equal(c.get_populations(), b.get_populations(i))
