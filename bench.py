@@ -57,8 +57,11 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
-    p.add_argument("--workload", choices=["outflow", "clumpy", "shells", "batch"],
+    p.add_argument("--workload", choices=["outflow", "clumpy", "shells", "batch", "serve"],
                    default="outflow")
+    p.add_argument("--serve-seconds", type=float, default=20.0,
+                   help="serve workload: length of the request stream")
+    p.add_argument("--serve-models", type=int, default=8)
     p.add_argument("--batch-models", type=int, default=256,
                    help="models in the batch workload (the recipe's first K)")
     p.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
@@ -303,6 +306,105 @@ def bench_batch(args, mgx, torch):
     print(json.dumps(out), flush=True)
 
 
+def serve_spec(count, seed=7):
+    """Resident models of the serving workload: outflows with point counts
+    log-uniform in [1e4, 1e6], 5-20 levels, 12 rays, 31 bins (seeded)."""
+    out = []
+    for i in range(count):
+        rng = np.random.default_rng([seed, i])
+        out.append(dict(npoints=int(round(10 ** rng.uniform(4.0, 6.0))),
+                        nlev=int(rng.integers(5, 21)), nside=1, nbins=31, seed=20_000 + i))
+    return out
+
+
+def bench_serve(args, mgx, torch):
+    """A Poisson stream of requests (mean 50/s) on resident models: 98 %
+    renders (256 x 256 pixels x 63 bins around a line, random model and
+    inclination), 2 % converges from LTE (random model, FP32 formal solution,
+    tol 1e-6, Ng order 4).  Reports latency percentiles per kind and the
+    formal-solution updates/s the server sustained."""
+    from paper_2411_03040_amd import synth
+    spec = serve_spec(args.serve_models)
+    srv = mgx.Server(device=0, precision=mgx.FP32, render_slots=2)
+    t0 = time.perf_counter()
+    models = []
+    for i, kw in enumerate(spec):
+        m = synth.outflow_3d(**kw)
+        srv.add_model(m)
+        models.append(m)
+        log(f"bench serve: model {i} ({m.npoints} points, {m.nlev} levels) loaded")
+    gen_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    srv.start()
+    start_s = time.perf_counter() - t0
+    st0 = srv.stats()
+    log(f"bench serve: started in {start_s:.1f} s, resident {st0['hbm_resident'] / 1e9:.1f} GB")
+    rng = np.random.default_rng(11)
+    rate, T = 50.0, args.serve_seconds
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=int(rate * T * 2)))
+    arrivals = arrivals[arrivals < T]
+    kinds = np.where(rng.random(arrivals.size) < 0.02, 0, 1)
+    which = rng.integers(0, len(models), arrivals.size)
+    th = np.arccos(rng.uniform(-1, 1, arrivals.size))
+    ph = rng.uniform(0, 2 * np.pi, arrivals.size)
+    ids = []
+    c0 = srv.clock()
+    w0 = time.perf_counter()
+    for k, ta in enumerate(arrivals):
+        dt = ta - (time.perf_counter() - w0)
+        if dt > 0:
+            time.sleep(dt)
+        j = int(which[k])
+        m = models[j]
+        if kinds[k] == 0:
+            ids.append(srv.submit_converge(j, tol=1e-6, max_iter=200, ng_order=4))
+        else:
+            nu = m.nu[min(1, m.nlines - 1)]
+            d = (np.sin(th[k]) * np.cos(ph[k]), np.sin(th[k]) * np.sin(ph[k]), np.cos(th[k]))
+            ids.append(srv.submit_render(j, d, 256, 256, nu * (1 - 5e-5), nu * (1 + 5e-5), 63))
+        if k % 200 == 199:
+            log(f"bench serve: {k + 1} requests submitted")
+    infos = []
+    for rid in ids:
+        infos.append(srv.wait(rid, timeout=600, raise_on_error=False))
+        infos[-1].pop("image", None)
+    wall = srv.clock() - c0
+    st = srv.stats()
+    log(f"bench serve: {len(infos)} requests done in {wall:.1f} s")
+
+    def pct(v, q):
+        return float(np.percentile(v, q)) if len(v) else None
+
+    res = {}
+    for name, kind in (("converge", 0), ("render", 1)):
+        lat = [i["t_done"] - i["t_submit"] for i in infos if i["kind"] == kind and i["status"] == 0]
+        svc = [i["t_done"] - i["t_start"] for i in infos if i["kind"] == kind and i["status"] == 0]
+        res[name] = {"requests": int(sum(1 for i in infos if i["kind"] == kind)),
+                     "ok": len(lat), "latency_p50_s": pct(lat, 50), "latency_p99_s": pct(lat, 99),
+                     "service_p50_s": pct(svc, 50), "service_p99_s": pct(svc, 99)}
+    res["converge"]["iterations_median"] = float(np.median(
+        [i["iterations"] for i in infos if i["kind"] == 0] or [0]))
+    upd = st["updates"] - st0["updates"]
+    out = {
+        "metric": METRIC, "value": upd / wall, "unit": "updates/s", "n_gpus": 1,
+        "steps": len(infos), "warmup": 0, "ms_per_step": None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"serving: Poisson 50 req/s for {T:.0f} s on {len(models)} resident "
+                               "outflow models (points log-uniform 1e4-1e6, 5-20 levels, 12 rays, "
+                               "31 bins); 98% renders 256x256x63, 2% converges from LTE",
+                   "models": [{"npoints": m.npoints, "levels": m.nlev} for m in models]},
+        "requests": len(infos), "request_rate_per_s": len(infos) / wall, "wall_s": wall,
+        "latency": res, "replays": st["replays"] - st0["replays"],
+        "iterate_busy_s": st["iterate_busy_s"], "render_busy_s": st["render_busy_s"],
+        "hbm": {"budget": st["hbm_budget"], "resident": st["hbm_resident"],
+                "render_peak": st["hbm_render_peak"]},
+        "generate_seconds": gen_s, "start_seconds": start_s,
+        "roofline": None, "cpu_baseline": None,
+    }
+    srv.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -319,6 +421,9 @@ def main():
         return
     if args.workload == "batch":
         bench_batch(args, mgx, torch)
+        return
+    if args.workload == "serve":
+        bench_serve(args, mgx, torch)
         return
     m, desc = make_model(args.workload)
     prec = mgx.FP32 if args.precision == "fp32" else mgx.FP64

@@ -52,7 +52,8 @@ typedef enum {
     MGX_EHIP = -4,        /* HIP runtime error                              */
     MGX_ENOCONV = -5,     /* iteration did not converge within max_iter     */
     MGX_ESINGULAR = -6,   /* singular statistical-equilibrium system        */
-    MGX_ENONFINITE = -7   /* non-finite input or result                     */
+    MGX_ENONFINITE = -7,  /* non-finite input or result                     */
+    MGX_EPENDING = -8     /* server request not finished (wait timed out)   */
 } mgx_status;
 
 enum { MGX_FP64 = 0, MGX_FP32 = 1 };
@@ -324,6 +325,89 @@ mgx_status mgx_batch_iterate(mgx_batch *b, double tol, int max_iter, int ng_orde
                              double *changes, int *converged_out);
 
 mgx_status mgx_batch_get_stats(mgx_batch *b, mgx_batch_stats *out);
+
+/* ------------------------------------------------------------------------
+ * Server: a resident set of models answering a stream of requests.  The two
+ * request kinds are the two steps of the paper's workflow (section
+ * "Application / programmer interface"): determine the state of the medium
+ * (level populations), then create synthetic observations of it.  Requests:
+ *  - converge: restart a model from LTE and Lambda-iterate it (tolerance,
+ *    iteration limit, Ng order of the request); on success its populations
+ *    are published.  All converge requests in flight share every iteration
+ *    (one batch replay advances all of them: continuous batching); requests
+ *    for one model run one after another in arrival order.
+ *  - render: a synthetic image (as mgx_render_image) of a model's published
+ *    populations (LTE until its first converge completes).  Renders run on
+ *    their own streams, concurrently with the iterations.
+ * Admission: the resident models (geometry, traces, iteration state,
+ * published populations) must fit the HBM budget at mgx_server_start
+ * (MGX_ENOMEM otherwise); a render is admitted to a render slot only while
+ * its estimated device footprint fits what the budget leaves, else it
+ * waits; one that can never fit fails with MGX_ENOMEM.
+ * Threads: one iteration worker and `render_slots` render workers inside
+ * the library; the entry points may be called from any thread.  Results
+ * per request are identical (bit for bit) to the same request run alone.
+ * ---------------------------------------------------------------------- */
+typedef struct mgx_server mgx_server;
+
+enum { MGX_REQ_CONVERGE = 0, MGX_REQ_RENDER = 1 };
+
+typedef struct {
+    int64_t id;
+    int kind;             /* MGX_REQ_CONVERGE or MGX_REQ_RENDER             */
+    int model;
+    int status;           /* mgx_status of the request (MGX_EPENDING: not done) */
+    double t_submit;      /* seconds on the server clock (mgx_server_clock)  */
+    double t_start;       /* admitted / started (-1 if not yet)             */
+    double t_done;        /* finished (-1 if not yet)                       */
+    int iterations;       /* converge: iterations run                       */
+    double change;        /* converge: last max relative change             */
+} mgx_request_info;
+
+typedef struct {
+    int models;
+    int render_slots;
+    int64_t submitted, completed, failed;
+    int64_t replays;          /* batch iterations run                       */
+    int64_t updates;          /* formal-solution point x ray x bin updates  */
+    double iterate_busy_s;    /* wall time the iteration worker was busy    */
+    double render_busy_s;     /* summed wall time of renders                */
+    uint64_t hbm_budget;      /* bytes                                      */
+    uint64_t hbm_resident;    /* bytes held by the resident models          */
+    uint64_t hbm_render_peak; /* peak bytes admitted to render slots        */
+} mgx_server_stats;
+
+/* Create a server on `device`: options for every model, HBM budget in bytes
+   (0: the device's total memory), render slots 1..8. */
+mgx_status mgx_server_create(mgx_server **out, int device, const mgx_options *opt,
+                             uint64_t hbm_budget, int render_slots);
+/* Stop the workers (requests not finished end with MGX_ESTATE) and free. */
+void mgx_server_destroy(mgx_server *s);
+const char *mgx_server_last_error(const mgx_server *s);
+
+/* Copy a model into the resident set (before mgx_server_start). */
+mgx_status mgx_server_add_model(mgx_server *s, const mgx_model *m, int *id_out);
+/* Trace and tabulate every model, publish LTE populations, tune and capture
+   the iteration, check the budget and start the workers. */
+mgx_status mgx_server_start(mgx_server *s);
+/* Seconds since mgx_server_create (the clock of mgx_request_info). */
+double mgx_server_clock(const mgx_server *s);
+
+/* Queue a converge request; *id_out receives its id. */
+mgx_status mgx_server_submit_converge(mgx_server *s, int model, double tol, int max_iter,
+                                      int ng_order, int64_t *id_out);
+/* Queue a render request; img ([npy][npx][nfreq] float, host or device)
+   must stay valid until the request is finished. */
+mgx_status mgx_server_submit_render(mgx_server *s, int model, const double dir[3], int npx,
+                                    int npy, double f_min, double f_max, int nfreq, float *img,
+                                    int64_t *id_out);
+/* Wait up to timeout_s seconds (< 0: no limit) for a request; fills *info
+   (may be NULL).  Returns the request's status, MGX_EPENDING on timeout,
+   MGX_EINVAL for an unknown id. */
+mgx_status mgx_server_wait(mgx_server *s, int64_t id, double timeout_s, mgx_request_info *info);
+/* Published populations of a model ([N][nlev], host or device). */
+mgx_status mgx_server_get_populations(mgx_server *s, int model, double *pops);
+mgx_status mgx_server_get_stats(mgx_server *s, mgx_server_stats *out);
 
 #ifdef __cplusplus
 }

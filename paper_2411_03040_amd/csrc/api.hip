@@ -1,210 +1,16 @@
 // C ABI of the library: context, device memory, model validation and the
 // iteration driver.  All arithmetic of the method runs in the kernels of
-// trace.hip, formal_solve.hip, stateq.hip and ng.hip; this file only moves
-// data, checks arguments and sequences launches on the context's stream.
-
-#include <math.h>
-#include <string.h>
+// trace.hip, formal_solve.hip, stateq.hip, ng.hip and render.hip; this file
+// only moves data, checks arguments and sequences launches on the context's
+// stream.
 
 #include <algorithm>
-#include <functional>
 #include <new>
-#include <string>
 #include <utility>
-#include <vector>
 
-#include "../../include/mgx.h"
-#include "mgx_internal.h"
+#include "host.h"
 
-extern "C" hipError_t mgx_internal_scan(int64_t *counts, int64_t *offsets, int64_t n,
-                                        void **tmp, size_t *tmp_bytes, hipStream_t s);
-
-using namespace mgx;
-
-namespace {
-
-struct Err {
-    mgx_status st;
-    std::string msg;
-};
-
-#define HIPCHK(x)                                                                         \
-    do {                                                                                  \
-        hipError_t e_ = (x);                                                              \
-        if (e_ != hipSuccess)                                                             \
-            throw Err{e_ == hipErrorOutOfMemory ? MGX_ENOMEM : MGX_EHIP,                  \
-                      std::string(#x) + ": " + hipGetErrorString(e_)};                    \
-    } while (0)
-
-#define REQUIRE(cond, code, text)                                                         \
-    do {                                                                                  \
-        if (!(cond)) throw Err{code, text};                                               \
-    } while (0)
-
-// Owning device allocation.
-struct DMem {
-    void *p = nullptr;
-    size_t bytes = 0;
-    DMem() = default;
-    DMem(const DMem &) = delete;
-    DMem &operator=(const DMem &) = delete;
-    ~DMem() { release(); }
-    void release()
-    {
-        if (p) (void)hipFree(p);
-        p = nullptr;
-        bytes = 0;
-    }
-    void ensure(size_t b)
-    {
-        if (b <= bytes && p) return;
-        release();
-        if (b == 0) b = 16;
-        HIPCHK(hipMalloc(&p, b));
-        bytes = b;
-    }
-    template <typename T>
-    T *as() const
-    {
-        return (T *)p;
-    }
-};
-
-struct DeviceGuard {
-    int prev = -1;
-    explicit DeviceGuard(int dev)
-    {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != dev) HIPCHK(hipSetDevice(dev));
-    }
-    ~DeviceGuard()
-    {
-        int cur = -1;
-        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-    }
-};
-
-thread_local std::string g_create_error;
-
-template <typename T>
-bool all_finite(const T *a, size_t n)
-{
-    for (size_t i = 0; i < n; i++)
-        if (!std::isfinite((double)a[i])) return false;
-    return true;
-}
-
-}  // namespace
-
-struct mgx_ctx {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    mgx_options opt{};
-    std::string err;
-
-    // model
-    bool loaded = false, traced = false, have_pops = false, have_rad = false;
-    int dim = 3, N = 0, R = 0, nlev = 0, nlines = 0, ncoll_tr = 0, nbins = 0, npairs = 0;
-    double mass = 0, xmax = 5, Tcmb = 2.72548, L_unit = 1;
-    int64_t n_records = 0;
-
-    DMem pos, vel, nbs_off, nbs, bdy, T, vturb2, nspec, ncoll, ray_dir, ray_w, antipode;
-    DMem E, g, up, lo, A, nu, cu, cl, K0;
-    DMem b2, b, bf, ibf, bd, ibd, xf, W;
-    DMem Bul, Blu, hnu4pi, chiscale, Iref, acmb;
-    DMem pair_r, pair_a, pair_w;
-    DMem pops, pops_new, J, L, S64, chiT, ST;
-    DMem counters;
-    // trace
-    DMem counts, offsets, scan_tmp_owner;
-    void *scan_tmp = nullptr;
-    size_t scan_tmp_bytes = 0;
-    DMem r_idx, r_semi, r_Z, r_dv, r_dx, r_ibb, rec;
-    // Ng
-    bool ng_active = false, ng_have_prev = false;
-    int ng_cap = 0, ng_nh = 0;
-    std::vector<DMem *> ng_y, ng_r;
-    std::vector<DMem *> ng_pool;
-    DMem ng_G, ng_coef, ng_status, ng_partial, ng_pred, ng_prev, ng_bits;
-    // images
-    DMem rg_proj, rg_pix, rg_off, rg_walk, rg_img;
-    // diagnostics
-    mgx_counters host_cnt{};
-    hipEvent_t ev_fs0 = nullptr, ev_fs1 = nullptr;
-    bool fs_pending = false;
-
-    ~mgx_ctx()
-    {
-        for (DMem *m : ng_pool) delete m;
-        if (scan_tmp) (void)hipFree(scan_tmp);
-        if (ev_fs0) (void)hipEventDestroy(ev_fs0);
-        if (ev_fs1) (void)hipEventDestroy(ev_fs1);
-        if (own_stream && stream) (void)hipStreamDestroy(stream);
-    }
-
-    int64_t npop() const { return (int64_t)N * nlev; }
-    int64_t nrad() const { return (int64_t)N * nlines; }
-    bool fp32() const { return opt.precision == MGX_FP32; }
-
-    void sync()
-    {
-        HIPCHK(hipStreamSynchronize(stream));
-        collect_timing();
-    }
-
-    // Duration of the last formal-solution kernel, once its events completed.
-    void collect_timing()
-    {
-        if (!fs_pending) return;
-        float ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&ms, ev_fs0, ev_fs1));
-        fs_pending = false;
-        host_cnt.fs_launches++;
-        host_cnt.fs_ms_total += ms;
-        host_cnt.fs_ms_last = ms;
-    }
-
-    Counters read_counters()
-    {
-        Counters c;
-        HIPCHK(hipMemcpyAsync(&c, counters.p, sizeof(Counters), hipMemcpyDeviceToHost, stream));
-        sync();
-        return c;
-    }
-};
-
-#define API_BEGIN(ctx)                                                                    \
-    if (!(ctx)) return MGX_EINVAL;                                                        \
-    try {                                                                                 \
-        DeviceGuard dg_((ctx)->device);                                                   \
-        (ctx)->err.clear();
-
-#define API_END(ctx)                                                                      \
-    }                                                                                     \
-    catch (const Err &e)                                                                  \
-    {                                                                                     \
-        (ctx)->err = e.msg;                                                               \
-        return e.st;                                                                      \
-    }                                                                                     \
-    catch (const std::bad_alloc &)                                                        \
-    {                                                                                     \
-        (ctx)->err = "host allocation failed";                                            \
-        return MGX_ENOMEM;                                                                \
-    }                                                                                     \
-    catch (...)                                                                           \
-    {                                                                                     \
-        (ctx)->err = "unexpected internal error";                                         \
-        return MGX_EHIP;                                                                  \
-    }                                                                                     \
-    return MGX_OK;
-
-template <typename T>
-static void upload(mgx_ctx *c, DMem &d, const T *src, size_t n)
-{
-    d.ensure(sizeof(T) * n);
-    if (n) HIPCHK(hipMemcpyAsync(d.p, src, sizeof(T) * n, hipMemcpyHostToDevice, c->stream));
-}
+thread_local std::string mgxh::g_create_error;
 
 // ---------------------------------------------------------------------------
 
@@ -652,13 +458,14 @@ extern "C" mgx_status mgx_set_lte_populations(mgx_ctx *ctx)
     API_END(ctx)
 }
 
-static void run_line_coeffs(mgx_ctx *ctx)
+void mgxh::line_coeffs_into(mgx_ctx *ctx, const double *pops, void *chiT, void *ST,
+                            double *S64, Counters *cnt, hipStream_t s)
 {
     LineArgs la{};
     la.N = ctx->N;
     la.nlev = ctx->nlev;
     la.nlines = ctx->nlines;
-    la.pops = ctx->pops.as<double>();
+    la.pops = pops;
     la.nspec = ctx->nspec.as<double>();
     la.b = ctx->b.as<double>();
     la.up = ctx->up.as<int32_t>();
@@ -670,19 +477,25 @@ static void run_line_coeffs(mgx_ctx *ctx)
     la.chiscale = ctx->chiscale.as<double>();
     la.Iref = ctx->Iref.as<double>();
     la.chi_min = ctx->opt.chi_min;
-    la.S64 = ctx->S64.as<double>();
-    la.chiT = ctx->chiT.p;
-    la.ST = ctx->ST.p;
+    la.S64 = S64;
+    la.chiT = chiT;
+    la.ST = ST;
     la.fp32 = ctx->fp32() ? 1 : 0;
-    la.cnt = ctx->counters.as<Counters>();
-    HIPCHK(launch_reset_counters(ctx->counters.as<Counters>(), ctx->stream));
-    HIPCHK(launch_line_coeffs(la, ctx->stream));
+    la.cnt = cnt;
+    HIPCHK(launch_reset_counters(cnt, s));
+    HIPCHK(launch_line_coeffs(la, s));
+}
+
+void mgxh::run_line_coeffs(mgx_ctx *ctx)
+{
+    line_coeffs_into(ctx, ctx->pops.as<double>(), ctx->chiT.p, ctx->ST.p, ctx->S64.as<double>(),
+                     ctx->counters.as<Counters>(), ctx->stream);
 }
 
 // Launch shape of one model's formal solution: lines per chunk (balanced)
 // and threads per workgroup (a multiple of 64 covering nlc * nbins).
 template <typename T>
-static FSArgs<T> fs_args(mgx_ctx *ctx)
+FSArgs<T> mgxh::fs_args(mgx_ctx *ctx)
 {
     FSArgs<T> a{};
     a.N = ctx->N;
@@ -722,6 +535,8 @@ static FSArgs<T> fs_args(mgx_ctx *ctx)
     a.L = ctx->L.as<double>();
     return a;
 }
+template FSArgs<float> mgxh::fs_args<float>(mgx_ctx *);
+template FSArgs<double> mgxh::fs_args<double>(mgx_ctx *);
 
 template <typename T>
 static void run_formal_solve_t(mgx_ctx *ctx)
@@ -788,7 +603,7 @@ static DMem *ng_buffer(mgx_ctx *ctx)
     return m;
 }
 
-static void ng_append(mgx_ctx *ctx)
+void mgxh::ng_append(mgx_ctx *ctx)
 {
     if (ctx->ng_nh == ctx->ng_cap) {  // window full: drop the oldest iterate
         DMem *y0 = ctx->ng_y.front();
@@ -818,7 +633,7 @@ static void ng_restart(mgx_ctx *ctx)
     ctx->ng_have_prev = false;
 }
 
-static StateqArgs stateq_args(mgx_ctx *ctx)
+StateqArgs mgxh::stateq_args(mgx_ctx *ctx)
 {
     StateqArgs s{};
     s.N = ctx->N;
@@ -887,7 +702,7 @@ extern "C" mgx_status mgx_update_populations(mgx_ctx *ctx, double *max_rel_chang
     API_END(ctx)
 }
 
-static void ng_reset(mgx_ctx *ctx, int capacity)
+void mgxh::ng_reset(mgx_ctx *ctx, int capacity)
 {
     REQUIRE(capacity >= 2 && capacity <= kNgMaxHist, MGX_EINVAL, "Ng capacity must be 2..32");
     REQUIRE(ctx->have_pops, MGX_ESTATE, "Ng reset without populations");
@@ -914,7 +729,7 @@ extern "C" mgx_status mgx_ng_reset(mgx_ctx *ctx, int capacity)
 }
 
 // Forms the prediction into ng_prev (when accepted).  Returns 1 accepted.
-static int ng_predict(mgx_ctx *ctx, double *pred_change)
+int mgxh::ng_predict(mgx_ctx *ctx, double *pred_change)
 {
     const int K = ctx->ng_nh - 1;
     *pred_change = INFINITY;
@@ -947,7 +762,7 @@ static int ng_predict(mgx_ctx *ctx, double *pred_change)
     return ok ? 1 : 0;
 }
 
-static void ng_apply(mgx_ctx *ctx, bool accepted)
+void mgxh::ng_apply(mgx_ctx *ctx, bool accepted)
 {
     if (accepted) {
         HIPCHK(launch_copy(ctx->npop(), ctx->ng_prev.as<double>(), ctx->pops.as<double>(),
@@ -1084,13 +899,10 @@ static void render_basis(const double dir[3], double d[3], double e1[3], double 
     e2[2] = d[0] * e1[1] - d[1] * e1[0];
 }
 
-extern "C" mgx_status mgx_render_image(mgx_ctx *ctx, const double dir[3], int npx, int npy,
-                                       double f_min, double f_max, int nfreq, float *img)
+void mgxh::check_render_args(const double dir[3], int npx, int npy, double f_min, double f_max,
+                             int nfreq)
 {
-    API_BEGIN(ctx)
-    REQUIRE(ctx->loaded && ctx->have_pops, MGX_ESTATE, "mgx_render_image needs a model and populations");
-    REQUIRE(ctx->dim == 3, MGX_EINVAL, "mgx_render_image supports point clouds (dim 3)");
-    REQUIRE(dir && img, MGX_EINVAL, "dir / img is NULL");
+    REQUIRE(dir, MGX_EINVAL, "dir is NULL");
     REQUIRE(std::isfinite(dir[0]) && std::isfinite(dir[1]) && std::isfinite(dir[2]) &&
                 (dir[0] != 0.0 || dir[1] != 0.0 || dir[2] != 0.0),
             MGX_EINVAL, "dir must be finite and non-zero");
@@ -1099,8 +911,20 @@ extern "C" mgx_status mgx_render_image(mgx_ctx *ctx, const double dir[3], int np
     REQUIRE(nfreq >= 1 && nfreq <= 1024, MGX_EINVAL, "nfreq must be 1..1024");
     REQUIRE(f_min > 0 && f_max >= f_min && std::isfinite(f_max), MGX_EINVAL,
             "need 0 < f_min <= f_max");
-    run_line_coeffs(ctx);
+}
+
+void mgxh::render_image(mgx_ctx *ctx, RenderBufs &rb, const double *pops, hipStream_t s,
+                        const double dir[3], int npx, int npy, double f_min, double f_max,
+                        int nfreq, float *img)
+{
     const int N = ctx->N;
+    const size_t tsz = ctx->fp32() ? sizeof(float) : sizeof(double);
+    rb.chiT.ensure(tsz * ctx->nrad());
+    rb.ST.ensure(tsz * ctx->nrad());
+    rb.S64.ensure(sizeof(double) * ctx->nrad());
+    rb.cnt.ensure(sizeof(Counters));
+    line_coeffs_into(ctx, pops, rb.chiT.p, rb.ST.p, rb.S64.as<double>(), rb.cnt.as<Counters>(),
+                     s);
     const int64_t npix = (int64_t)npx * npy;
     RenderGeom g{};
     g.N = N;
@@ -1118,31 +942,30 @@ extern "C" mgx_status mgx_render_image(mgx_ctx *ctx, const double dir[3], int np
     g.nbs_off = ctx->nbs_off.as<int32_t>();
     g.nbs = ctx->nbs.as<int32_t>();
     g.bdy = ctx->bdy.as<uint8_t>();
-    ctx->rg_proj.ensure(sizeof(double) * 4 * (size_t)N + sizeof(double) * 4);
-    g.u = ctx->rg_proj.as<double>();
+    rb.proj.ensure(sizeof(double) * 4 * (size_t)N + sizeof(double) * 4);
+    g.u = rb.proj.as<double>();
     g.v = g.u + N;
     g.Z = g.v + N;
     g.w = g.Z + N;
     g.ext = g.w + N;
-    ctx->rg_pix.ensure((sizeof(unsigned long long) + sizeof(int32_t)) * npix + 16);
-    g.key = ctx->rg_pix.as<unsigned long long>();
+    rb.pix.ensure((sizeof(unsigned long long) + sizeof(int32_t)) * npix + 16);
+    g.key = rb.pix.as<unsigned long long>();
     g.entry = (int32_t *)(g.key + npix);
-    ctx->rg_off.ensure(sizeof(int64_t) * 2 * (npix + 1));
-    g.counts = ctx->rg_off.as<int64_t>();
+    rb.off.ensure(sizeof(int64_t) * 2 * (npix + 1));
+    g.counts = rb.off.as<int64_t>();
     int64_t *off = g.counts + (npix + 1);
-    HIPCHK(hipMemsetAsync(g.counts, 0, sizeof(int64_t) * (npix + 1), ctx->stream));
-    HIPCHK(launch_render_geometry(g, ctx->stream));
-    HIPCHK(launch_render_walk(g, false, ctx->stream));
-    HIPCHK(mgx_internal_scan(g.counts, off, npix + 1, &ctx->scan_tmp, &ctx->scan_tmp_bytes,
-                             ctx->stream));
+    HIPCHK(hipMemsetAsync(g.counts, 0, sizeof(int64_t) * (npix + 1), s));
+    HIPCHK(launch_render_geometry(g, s));
+    HIPCHK(launch_render_walk(g, false, s));
+    HIPCHK(mgx_internal_scan(g.counts, off, npix + 1, &rb.scan_tmp, &rb.scan_tmp_bytes, s));
     int64_t total = 0;
-    HIPCHK(hipMemcpyAsync(&total, off + npix, sizeof(int64_t), hipMemcpyDeviceToHost, ctx->stream));
-    ctx->sync();
-    ctx->rg_walk.ensure(sizeof(int32_t) * (size_t)(total > 0 ? total : 1));
+    HIPCHK(hipMemcpyAsync(&total, off + npix, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    rb.walk.ensure(sizeof(int32_t) * (size_t)(total > 0 ? total : 1));
     g.off = off;
-    g.walk = ctx->rg_walk.as<int32_t>();
-    HIPCHK(launch_render_walk(g, true, ctx->stream));
-    ctx->rg_img.ensure(sizeof(float) * (size_t)npix * nfreq);
+    g.walk = rb.walk.as<int32_t>();
+    HIPCHK(launch_render_walk(g, true, s));
+    rb.img.ensure(sizeof(float) * (size_t)npix * nfreq);
     const double I_img = 2.0 * kH * pow(0.5 * (f_min + f_max), 3) / (kC * kC);
     auto fill_args = [&](auto &ra) {
         ra.npx = npx;
@@ -1164,541 +987,55 @@ extern "C" mgx_status mgx_render_image(mgx_ctx *ctx, const double dir[3], int np
         ra.I_img = I_img;
         ra.thr = ctx->opt.branch_threshold;
         ra.b2 = ctx->b2.as<double>();
-        ra.img = ctx->rg_img.as<float>();
+        ra.img = rb.img.as<float>();
     };
     if (ctx->fp32()) {
         RenderArgs<float> ra{};
         fill_args(ra);
-        ra.chi = (const float *)ctx->chiT.p;
-        ra.S = (const float *)ctx->ST.p;
-        HIPCHK(launch_render_integrate<float>(ra, ctx->stream));
+        ra.chi = (const float *)rb.chiT.p;
+        ra.S = (const float *)rb.ST.p;
+        HIPCHK(launch_render_integrate<float>(ra, s));
     } else {
         RenderArgs<double> ra{};
         fill_args(ra);
-        ra.chi = (const double *)ctx->chiT.p;
-        ra.S = (const double *)ctx->ST.p;
-        HIPCHK(launch_render_integrate<double>(ra, ctx->stream));
+        ra.chi = (const double *)rb.chiT.p;
+        ra.S = (const double *)rb.ST.p;
+        HIPCHK(launch_render_integrate<double>(ra, s));
     }
-    HIPCHK(hipMemcpyAsync(img, ctx->rg_img.p, sizeof(float) * (size_t)npix * nfreq,
-                          hipMemcpyDefault, ctx->stream));
+    HIPCHK(hipMemcpyAsync(img, rb.img.p, sizeof(float) * (size_t)npix * nfreq, hipMemcpyDefault,
+                          s));
+    HIPCHK(hipStreamSynchronize(s));
+}
+
+extern "C" mgx_status mgx_render_image(mgx_ctx *ctx, const double dir[3], int npx, int npy,
+                                       double f_min, double f_max, int nfreq, float *img)
+{
+    API_BEGIN(ctx)
+    REQUIRE(ctx->loaded && ctx->have_pops, MGX_ESTATE, "mgx_render_image needs a model and populations");
+    REQUIRE(ctx->dim == 3, MGX_EINVAL, "mgx_render_image supports point clouds (dim 3)");
+    REQUIRE(img, MGX_EINVAL, "img is NULL");
+    check_render_args(dir, npx, npy, f_min, f_max, nfreq);
     ctx->sync();
+    render_image(ctx, ctx->rb, ctx->pops.as<double>(), ctx->stream, dir, npx, npy, f_min, f_max,
+                 nfreq, img);
     API_END(ctx)
 }
 
-// ---------------------------------------------------------------------------
-// Batches
-// ---------------------------------------------------------------------------
-
-struct mgx_batch {
-    int device = 0;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    mgx_options opt{};
-    std::string err;
-    std::vector<mgx_ctx *> m;
-    bool prepared = false, tuned = false;
-    // device tables
-    DMem descs, active, changes, cnt_ptrs, counts, tune_count;
-    // work items per class: every item in longest-first order, and the items
-    // of the models still iterating (same order; *counts[k] of them)
-    DMem items_all[MGX_BATCH_CLASSES], items[MGX_BATCH_CLASSES];
-    DMem sample[MGX_BATCH_CLASSES];  // strided sample of the items, for tuning
-    int class_nsample[MGX_BATCH_CLASSES] = {};
-    void *select_tmp = nullptr;
-    size_t select_tmp_bytes = 0;
-    int nclass = 0;
-    // lane class k: workgroups of 64 (k + 1) threads
-    int class_threads[MGX_BATCH_CLASSES] = {};
-    int class_nitems[MGX_BATCH_CLASSES] = {};
-    int class_nlc_max[MGX_BATCH_CLASSES] = {};
-    int class_ch[MGX_BATCH_CLASSES] = {};
-    int64_t work_items = 0;
-    std::vector<int> host_active;
-    // one iteration as three captured graphs: line coefficients, formal
-    // solution (timed with events between the launches), populations
-    hipGraph_t graph[3] = {nullptr, nullptr, nullptr};
-    hipGraphExec_t gexec[3] = {nullptr, nullptr, nullptr};
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    mgx_batch_stats st{};
-
-    ~mgx_batch()
-    {
-        if (stream) (void)hipStreamSynchronize(stream);
-        for (int i = 0; i < 3; i++) {
-            if (gexec[i]) (void)hipGraphExecDestroy(gexec[i]);
-            if (graph[i]) (void)hipGraphDestroy(graph[i]);
-        }
-        for (mgx_ctx *c : m) delete c;
-        if (ev0) (void)hipEventDestroy(ev0);
-        if (ev1) (void)hipEventDestroy(ev1);
-        if (select_tmp) (void)hipFree(select_tmp);
-        if (own_stream && stream) (void)hipStreamDestroy(stream);
-    }
-    bool fp32() const { return opt.precision == MGX_FP32; }
-    void sync() { HIPCHK(hipStreamSynchronize(stream)); }
-};
-
-#define BATCH_BEGIN(b)                                                                    \
-    if (!(b)) return MGX_EINVAL;                                                          \
-    try {                                                                                 \
-        DeviceGuard dg_((b)->device);                                                     \
-        (b)->err.clear();
-
-#define BATCH_END(b)                                                                      \
-    }                                                                                     \
-    catch (const Err &e)                                                                  \
-    {                                                                                     \
-        (b)->err = e.msg;                                                                 \
-        return e.st;                                                                      \
-    }                                                                                     \
-    catch (const std::bad_alloc &)                                                        \
-    {                                                                                     \
-        (b)->err = "host allocation failed";                                              \
-        return MGX_ENOMEM;                                                                \
-    }                                                                                     \
-    catch (...)                                                                           \
-    {                                                                                     \
-        (b)->err = "unexpected internal error";                                           \
-        return MGX_EHIP;                                                                  \
-    }                                                                                     \
-    return MGX_OK;
-
-static void check_sub(mgx_batch *b, mgx_ctx *c, mgx_status st)
+size_t mgxh::ctx_bytes(const mgx_ctx *c)
 {
-    if (st != MGX_OK) throw Err{st, c->err};
-    (void)b;
+    const DMem *all[] = {&c->pos, &c->vel, &c->nbs_off, &c->nbs, &c->bdy, &c->T, &c->vturb2,
+                         &c->nspec, &c->ncoll, &c->ray_dir, &c->ray_w, &c->antipode, &c->E,
+                         &c->g, &c->up, &c->lo, &c->A, &c->nu, &c->cu, &c->cl, &c->K0, &c->b2,
+                         &c->b, &c->bf, &c->ibf, &c->bd, &c->ibd, &c->xf, &c->W, &c->Bul,
+                         &c->Blu, &c->hnu4pi, &c->chiscale, &c->Iref, &c->acmb, &c->pair_r,
+                         &c->pair_a, &c->pair_w, &c->pops, &c->pops_new, &c->J, &c->L, &c->S64,
+                         &c->chiT, &c->ST, &c->counters, &c->counts, &c->offsets, &c->r_idx,
+                         &c->r_semi, &c->r_Z, &c->r_dv, &c->r_dx, &c->r_ibb, &c->rec, &c->ng_G,
+                         &c->ng_coef, &c->ng_status, &c->ng_partial, &c->ng_pred, &c->ng_prev,
+                         &c->ng_bits};
+    size_t n = c->scan_tmp_bytes + c->rb.bytes();
+    for (const DMem *m : all) n += m->bytes;
+    for (const DMem *m : c->ng_pool) n += m->bytes;
+    return n;
 }
 
-extern "C" mgx_status mgx_batch_create(mgx_batch **out, int device, void *stream,
-                                       const mgx_options *opt)
-{
-    g_create_error.clear();
-    if (!out) return MGX_EINVAL;
-    *out = nullptr;
-    int ndev = 0;
-    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
-        g_create_error = "no such HIP device";
-        return MGX_EINVAL;
-    }
-    mgx_options o;
-    mgx_default_options(&o);
-    if (opt) o = *opt;
-    mgx_batch *b = new (std::nothrow) mgx_batch();
-    if (!b) return MGX_ENOMEM;
-    b->device = device;
-    b->opt = o;
-    try {
-        DeviceGuard dg(device);
-        if (stream) {
-            b->stream = (hipStream_t)stream;
-        } else {
-            HIPCHK(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
-            b->own_stream = true;
-        }
-        HIPCHK(hipEventCreate(&b->ev0));
-        HIPCHK(hipEventCreate(&b->ev1));
-    } catch (const Err &e) {
-        g_create_error = e.msg;
-        delete b;
-        return e.st;
-    }
-    *out = b;
-    return MGX_OK;
-}
-
-extern "C" void mgx_batch_destroy(mgx_batch *b)
-{
-    if (!b) return;
-    int prev = -1;
-    (void)hipGetDevice(&prev);
-    (void)hipSetDevice(b->device);
-    delete b;
-    if (prev >= 0) (void)hipSetDevice(prev);
-}
-
-extern "C" const char *mgx_batch_last_error(const mgx_batch *b)
-{
-    if (!b) return g_create_error.c_str();
-    return b->err.c_str();
-}
-
-extern "C" mgx_status mgx_batch_add_model(mgx_batch *b, const mgx_model *model, int *id_out)
-{
-    BATCH_BEGIN(b)
-    REQUIRE(!b->prepared, MGX_ESTATE, "mgx_batch_add_model after mgx_batch_prepare");
-    mgx_ctx *c = nullptr;
-    const mgx_status st = mgx_create(&c, b->device, b->stream, &b->opt);
-    if (st != MGX_OK) throw Err{st, g_create_error};
-    const mgx_status ls = mgx_load_model(c, model);
-    if (ls != MGX_OK) {
-        Err e{ls, c->err};
-        delete c;
-        throw e;
-    }
-    b->m.push_back(c);
-    if (id_out) *id_out = (int)b->m.size() - 1;
-    BATCH_END(b)
-}
-
-template <typename T>
-static void batch_build_tables(mgx_batch *b)
-{
-    const int M = (int)b->m.size();
-    std::vector<FSArgs<T>> d(M);
-    std::vector<std::vector<std::pair<int64_t, int4>>> cls(MGX_BATCH_CLASSES);
-    DMem cost;
-    for (int k = 0; k < MGX_BATCH_CLASSES; k++) {
-        b->class_threads[k] = 64 * (k + 1);
-        b->class_nlc_max[k] = 0;
-        b->class_ch[k] = 64;
-    }
-    for (int i = 0; i < M; i++) {
-        mgx_ctx *c = b->m[i];
-        d[i] = fs_args<T>(c);
-        // a model's workgroup size is a multiple of 64 up to 1024
-        const int k = d[i].nthreads / 64 - 1;
-        b->class_nlc_max[k] = std::max(b->class_nlc_max[k], d[i].nlc);
-        cost.ensure(sizeof(int64_t) * c->N);
-        HIPCHK(launch_origin_cost(c->N, c->R, c->offsets.as<int64_t>(), cost.as<int64_t>(),
-                                  b->stream));
-        std::vector<int64_t> hc(c->N);
-        HIPCHK(hipMemcpyAsync(hc.data(), cost.p, sizeof(int64_t) * c->N, hipMemcpyDeviceToHost,
-                              b->stream));
-        b->sync();
-        const int nchunks = (c->nlines + d[i].nlc - 1) / d[i].nlc;
-        const int64_t lanes = (int64_t)d[i].nlc * c->nbins;
-        for (int o = 0; o < c->N; o++)
-            for (int ch = 0; ch < nchunks; ch++)
-                cls[k].push_back({(hc[o] + c->npairs) * lanes, make_int4(i, o, ch, 0)});
-    }
-    upload(b->m[0], b->descs, d.data(), d.size());
-    b->st.updates_per_iteration = b->st.lane_records = b->st.lane_semi = 0;
-    b->st.lane_origin_pairs = 0;
-    for (mgx_ctx *c : b->m) {
-        const int64_t lanes = (int64_t)c->nlines * c->nbins;
-        b->st.updates_per_iteration += (int64_t)c->N * c->R * lanes;
-        b->st.lane_records += lanes * c->host_cnt.total_records;
-        b->st.lane_semi += lanes * c->host_cnt.semi_segments;
-        b->st.lane_origin_pairs += lanes * c->N * c->npairs;
-    }
-    b->work_items = 0;
-    b->nclass = 0;
-    for (int k = 0; k < MGX_BATCH_CLASSES; k++) {
-        auto &v = cls[k];
-        std::stable_sort(v.begin(), v.end(),
-                         [](const std::pair<int64_t, int4> &x, const std::pair<int64_t, int4> &y) {
-                             return x.first > y.first;
-                         });
-        std::vector<int4> it(v.size());
-        for (size_t j = 0; j < v.size(); j++) it[j] = v[j].second;
-        b->class_nitems[k] = (int)it.size();
-        b->work_items += (int64_t)it.size();
-        if (!it.empty()) b->nclass++;
-        upload(b->m[0], b->items_all[k], it.data(), it.size());
-        b->items[k].ensure(sizeof(int4) * std::max<size_t>(1, it.size()));
-        const size_t stride = it.size() >= 32768 ? 8 : 1;
-        std::vector<int4> smp;
-        for (size_t j = 0; j < it.size(); j += stride) smp.push_back(it[j]);
-        b->class_nsample[k] = (int)smp.size();
-        upload(b->m[0], b->sample[k], smp.data(), smp.size());
-    }
-    b->counts.ensure(sizeof(int) * MGX_BATCH_CLASSES);
-    b->tune_count.ensure(sizeof(int));
-    b->sync();
-}
-
-extern "C" mgx_status mgx_batch_prepare(mgx_batch *b)
-{
-    BATCH_BEGIN(b)
-    REQUIRE(!b->m.empty(), MGX_ESTATE, "mgx_batch_prepare on an empty batch");
-    REQUIRE(!b->prepared, MGX_ESTATE, "batch already prepared");
-    const int M = (int)b->m.size();
-    for (mgx_ctx *c : b->m) {
-        check_sub(b, c, mgx_trace_rays(c, nullptr));
-        // iterations read only the packed records: drop the raw trace
-        c->r_idx.release();
-        c->r_semi.release();
-        c->r_Z.release();
-        c->r_dv.release();
-        c->r_dx.release();
-        c->r_ibb.release();
-        c->counts.release();
-    }
-    if (b->fp32())
-        batch_build_tables<float>(b);
-    else
-        batch_build_tables<double>(b);
-    std::vector<Counters *> cp(M);
-    for (int i = 0; i < M; i++) cp[i] = b->m[i]->counters.as<Counters>();
-    upload(b->m[0], b->cnt_ptrs, cp.data(), cp.size());
-    b->host_active.assign(M, 1);
-    upload(b->m[0], b->active, b->host_active.data(), (size_t)M);
-    b->changes.ensure(sizeof(double) * 2 * M);
-    b->sync();
-    b->prepared = true;
-    BATCH_END(b)
-}
-
-extern "C" mgx_status mgx_batch_set_lte_populations(mgx_batch *b)
-{
-    BATCH_BEGIN(b)
-    for (mgx_ctx *c : b->m) check_sub(b, c, mgx_set_lte_populations(c));
-    BATCH_END(b)
-}
-
-extern "C" mgx_status mgx_batch_set_populations(mgx_batch *b, int id, const double *pops)
-{
-    BATCH_BEGIN(b)
-    REQUIRE(id >= 0 && id < (int)b->m.size(), MGX_EINVAL, "model id out of range");
-    check_sub(b, b->m[id], mgx_set_populations(b->m[id], pops));
-    BATCH_END(b)
-}
-
-extern "C" mgx_status mgx_batch_get_populations(mgx_batch *b, int id, double *pops)
-{
-    BATCH_BEGIN(b)
-    REQUIRE(id >= 0 && id < (int)b->m.size(), MGX_EINVAL, "model id out of range");
-    check_sub(b, b->m[id], mgx_get_populations(b->m[id], pops));
-    BATCH_END(b)
-}
-
-// All items of every class in play again (start of an iterate call).
-static void batch_restore_items(mgx_batch *b)
-{
-    for (int k = 0; k < MGX_BATCH_CLASSES; k++)
-        if (b->class_nitems[k])
-            HIPCHK(hipMemcpyAsync(b->items[k].p, b->items_all[k].p,
-                                  sizeof(int4) * b->class_nitems[k], hipMemcpyDeviceToDevice,
-                                  b->stream));
-    HIPCHK(hipMemcpyAsync(b->counts.p, b->class_nitems, sizeof(int) * MGX_BATCH_CLASSES,
-                          hipMemcpyHostToDevice, b->stream));
-    b->sync();
-}
-
-// Keep only the items of models still iterating (after the mask changed).
-static void batch_compact_items(mgx_batch *b)
-{
-    for (int k = 0; k < MGX_BATCH_CLASSES; k++)
-        if (b->class_nitems[k])
-            HIPCHK(launch_compact_items(b->items_all[k].as<int4>(), b->class_nitems[k],
-                                        b->items[k].as<int4>(), b->counts.as<int>() + k,
-                                        b->active.as<int>(), &b->select_tmp,
-                                        &b->select_tmp_bytes, b->stream));
-}
-
-template <typename T>
-static void batch_launch_class(mgx_batch *b, int k, const int4 *items, const int *count,
-                               int blocks, int ch)
-{
-    const size_t lds = formal_solve_lds<T>(ch, b->class_nlc_max[k], b->class_threads[k]);
-    HIPCHK(launch_formal_solve_batch<T>((const FSArgs<T> *)b->descs.p, items, count, blocks,
-                                        b->active.as<int>(), ch, b->class_threads[k], lds,
-                                        b->stream));
-}
-
-// Schedule tuning: per lane class, time each LDS chunk size (records staged
-// per half-ray) on a strided sample of the class's items and keep the
-// fastest.
-template <typename T>
-static void batch_tune(mgx_batch *b)
-{
-    for (int k = 0; k < MGX_BATCH_CLASSES; k++) {
-        const int n = b->class_nitems[k];
-        if (n == 0) continue;
-        const int nlc = b->class_nlc_max[k], nth = b->class_threads[k];
-        // the largest chunk that fits 60 KB (at least 8, as the single-model
-        // launch does) and every smaller candidate
-        int chmax = 64;
-        while (formal_solve_lds<T>(chmax, nlc, nth) > 60 * 1024 && chmax > 8) chmax /= 2;
-        REQUIRE(formal_solve_lds<T>(chmax, nlc, nth) <= 160 * 1024, MGX_EINVAL,
-                "line chunk does not fit the LDS");
-        const int ns = b->class_nsample[k];
-        HIPCHK(hipMemcpyAsync(b->tune_count.p, &ns, sizeof(int), hipMemcpyHostToDevice,
-                              b->stream));
-        float best = INFINITY;
-        for (int ch : {8, 16, 32, 64}) {
-            if (ch > chmax || (ch == 8 && chmax > 8)) continue;
-            HIPCHK(hipEventRecord(b->ev0, b->stream));
-            batch_launch_class<T>(b, k, b->sample[k].as<int4>(), b->tune_count.as<int>(), ns, ch);
-            HIPCHK(hipEventRecord(b->ev1, b->stream));
-            b->sync();
-            float ms = 0.f;
-            HIPCHK(hipEventElapsedTime(&ms, b->ev0, b->ev1));
-            if (ms < best) {
-                best = ms;
-                b->class_ch[k] = ch;
-            }
-        }
-    }
-}
-
-// One Lambda-iteration of every model, captured once as three HIP graphs.
-static void batch_capture_part(mgx_batch *b, int part, const std::function<void()> &body)
-{
-    HIPCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-    try {
-        body();
-    } catch (...) {
-        hipGraph_t g = nullptr;
-        (void)hipStreamEndCapture(b->stream, &g);
-        if (g) (void)hipGraphDestroy(g);
-        throw;
-    }
-    HIPCHK(hipStreamEndCapture(b->stream, &b->graph[part]));
-    HIPCHK(hipGraphInstantiate(&b->gexec[part], b->graph[part], nullptr, nullptr, 0));
-}
-
-template <typename T>
-static void batch_capture(mgx_batch *b)
-{
-    const int M = (int)b->m.size();
-    batch_capture_part(b, 0, [&]() {
-        for (mgx_ctx *c : b->m) run_line_coeffs(c);
-    });
-    batch_capture_part(b, 1, [&]() {
-        for (int k = 0; k < MGX_BATCH_CLASSES; k++)
-            if (b->class_nitems[k])
-                batch_launch_class<T>(b, k, b->items[k].as<int4>(), b->counts.as<int>() + k,
-                                      b->class_nitems[k], b->class_ch[k]);
-    });
-    batch_capture_part(b, 2, [&]() {
-        for (int i = 0; i < M; i++) {
-            mgx_ctx *c = b->m[i];
-            StateqArgs s = stateq_args(c);
-            s.active = b->active.as<int>();
-            s.model = i;
-            HIPCHK(launch_reset_counters(c->counters.as<Counters>(), b->stream));
-            HIPCHK(launch_stateq(s, b->stream));
-            HIPCHK(launch_copy_if_active(c->npop(), c->pops_new.as<double>(), c->pops.as<double>(),
-                                         b->active.as<int>(), i, b->stream));
-        }
-        HIPCHK(launch_gather_changes(M, b->cnt_ptrs.as<Counters *>(), b->changes.as<double>(),
-                                     b->stream));
-    });
-}
-
-extern "C" mgx_status mgx_batch_iterate(mgx_batch *b, double tol, int max_iter, int ng_order,
-                                        int *iters, double *changes, int *converged_out)
-{
-    BATCH_BEGIN(b)
-    REQUIRE(b->prepared, MGX_ESTATE, "mgx_batch_iterate before mgx_batch_prepare");
-    REQUIRE(max_iter >= 1 && tol >= 0, MGX_EINVAL, "max_iter >= 1 and tol >= 0 required");
-    REQUIRE(ng_order >= 0 && ng_order + 1 <= kNgMaxHist, MGX_EINVAL, "Ng order must be 0..31");
-    const int M = (int)b->m.size();
-    for (mgx_ctx *c : b->m) REQUIRE(c->have_pops, MGX_ESTATE, "batch model without populations");
-    auto wall = []() {
-        struct timespec ts;
-        clock_gettime(CLOCK_MONOTONIC, &ts);
-        return ts.tv_sec + 1e-9 * ts.tv_nsec;
-    };
-    batch_restore_items(b);
-    if (!b->tuned) {
-        const double t0 = wall();
-        for (mgx_ctx *c : b->m) run_line_coeffs(c);
-        if (b->fp32())
-            batch_tune<float>(b);
-        else
-            batch_tune<double>(b);
-        b->st.tune_seconds = wall() - t0;
-        if (b->fp32())
-            batch_capture<float>(b);
-        else
-            batch_capture<double>(b);
-        b->tuned = true;
-    }
-    const double t0 = wall();
-    b->st.fs_launches = 0;
-    b->st.fs_ms_total = b->st.fs_ms_last = 0.0;
-    for (mgx_ctx *c : b->m) {
-        c->ng_active = false;
-        if (ng_order > 0) ng_reset(c, ng_order + 1);
-    }
-    b->host_active.assign(M, 1);
-    HIPCHK(hipMemcpyAsync(b->active.p, b->host_active.data(), sizeof(int) * M,
-                          hipMemcpyHostToDevice, b->stream));
-    std::vector<double> ch(M, INFINITY);
-    std::vector<int> its(M, 0);
-    int n_active = M, it = 0;
-    mgx_status result = MGX_OK;
-    for (it = 1; it <= max_iter && n_active > 0; it++) {
-        HIPCHK(hipGraphLaunch(b->gexec[0], b->stream));
-        HIPCHK(hipEventRecord(b->ev0, b->stream));
-        HIPCHK(hipGraphLaunch(b->gexec[1], b->stream));
-        HIPCHK(hipEventRecord(b->ev1, b->stream));
-        HIPCHK(hipGraphLaunch(b->gexec[2], b->stream));
-        std::vector<double> hc(2 * M);
-        HIPCHK(hipMemcpyAsync(hc.data(), b->changes.p, sizeof(double) * 2 * M,
-                              hipMemcpyDeviceToHost, b->stream));
-        b->sync();
-        float fs_ms = 0.f;
-        HIPCHK(hipEventElapsedTime(&fs_ms, b->ev0, b->ev1));
-        b->st.fs_ms_last = fs_ms;
-        b->st.fs_ms_total += fs_ms;
-        b->st.fs_launches++;
-        bool mask_changed = false;
-        for (int i = 0; i < M; i++) {
-            if (!b->host_active[i]) continue;
-            its[i] = it;
-            ch[i] = hc[i];
-            const bool failed = hc[M + i] != 0.0 || !std::isfinite(hc[i]);
-            if (failed && result == MGX_OK) {
-                const bool sing = hc[M + i] == 1.0;
-                result = sing ? MGX_ESINGULAR : MGX_ENONFINITE;
-                b->err = std::string(sing ? "singular statistical equilibrium"
-                                          : "non-finite populations") +
-                         " in model " + std::to_string(i);
-            }
-            if (hc[i] <= tol || failed) {
-                b->host_active[i] = 0;
-                mask_changed = true;
-                n_active--;
-                continue;
-            }
-            if (ng_order > 0) {
-                mgx_ctx *c = b->m[i];
-                ng_append(c);
-                if (c->ng_nh == ng_order + 1) {
-                    double pc;
-                    ng_apply(c, ng_predict(c, &pc) != 0);
-                }
-            }
-        }
-        if (mask_changed) {
-            HIPCHK(hipMemcpyAsync(b->active.p, b->host_active.data(), sizeof(int) * M,
-                                  hipMemcpyHostToDevice, b->stream));
-            if (n_active > 0) batch_compact_items(b);
-        }
-    }
-    b->sync();
-    for (mgx_ctx *c : b->m) c->ng_active = false;
-    b->st.iterate_seconds = wall() - t0;
-    b->st.iterations = it - 1;
-    b->st.active = n_active;
-    if (iters)
-        for (int i = 0; i < M; i++) iters[i] = its[i];
-    if (changes)
-        for (int i = 0; i < M; i++) changes[i] = ch[i];
-    if (converged_out) *converged_out = M - n_active;
-    if (result == MGX_OK && n_active > 0) {
-        result = MGX_ENOCONV;
-        b->err = std::to_string(n_active) + " model(s) did not converge within max_iter";
-    }
-    if (result != MGX_OK) return result;
-    BATCH_END(b)
-}
-
-extern "C" mgx_status mgx_batch_get_stats(mgx_batch *b, mgx_batch_stats *out)
-{
-    BATCH_BEGIN(b)
-    REQUIRE(out, MGX_EINVAL, "out is NULL");
-    b->st.models = (int)b->m.size();
-    b->st.lane_classes = b->nclass;
-    b->st.work_items = b->work_items;
-    for (int k = 0; k < MGX_BATCH_CLASSES; k++) {
-        b->st.class_items[k] = b->class_nitems[k];
-        b->st.class_threads[k] = b->class_nitems[k] ? b->class_threads[k] : 0;
-        b->st.class_chunk[k] = b->class_nitems[k] ? b->class_ch[k] : 0;
-    }
-    *out = b->st;
-    BATCH_END(b)
-}

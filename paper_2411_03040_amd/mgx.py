@@ -19,12 +19,13 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmgx.so")
 
 MGX_OK, MGX_EINVAL, MGX_ESTATE, MGX_ENOMEM, MGX_EHIP = 0, -1, -2, -3, -4
-MGX_ENOCONV, MGX_ESINGULAR, MGX_ENONFINITE = -5, -6, -7
+MGX_ENOCONV, MGX_ESINGULAR, MGX_ENONFINITE, MGX_EPENDING = -5, -6, -7, -8
 FP64, FP32 = 0, 1
 NG_NONE, NG_CLASSICAL, NG_ADAPTIVE = 0, 1, 2
 
 _STATUS = {0: "MGX_OK", -1: "MGX_EINVAL", -2: "MGX_ESTATE", -3: "MGX_ENOMEM", -4: "MGX_EHIP",
-           -5: "MGX_ENOCONV", -6: "MGX_ESINGULAR", -7: "MGX_ENONFINITE"}
+           -5: "MGX_ENOCONV", -6: "MGX_ESINGULAR", -7: "MGX_ENONFINITE", -8: "MGX_EPENDING"}
+REQ_CONVERGE, REQ_RENDER = 0, 1
 
 
 class MgxError(RuntimeError):
@@ -62,6 +63,20 @@ class BatchStats(C.Structure):
                 ("lane_records", C.c_int64), ("lane_semi", C.c_int64),
                 ("lane_origin_pairs", C.c_int64), ("fs_launches", C.c_int64),
                 ("fs_ms_total", C.c_double), ("fs_ms_last", C.c_double)]
+
+
+class RequestInfo(C.Structure):
+    _fields_ = [("id", C.c_int64), ("kind", C.c_int), ("model", C.c_int), ("status", C.c_int),
+                ("t_submit", C.c_double), ("t_start", C.c_double), ("t_done", C.c_double),
+                ("iterations", C.c_int), ("change", C.c_double)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("models", C.c_int), ("render_slots", C.c_int), ("submitted", C.c_int64),
+                ("completed", C.c_int64), ("failed", C.c_int64), ("replays", C.c_int64),
+                ("updates", C.c_int64), ("iterate_busy_s", C.c_double),
+                ("render_busy_s", C.c_double), ("hbm_budget", C.c_uint64),
+                ("hbm_resident", C.c_uint64), ("hbm_render_peak", C.c_uint64)]
 
 
 class Counters(C.Structure):
@@ -122,6 +137,17 @@ def lib():
         "mgx_batch_get_populations": (I, [P, I, P]),
         "mgx_batch_iterate": (I, [P, D, I, I, P, P, P]),
         "mgx_batch_get_stats": (I, [P, P]),
+        "mgx_server_create": (I, [P, I, P, C.c_uint64, I]),
+        "mgx_server_destroy": (None, [P]),
+        "mgx_server_last_error": (C.c_char_p, [P]),
+        "mgx_server_add_model": (I, [P, P, P]),
+        "mgx_server_start": (I, [P]),
+        "mgx_server_clock": (D, [P]),
+        "mgx_server_submit_converge": (I, [P, I, D, I, I, P]),
+        "mgx_server_submit_render": (I, [P, I, P, I, I, D, D, I, P, P]),
+        "mgx_server_wait": (I, [P, I64, D, P]),
+        "mgx_server_get_populations": (I, [P, I, P]),
+        "mgx_server_get_stats": (I, [P, P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)
@@ -417,6 +443,99 @@ class Batch:
             v = getattr(s, k)
             out[k] = list(v) if not isinstance(v, (int, float)) else v
         return out
+
+
+class Server:
+    """Resident models answering converge and render requests (mgx_server_*)."""
+
+    def __init__(self, device: int = 0, precision: int = FP32, hbm_budget: int = 0,
+                 render_slots: int = 2, branch_threshold: float = 0.35,
+                 tau_floor: float = 1e-15, chi_min: float = 1e-30, pop_floor: float = 1e-12):
+        L = lib()
+        opt = _options(precision, branch_threshold, tau_floor, chi_min, pop_floor)
+        h = C.c_void_p()
+        st = L.mgx_server_create(C.byref(h), device, C.byref(opt), int(hbm_budget), render_slots)
+        if st != MGX_OK:
+            raise MgxError(st, L.mgx_server_last_error(None).decode())
+        self._h = h
+        self.models = []
+        self._images = {}   # request id -> image array (kept alive until finished)
+
+    def _check(self, st: int):
+        if st != MGX_OK:
+            raise MgxError(st, lib().mgx_server_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().mgx_server_destroy(self._h)
+            self._h = None
+            self._images.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def add_model(self, m) -> int:
+        s, keep = _model_struct(m)
+        i = C.c_int()
+        self._check(lib().mgx_server_add_model(self._h, C.byref(s), C.byref(i)))
+        del keep
+        self.models.append(m)
+        return i.value
+
+    def start(self) -> None:
+        self._check(lib().mgx_server_start(self._h))
+
+    def clock(self) -> float:
+        return lib().mgx_server_clock(self._h)
+
+    def submit_converge(self, model: int, tol: float = 1e-6, max_iter: int = 200,
+                        ng_order: int = 4) -> int:
+        rid = C.c_int64()
+        self._check(lib().mgx_server_submit_converge(self._h, model, tol, max_iter, ng_order,
+                                                     C.byref(rid)))
+        return rid.value
+
+    def submit_render(self, model: int, direction, npx: int, npy: int, f_min: float,
+                      f_max: float, nfreq: int, out=None) -> int:
+        d = (C.c_double * 3)(*[float(x) for x in direction])
+        if out is None:
+            out = np.zeros((npy, npx, nfreq), np.float32)
+        rid = C.c_int64()
+        self._check(lib().mgx_server_submit_render(self._h, model, d, npx, npy, f_min, f_max,
+                                                   nfreq, _ptr(out), C.byref(rid)))
+        self._images[rid.value] = out
+        return rid.value
+
+    def wait(self, rid: int, timeout: float = -1.0, raise_on_error: bool = True) -> dict:
+        info = RequestInfo()
+        st = lib().mgx_server_wait(self._h, rid, timeout, C.byref(info))
+        out = {k: getattr(info, k) for k, _ in RequestInfo._fields_}
+        if st != MGX_EPENDING:
+            out["image"] = self._images.pop(rid, None)
+        if raise_on_error and st not in (MGX_OK, MGX_EPENDING):
+            raise MgxError(st, lib().mgx_server_last_error(self._h).decode())
+        return out
+
+    def get_populations(self, model: int, out=None):
+        m = self.models[model]
+        if out is None:
+            out = np.empty((m.npoints, m.nlev), np.float64)
+        self._check(lib().mgx_server_get_populations(self._h, model, _ptr(out)))
+        return out
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        self._check(lib().mgx_server_get_stats(self._h, C.byref(s)))
+        return {k: getattr(s, k) for k, _ in ServerStats._fields_}
 
 
 def header_functions(header_path: Optional[str] = None):

@@ -1,0 +1,196 @@
+"""GPU tests of the request server: converge and render requests on resident
+models, run through the C ABI.
+
+The bar is identity: a request's result (published populations, image) is
+bit for bit the result of the same work done alone -- by a lone context
+(itself checked against the oracle in the parity tests) and by a server that
+runs only that request -- whatever else is in flight.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2411_03040_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def mgx():
+    import torch
+    assert torch.cuda.is_available(), "GPU test on a host without a GPU"
+    from paper_2411_03040_amd import mgx as m
+    m.lib()
+    return m
+
+
+def bits_equal(a, b):
+    a = np.ascontiguousarray(a)
+    b = np.ascontiguousarray(b)
+    return a.shape == b.shape and a.dtype == b.dtype and np.array_equal(
+        a.view(np.uint8), b.view(np.uint8))
+
+
+def models():
+    return [synth.outflow_3d(npoints=500, seed=21, nside=1, nlev=5, nbins=15),
+            synth.outflow_3d(npoints=900, seed=22, nside=1, nlev=4, nbins=15),
+            synth.outflow_3d(npoints=300, seed=23, nside=2, nlev=6, nbins=15)]
+
+
+VIEW = (0.3, -0.5, 0.81)
+
+
+def band(m):
+    nu = m.nu[0]
+    return nu * (1 - 6e-5), nu * (1 + 6e-5)
+
+
+def lone(mgx, m, tol=1e-6):
+    c = mgx.Context(precision=mgx.FP32)
+    c.load_model(m)
+    c.trace_rays()
+    c.set_lte_populations()
+    lte_img = c.render_image(VIEW, 24, 20, *band(m), 17)
+    it, _, ok = c.iterate(tol=tol, max_iter=300, ng_mode=mgx.NG_CLASSICAL, ng_param=4)
+    assert ok
+    img = c.render_image(VIEW, 24, 20, *band(m), 17)
+    return it, c.get_populations(), lte_img, img
+
+
+def test_server_matches_lone_context(mgx):
+    ms = models()
+    srv = mgx.Server(precision=mgx.FP32, render_slots=2)
+    for m in ms:
+        srv.add_model(m)
+    srv.start()
+    # images of the published LTE state, then every model converged at once
+    lte = [srv.submit_render(i, VIEW, 24, 20, *band(m), 17) for i, m in enumerate(ms)]
+    lte_imgs = [srv.wait(r, timeout=120)["image"] for r in lte]
+    conv = [srv.submit_converge(i, tol=1e-6, max_iter=300, ng_order=4) for i in range(len(ms))]
+    infos = [srv.wait(r, timeout=120) for r in conv]
+    after = [srv.submit_render(i, VIEW, 24, 20, *band(m), 17) for i, m in enumerate(ms)]
+    imgs = [srv.wait(r, timeout=120)["image"] for r in after]
+    st = srv.stats()
+    say(f"  iterations {[i['iterations'] for i in infos]} replays {st['replays']} "
+        f"resident {st['hbm_resident'] / 1e6:.1f} MB")
+    assert st["completed"] == st["submitted"] == 3 * len(ms) and st["failed"] == 0
+    # replays are shared by the converges in flight (continuous batching)
+    its = [i["iterations"] for i in infos]
+    assert max(its) <= st["replays"] < sum(its)
+    for i, m in enumerate(ms):
+        it, pops, lte_img, img = lone(mgx, m)
+        assert infos[i]["status"] == 0 and infos[i]["iterations"] == it
+        assert bits_equal(srv.get_populations(i), pops), i
+        assert bits_equal(lte_imgs[i], lte_img), i
+        assert bits_equal(imgs[i], img), i
+    srv.close()
+
+
+def test_server_alone_vs_mixed(mgx):
+    """The same converge + render of model 0, alone and inside a stream of
+    requests on all models (renders before, during and after, converges of
+    the others, a repeated converge of model 0 queued behind the first)."""
+    ms = models()
+
+    def fresh():
+        s = mgx.Server(precision=mgx.FP32, render_slots=3)
+        for m in ms:
+            s.add_model(m)
+        s.start()
+        return s
+
+    a = fresh()
+    r = a.submit_converge(0, tol=1e-6, max_iter=300, ng_order=4)
+    ia = a.wait(r, timeout=120)
+    pa = a.get_populations(0)
+    img_a = a.wait(a.submit_render(0, VIEW, 32, 24, *band(ms[0]), 21), timeout=120)["image"]
+    a.close()
+
+    b = fresh()
+    rng = np.random.default_rng(5)
+    pending = []
+    for k in range(6):
+        j = int(rng.integers(0, len(ms)))
+        d = synth.random_rotation(k)[:, 2]
+        pending.append(b.submit_render(j, d, 32, 24, *band(ms[j]), 21))
+    pending.append(b.submit_converge(1, tol=1e-6, max_iter=300, ng_order=4))
+    pending.append(b.submit_converge(2, tol=1e-6, max_iter=300, ng_order=0))
+    r0 = b.submit_converge(0, tol=1e-6, max_iter=300, ng_order=4)
+    r0b = b.submit_converge(0, tol=1e-6, max_iter=300, ng_order=4)
+    for k in range(6):
+        j = int(rng.integers(0, len(ms)))
+        pending.append(b.submit_render(j, VIEW, 16, 16, *band(ms[j]), 9))
+    ib = b.wait(r0, timeout=120)
+    pb = b.get_populations(0)
+    ib2 = b.wait(r0b, timeout=120)
+    assert ib2["t_start"] >= ib["t_done"]      # one model, one converge at a time
+    img_b = b.wait(b.submit_render(0, VIEW, 32, 24, *band(ms[0]), 21), timeout=120)["image"]
+    for p in pending:
+        assert b.wait(p, timeout=120)["status"] == 0
+    say(f"  alone {ia['iterations']} it, mixed {ib['iterations']} it; "
+        f"latency alone {ia['t_done'] - ia['t_submit']:.3f}s mixed {ib['t_done'] - ib['t_submit']:.3f}s")
+    assert ia["iterations"] == ib["iterations"] == ib2["iterations"]
+    assert bits_equal(pa, pb)
+    assert bits_equal(b.get_populations(0), pa)
+    assert bits_equal(img_a, img_b)
+    b.close()
+
+
+def test_server_admission_and_errors(mgx):
+    ms = models()[:2]
+    # a budget below the resident footprint: start fails
+    s = mgx.Server(precision=mgx.FP32, hbm_budget=1 << 20)
+    for m in ms:
+        s.add_model(m)
+    with pytest.raises(mgx.MgxError) as e:
+        s.start()
+    assert e.value.status == mgx.MGX_ENOMEM
+    s.close()
+    # measure the resident footprint, then leave room for small images only
+    s = mgx.Server(precision=mgx.FP32)
+    with pytest.raises(mgx.MgxError) as e:
+        s.submit_converge(0)
+    assert e.value.status == mgx.MGX_ESTATE
+    for m in ms:
+        s.add_model(m)
+    s.start()
+    resident = s.stats()["hbm_resident"]
+    s.close()
+    s = mgx.Server(precision=mgx.FP32, hbm_budget=resident + (24 << 20), render_slots=2)
+    for m in ms:
+        s.add_model(m)
+    s.start()
+    small = [s.submit_render(0, VIEW, 16, 16, *band(ms[0]), 9) for _ in range(4)]
+    big = s.submit_render(1, VIEW, 1024, 1024, *band(ms[1]), 63)   # ~264 MB image alone
+    for r in small:
+        assert s.wait(r, timeout=120)["status"] == 0
+    ib = s.wait(big, timeout=120, raise_on_error=False)
+    assert ib["status"] == mgx.MGX_ENOMEM
+    st = s.stats()
+    assert st["hbm_render_peak"] <= 24 << 20 and st["failed"] == 1
+    with pytest.raises(mgx.MgxError) as e:
+        s.submit_converge(5)
+    assert e.value.status == mgx.MGX_EINVAL
+    with pytest.raises(mgx.MgxError) as e:
+        s.wait(12345)
+    assert e.value.status == mgx.MGX_EINVAL
+    with pytest.raises(mgx.MgxError) as e:
+        s.submit_render(0, (0.0, 0.0, 0.0), 8, 8, *band(ms[0]), 5)
+    assert e.value.status == mgx.MGX_EINVAL
+    s.close()
+    # point clouds only for images
+    s = mgx.Server(precision=mgx.FP64)
+    s.add_model(synth.spherical_shells("a"))
+    s.start()
+    with pytest.raises(mgx.MgxError) as e:
+        s.submit_render(0, VIEW, 8, 8, 1e11, 1e11, 3)
+    assert e.value.status == mgx.MGX_EINVAL
+    r = s.submit_converge(0, tol=1e-10, max_iter=500, ng_order=0)
+    assert s.wait(r, timeout=120)["status"] == 0
+    s.close()
