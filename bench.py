@@ -306,17 +306,6 @@ def bench_batch(args, mgx, torch):
     print(json.dumps(out), flush=True)
 
 
-def serve_spec(count, seed=7):
-    """Resident models of the serving workload: outflows with point counts
-    log-uniform in [1e4, 1e6], 5-20 levels, 12 rays, 31 bins (seeded)."""
-    out = []
-    for i in range(count):
-        rng = np.random.default_rng([seed, i])
-        out.append(dict(npoints=int(round(10 ** rng.uniform(4.0, 6.0))),
-                        nlev=int(rng.integers(5, 21)), nside=1, nbins=31, seed=20_000 + i))
-    return out
-
-
 def bench_serve(args, mgx, torch):
     """A Poisson stream of requests (mean 50/s) on resident models: 98 %
     renders (256 x 256 pixels x 63 bins around a line, random model and
@@ -324,7 +313,7 @@ def bench_serve(args, mgx, torch):
     tol 1e-6, Ng order 4).  Reports latency percentiles per kind and the
     formal-solution updates/s the server sustained."""
     from paper_2411_03040_amd import synth
-    spec = serve_spec(args.serve_models)
+    spec = synth.serve_spec(args.serve_models)
     srv = mgx.Server(device=0, precision=mgx.FP32, render_slots=2)
     t0 = time.perf_counter()
     models = []

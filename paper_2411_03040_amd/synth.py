@@ -493,6 +493,18 @@ def batch_models(count: int = 256, seed: int = 4, subset=None):
     return [outflow_3d(**spec[i]) for i in idx]
 
 
+def serve_spec(count: int = 8, seed: int = 7):
+    """Seeded recipe of the resident models of the serving workload: outflows
+    (as outflow_3d) with point counts log-uniform in [1e4, 1e6], 5-20 levels,
+    12 rays, 31 bins.  Returns keyword dicts for outflow_3d."""
+    out = []
+    for i in range(count):
+        rng = np.random.default_rng([seed, i])
+        out.append(dict(npoints=int(round(10 ** rng.uniform(4.0, 6.0))),
+                        nlev=int(rng.integers(5, 21)), nside=1, nbins=31, seed=20_000 + i))
+    return out
+
+
 def origin_sample(N: int, count: int, seed: int = 12345) -> np.ndarray:
     """Seeded sorted sample of origin points (for sampled parity / timing)."""
     rng = np.random.default_rng(seed)
