@@ -40,6 +40,11 @@
 
 #include "mgx_internal.h"
 
+// Multiply-adds are fused only where one source expression writes them, so
+// every kernel that inlines the solve (single model, batched) rounds the
+// same way and their results agree bit for bit.
+#pragma clang fp contract(on)
+
 namespace mgx {
 
 template <typename T>
@@ -77,6 +82,12 @@ struct FM<float> {
         return t * __builtin_amdgcn_exp2f(arg * 1.44269504f);
     }
     static __device__ __forceinline__ float expm1_(float x) { return expm1f(x); }
+    // max(x, lo) for lo > 0 and x >= 0 (or -0): IEEE bit patterns of
+    // non-negative floats order like signed integers, one integer max
+    static __device__ __forceinline__ float at_least(float x, float lo)
+    {
+        return __int_as_float(max(__float_as_int(x), __float_as_int(lo)));
+    }
 };
 
 template <>
@@ -85,6 +96,10 @@ struct FM<double> {
     static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
     static __device__ __forceinline__ double erfc_(double x) { return erfc(x); }
     static __device__ __forceinline__ double expm1_(double x) { return expm1(x); }
+    static __device__ __forceinline__ double at_least(double x, double lo)
+    {
+        return x > lo ? x : lo;
+    }
 };
 
 // erf(b) - erf(a) from two erfc evaluations, without cancellation for
@@ -102,22 +117,23 @@ __device__ __forceinline__ T erf_diff(T a, T b)
     return (b > a) ? t : -t;
 }
 
-// Per staged record: meta A (dv, 1/b scaled for the profile, dx, 1/b-bar of
-// the segment ending here) and meta B (b, point index with the branch bit),
-// read as one broadcast each; per record and line of the chunk the pair
-// (chi', S').
+// Per staged record: meta A (dv, 1/b scaled for the profile, half the
+// length of the segment ending here -- negative when that segment takes the
+// semi-analytic form -- and its 1/b-bar), read by the solve as one broadcast;
+// meta B (b, point index) only feeds the line gather.  Per record and line
+// of the chunk: chi', S' and chi' b (the semi-analytic segment's weight).
 template <typename T>
 struct alignas(4 * sizeof(T)) MetaA {
-    T dv, ib, dx, ibb;
+    T dv, ib, hdx, ibb;
 };
 template <typename T>
 struct alignas(2 * sizeof(T)) MetaB {
     T b;
-    int32_t ps;
+    int32_t p;
 };
 template <typename T>
-struct alignas(2 * sizeof(T)) LinePair {
-    T chi, S;
+struct alignas(4 * sizeof(T)) LineRec {
+    T chi, S, cb, pad;
 };
 
 struct LDSLayout {
@@ -136,7 +152,7 @@ __host__ __device__ inline LDSLayout lds_layout(int ch, int nlc, int nthreads)
     L.b = o;
     o += sizeof(MetaB<T>) * 2 * ch;
     L.line = o;
-    o += sizeof(LinePair<T>) * 2 * ch * nlc;
+    o += sizeof(LineRec<T>) * 2 * ch * nlc;
     const size_t red = sizeof(double) * 2 * nthreads;
     L.total = o > red ? o : red;
     return L;
@@ -193,9 +209,11 @@ template <typename T>
 struct HalfState {
     T g, eps, dm;      // elimination state
     T chi, S, dv, cb;  // previous point: opacity, source, velocity, chi'*b
-    T sdx, sibb;       // segment data stored with the previous record
-    bool semi;
+    T hdx, sibb;       // segment data stored with the previous record
 };
+
+template <typename T>
+constexpr int kUnrollBoth = sizeof(T) == 8 ? 2 : 1;
 
 // One origin x line chunk, executed by the whole workgroup (blockDim.x
 // threads, at least nlc * nbins).  Shared by the single-model launch and the
@@ -224,7 +242,7 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
     const LDSLayout LY = lds_layout<T>(ch, nlc, nth);
     MetaA<T> *s_a = (MetaA<T> *)(smem + LY.a);
     MetaB<T> *s_b = (MetaB<T> *)(smem + LY.b);
-    LinePair<T> *s_line = (LinePair<T> *)(smem + LY.line);
+    LineRec<T> *s_line = (LineRec<T> *)(smem + LY.line);
 
     // per-lane constants
     const double bo = b64[o];
@@ -240,7 +258,7 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
     const T cb_o = chi[ol] * bpt[o];
     const T tau_floor = (T)a.tau_floor;
     const T half = (T)0.5;
-    const T spi4 = (T)(kSqrtPi / 4.0);
+    const T spi2 = (T)(kSqrtPi / 2.0);
 
     auto bdy_I = [&](T dv) -> T {
         const T r = k1 * ((T)1 + dv * inv_c);
@@ -256,18 +274,20 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
         st.dm = dt;
     };
 
-    // segment from the previous point of st (farther out) to Q
+    // segment from the previous point of st (farther out) to Q; hdx carries
+    // half the segment length, so the trapezoid needs no factor 1/2
     auto segment = [&](HalfState<T> &st, T chiQ, T dvQ, T cbQ) -> T {
         T dt;
-        if (st.semi) {
+        if (signbit(st.hdx)) {
             const T xP = (xb + st.dv * k1) * st.sibb;
             const T xQ = (xb + dvQ * k1) * st.sibb;
             const T dxb = (dvQ - st.dv) * k1 * st.sibb;
-            dt = st.sdx * (st.cb + cbQ) * spi4 * st.sibb * erf_diff<T>(xP, xQ) * FM<T>::rcp(dxb);
+            dt = -st.hdx * (st.cb + cbQ) * spi2 * st.sibb * erf_diff<T>(xP, xQ) *
+                 FM<T>::rcp(dxb);
         } else {
-            dt = st.sdx * (st.chi + chiQ) * half;
+            dt = st.hdx * (st.chi + chiQ);
         }
-        return dt > tau_floor ? dt : tau_floor;
+        return FM<T>::at_least(dt, tau_floor);
     };
 
     double accJ = 0.0, accL = 0.0;
@@ -278,19 +298,39 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
         const int np = (int)(off[(int64_t)o * R + rp + 1] - offp);
         const int64_t offm = off[(int64_t)o * R + rm];
         const int nm = (int)(off[(int64_t)o * R + rm + 1] - offm);
-        const int K = max(np, nm);
 
-        HalfState<T> st[2];
-#pragma unroll
-        for (int h = 0; h < 2; h++) {
-            st[h].g = (T)1;
-            st[h].dm = (T)0;
-            st[h].eps = bdy_I((T)0);  // replaced at the far end of a non-empty half
-            st[h].chi = st[h].S = st[h].dv = st[h].cb = st[h].sdx = st[h].sibb = (T)0;
-            st[h].semi = false;
-        }
+        // Halves by length: A the longer (all of a chunk's records lie
+        // inside it), B the shorter.  The minus half is staged first.
+        const bool a_minus = nm >= np;
+        const int nA = a_minus ? nm : np, nB = a_minus ? np : nm;
+        HalfState<T> A, B;
+        A.g = B.g = (T)1;
+        A.dm = B.dm = (T)0;
+        A.eps = B.eps = bdy_I((T)0);  // replaced at the far end of a non-empty half
+        A.chi = A.S = A.dv = A.cb = A.hdx = A.sibb = (T)0;
+        B.chi = B.S = B.dv = B.cb = B.hdx = B.sibb = (T)0;
 
-        for (int hi = K; hi > 0; hi -= ch) {
+        // point Q (staged record e) of a half: its profile, then either the
+        // far-end boundary intensity or one elimination row
+        auto visit = [&](HalfState<T> &s, int e, bool far_end) {
+            const MetaA<T> ma = s_a[e];
+            const LineRec<T> lr = s_line[e * nlc + ll];
+            const T dvQ = ma.dv;
+            const T xQ = (xb + dvQ * k1) * ma.ib;
+            const T chiQ = lr.chi * FM<T>::phi_scaled(xQ);
+            if (far_end)
+                s.eps = bdy_I(dvQ);
+            else
+                row(s, segment(s, chiQ, dvQ, lr.cb));
+            s.chi = chiQ;
+            s.S = lr.S;
+            s.dv = dvQ;
+            s.cb = lr.cb;
+            s.hdx = ma.hdx;
+            s.sibb = ma.ibb;
+        };
+
+        for (int hi = nA; hi > 0; hi -= ch) {
             const int lo = hi - ch > 0 ? hi - ch : 0;
             // valid records of each half in [lo, hi), packed densely: the
             // minus half first, then the plus half
@@ -306,67 +346,61 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
                 MetaA<T> ma;
                 ma.dv = rc.dv;
                 ma.ib = ibpt[p];
-                ma.dx = rc.dx;
+                ma.hdx = rc.ps < 0 ? -(rc.dx * half) : rc.dx * half;
                 ma.ibb = rc.ibb;
                 s_a[t] = ma;
                 MetaB<T> mb;
                 mb.b = bpt[p];
-                mb.ps = rc.ps;
+                mb.p = p;
                 s_b[t] = mb;
             }
             __syncthreads();
             for (int t = tid; t < cnt * nl_here; t += nth) {
                 const int e = t / nl_here;
                 const int li = t - e * nl_here;
-                const int64_t idx = (int64_t)(s_b[e].ps & 0x7fffffff) * nl + l0 + li;
-                LinePair<T> lp;
-                lp.chi = chi[idx];
-                lp.S = S[idx];
-                s_line[e * nlc + li] = lp;
+                const MetaB<T> mb = s_b[e];
+                const int64_t idx = (int64_t)mb.p * nl + l0 + li;
+                LineRec<T> lr;
+                lr.chi = chi[idx];
+                lr.S = S[idx];
+                lr.cb = lr.chi * mb.b;
+                lr.pad = (T)0;
+                s_line[e * nlc + li] = lr;
             }
             __syncthreads();
-            for (int k = hi - 1; k >= lo; k--) {
-#pragma unroll
-                for (int h = 0; h < 2; h++) {
-                    const int nh = h ? np : nm;
-                    if (k < nh) {
-                        const int e = (h ? cm : 0) + (k - lo);
-                        const MetaA<T> ma = s_a[e];
-                        const MetaB<T> mb = s_b[e];
-                        const LinePair<T> lp = s_line[e * nlc + ll];
-                        const T dvQ = ma.dv;
-                        HalfState<T> &s = st[h];
-                        // the profile value at Q only enters trapezoidal
-                        // segments: skip it when both neighbouring segments
-                        // are semi-analytic (uniform across the workgroup)
-                        const bool next_semi = mb.ps < 0;
-                        const bool prev_semi = (k != nh - 1) && s.semi;
-                        (void)prev_semi;
-                        const T xQ = (xb + dvQ * k1) * ma.ib;
-                        const T chiQ = lp.chi * FM<T>::phi_scaled(xQ);
-                        const T cbQ = lp.chi * mb.b;
-                        if (k == nh - 1) {
-                            s.eps = bdy_I(dvQ);
-                        } else {
-                            row(s, segment(s, chiQ, dvQ, cbQ));
-                        }
-                        s.chi = chiQ;
-                        s.S = lp.S;
-                        s.dv = dvQ;
-                        s.cb = cbQ;
-                        s.sdx = ma.dx;
-                        s.sibb = ma.ibb;
-                        s.semi = next_semi;
-                    }
-                }
+            // record k of half A is staged at eA + k, of half B at eB + k
+            const int eA = (a_minus ? 0 : cm) - lo, eB = (a_minus ? cm : 0) - lo;
+            int k = hi - 1;
+            // records beyond the end of B: A alone (its far end first)
+            if (k >= nB && k == nA - 1) {
+                visit(A, eA + k, true);
+                k--;
+            }
+            const int kAB = max(lo, nB);
+#pragma unroll 2
+            for (; k >= kAB; k--) visit(A, eA + k, false);
+            // B's far end (A's too when the halves are equally long)
+            if (k >= lo && k == nB - 1) {
+                visit(A, eA + k, k == nA - 1);
+                visit(B, eB + k, true);
+                k--;
+            }
+            // (unrolled twice in FP64 only: measured faster there, slower in
+            // FP32 where the extra registers cost occupancy)
+#pragma unroll kUnrollBoth<T>
+            for (; k >= lo; k--) {
+                visit(A, eA + k, false);
+                visit(B, eB + k, false);
             }
         }
         // last segment of each non-empty half ends at the origin
-        if (nm > 0) row(st[0], segment(st[0], chi_o, (T)0, cb_o));
-        if (np > 0) row(st[1], segment(st[1], chi_o, (T)0, cb_o));
-        const T Do = (st[0].dm + st[1].dm) * half;
-        const T inv_den = FM<T>::rcp(Do + st[0].g + st[1].g);
-        const T u = (Do * S_o + st[0].eps + st[1].eps) * inv_den;
+        if (nA > 0) row(A, segment(A, chi_o, (T)0, cb_o));
+        if (nB > 0) row(B, segment(B, chi_o, (T)0, cb_o));
+        // combine in the order minus, plus
+        const HalfState<T> &Hm = a_minus ? A : B, &Hp = a_minus ? B : A;
+        const T Do = (Hm.dm + Hp.dm) * half;
+        const T inv_den = FM<T>::rcp(Do + Hm.g + Hp.g);
+        const T u = (Do * S_o + Hm.eps + Hp.eps) * inv_den;
         const T lam = Do * inv_den;
         const double w = pair_w[pi];
         accJ += w * (double)u;
