@@ -127,10 +127,10 @@ __device__ __forceinline__ T erf_diff(T a, T b)
 // Per staged record: meta A (dv, 1/b scaled for the profile, half the
 // length of the segment ending here -- negative when that segment takes the
 // semi-analytic form -- and its 1/b-bar), read by the solve as one broadcast;
-// meta B (b, point index, and for a semi-analytic segment the reciprocal of
-// its projected velocity change in averaged widths) only feeds the line
-// gather.  Per record and line of the chunk: chi', S', chi' b (the
-// semi-analytic segment's weight) and that reciprocal again.
+// meta B (b, point index, and for a semi-analytic segment the lane-
+// independent factor of its optical depth, dx sqrt(pi)/4 / (dv_Q - dv_P))
+// only feeds the line gather.  Per record and line of the chunk: chi', S', chi' b (the
+// semi-analytic segment's weight) and that factor again.
 template <typename T>
 struct alignas(4 * sizeof(T)) MetaA {
     T dv, ib, hdx, ibb;
@@ -139,11 +139,11 @@ template <typename T>
 struct alignas(2 * sizeof(T)) MetaB {
     T b;
     int32_t p;
-    T rdv;
+    T rw;
 };
 template <typename T>
 struct alignas(4 * sizeof(T)) LineRec {
-    T chi, S, cb, rdv;
+    T chi, S, cb, rw;
 };
 
 struct LDSLayout {
@@ -218,8 +218,8 @@ __device__ __forceinline__ Rec<double> load_stream(gptr<Rec<double>> p)
 template <typename T>
 struct HalfState {
     T g, eps, dm;      // elimination state
-    T chi, S, dv, cb;  // previous point: opacity, source, velocity, chi'*b
-    T hdx, sibb, rdv;  // segment data stored with the previous record
+    T chi, S, u, cb;   // previous point: opacity, source, xb + dv k1, chi'*b
+    T hdx, sibb, rw;   // segment data stored with the previous record
 };
 
 template <typename T>
@@ -269,7 +269,7 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
     const T cb_o = chi[ol] * bpt[o];
     const T tau_floor = (T)a.tau_floor;
     const T half = (T)0.5;
-    const T spi2 = (T)(kSqrtPi / 2.0);
+    const T spi4 = (T)(kSqrtPi / 4.0);
 
     auto bdy_I = [&](T dv) -> T {
         const T r = k1 * ((T)1 + dv * inv_c);
@@ -285,17 +285,19 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
         st.dm = dt;
     };
 
-    // segment from the previous point of st (farther out) to Q; hdx carries
-    // half the segment length, so the trapezoid needs no factor 1/2
-    auto segment = [&](HalfState<T> &st, T chiQ, T dvQ, T cbQ) -> T {
+    // segment from the previous point of st (farther out) to Q, whose
+    // unscaled offset is uQ = xb + dvQ k1; hdx carries half the segment
+    // length, so the trapezoid needs no factor 1/2.  Semi-analytic:
+    //   dt = dx sqrt(pi)/4 (cb_P + cb_Q) (erf x_Q - erf x_P) / (b-bar (x_Q - x_P))
+    // with x = u / b-bar and x_Q - x_P = (dvQ - dvP) k1 / b-bar, so b-bar
+    // cancels outside the erf arguments; dx sqrt(pi)/4 / (dvQ - dvP) is
+    // staged with the record (rw).
+    auto segment = [&](HalfState<T> &st, T chiQ, T uQ, T cbQ) -> T {
         T dt;
         if (signbit(st.hdx)) {
-            const T xP = (xb + st.dv * k1) * st.sibb;
-            const T xQ = (xb + dvQ * k1) * st.sibb;
-            // 1 / (xQ - xP) = 1 / ((dvQ - dvP) k1 / b-bar), the uniform part
-            // staged with the record
-            dt = -st.hdx * (st.cb + cbQ) * spi2 * st.sibb * erf_diff<T>(xP, xQ) *
-                 (st.rdv * inv_k1);
+            const T xP = st.u * st.sibb;
+            const T xQ = uQ * st.sibb;
+            dt = (st.cb + cbQ) * erf_diff<T>(xP, xQ) * (st.rw * inv_k1);
         } else {
             dt = st.hdx * (st.chi + chiQ);
         }
@@ -319,8 +321,8 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
         A.g = B.g = (T)1;
         A.dm = B.dm = (T)0;
         A.eps = B.eps = bdy_I((T)0);  // replaced at the far end of a non-empty half
-        A.chi = A.S = A.dv = A.cb = A.hdx = A.sibb = A.rdv = (T)0;
-        B.chi = B.S = B.dv = B.cb = B.hdx = B.sibb = B.rdv = (T)0;
+        A.chi = A.S = A.u = A.cb = A.hdx = A.sibb = A.rw = (T)0;
+        B.chi = B.S = B.u = B.cb = B.hdx = B.sibb = B.rw = (T)0;
 
         // point Q (staged record e) of a half: its profile, then either the
         // far-end boundary intensity or one elimination row
@@ -328,22 +330,22 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
             const MetaA<T> ma = s_a[e];
             const LineRec<T> lr = s_line[e * nlc + ll];
             const T dvQ = ma.dv;
+            const T uQ = xb + dvQ * k1;
             // (the profile is evaluated even where both segments at Q are
             // semi-analytic and never read it: a branch around it measured
             // 12 % slower)
-            const T xQ = (xb + dvQ * k1) * ma.ib;
-            const T chiQ = lr.chi * FM<T>::phi_scaled(xQ);
+            const T chiQ = lr.chi * FM<T>::phi_scaled(uQ * ma.ib);
             if (far_end)
                 s.eps = bdy_I(dvQ);
             else
-                row(s, segment(s, chiQ, dvQ, lr.cb));
+                row(s, segment(s, chiQ, uQ, lr.cb));
             s.chi = chiQ;
             s.S = lr.S;
-            s.dv = dvQ;
+            s.u = uQ;
             s.cb = lr.cb;
             s.hdx = ma.hdx;
             s.sibb = ma.ibb;
-            s.rdv = lr.rdv;
+            s.rw = lr.rw;
         };
 
         for (int hi = nA; hi > 0; hi -= ch) {
@@ -369,10 +371,10 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
                 MetaB<T> mb;
                 mb.b = bpt[p];
                 mb.p = p;
-                mb.rdv = (T)0;
+                mb.rw = (T)0;
                 if (rc.ps < 0) {  // semi-analytic: the walk predecessor's dv
                     const T dv_prev = k > 0 ? rec[base + k - 1].dv : (T)0;
-                    mb.rdv = FM<T>::rcp((dv_prev - rc.dv) * rc.ibb);
+                    mb.rw = rc.dx * spi4 * FM<T>::rcp(dv_prev - rc.dv);
                 }
                 s_b[t] = mb;
             }
@@ -386,7 +388,7 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
                 lr.chi = chi[idx];
                 lr.S = S[idx];
                 lr.cb = lr.chi * mb.b;
-                lr.rdv = mb.rdv;
+                lr.rw = mb.rw;
                 s_line[e * nlc + li] = lr;
             }
             __syncthreads();
@@ -416,8 +418,8 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
             }
         }
         // last segment of each non-empty half ends at the origin
-        if (nA > 0) row(A, segment(A, chi_o, (T)0, cb_o));
-        if (nB > 0) row(B, segment(B, chi_o, (T)0, cb_o));
+        if (nA > 0) row(A, segment(A, chi_o, xb, cb_o));
+        if (nB > 0) row(B, segment(B, chi_o, xb, cb_o));
         // combine in the order minus, plus
         const HalfState<T> &Hm = a_minus ? A : B, &Hp = a_minus ? B : A;
         const T Do = (Hm.dm + Hp.dm) * half;
