@@ -64,22 +64,25 @@ struct FM<float> {
     // fractional error below 1.2e-7 for all x >= 0.  One reciprocal, one
     // exp2 and a degree-9 Horner chain, the same for every lane (the library
     // erfcf branches by argument range, which diverges across the bins of a
-    // wave).
-    static __device__ __forceinline__ float erfc_(float x)
+    // wave).  Evaluated in base 2: the argument comes scaled by sqrt(log2 e)
+    // (xs = x sqrt(log2 e), see erf_scale) and the coefficients below are the
+    // published ones times log2 e, so exp2 takes -xs^2 + log2(e) P(t)
+    // directly.
+    static constexpr float erf_scale = 1.2011224f;  // sqrt(log2 e)
+    static __device__ __forceinline__ float erfc_scaled(float xs)
     {
-        const float t = __builtin_amdgcn_rcpf(1.0f + 0.5f * x);
-        float p = 0.17087277f;
-        p = fmaf(p, t, -0.82215223f);
-        p = fmaf(p, t, 1.48851587f);
-        p = fmaf(p, t, -1.13520398f);
-        p = fmaf(p, t, 0.27886807f);
-        p = fmaf(p, t, -0.18628806f);
-        p = fmaf(p, t, 0.09678418f);
-        p = fmaf(p, t, 0.37409196f);
-        p = fmaf(p, t, 1.00002368f);
-        p = fmaf(p, t, -1.26551223f);
-        const float arg = fmaf(-x, x, p);
-        return t * __builtin_amdgcn_exp2f(arg * 1.44269504f);
+        const float t = __builtin_amdgcn_rcpf(fmaf(xs, 0.41627732f, 1.0f));
+        float p = 0.2465173f;
+        p = fmaf(p, t, -1.1861149f);
+        p = fmaf(p, t, 2.1474745f);
+        p = fmaf(p, t, -1.6377531f);
+        p = fmaf(p, t, 0.40232158f);
+        p = fmaf(p, t, -0.26875687f);
+        p = fmaf(p, t, 0.13963005f);
+        p = fmaf(p, t, 0.5397006f);
+        p = fmaf(p, t, 1.4427292f);
+        p = fmaf(p, t, -1.8257482f);
+        return t * __builtin_amdgcn_exp2f(fmaf(-xs, xs, p));
     }
     // e^x - 1 for the CMB boundary intensity: exp2 away from zero, a
     // four-term series below |x| = 0.1 (relative error < 1e-6 on both sides)
@@ -101,7 +104,8 @@ template <>
 struct FM<double> {
     static __device__ __forceinline__ double phi_scaled(double x) { return exp(-(x * x)); }
     static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
-    static __device__ __forceinline__ double erfc_(double x) { return erfc(x); }
+    static constexpr double erf_scale = 1.0;
+    static __device__ __forceinline__ double erfc_scaled(double x) { return erfc(x); }
     static __device__ __forceinline__ double expm1_(double x) { return expm1(x); }
     static __device__ __forceinline__ double at_least(double x, double lo)
     {
@@ -109,15 +113,15 @@ struct FM<double> {
     }
 };
 
-// erf(b) - erf(a) from two erfc evaluations, without cancellation for
-// arguments of equal sign (the semi-analytic branch guarantees |b - a| is at
-// least about the branch threshold, so the opposite-sign form 2 - erfc - erfc
-// never cancels either).
+// erf(b) - erf(a) from two erfc evaluations (arguments scaled by erf_scale),
+// without cancellation for arguments of equal sign (the semi-analytic branch
+// guarantees |b - a| is at least about the branch threshold, so the
+// opposite-sign form 2 - erfc - erfc never cancels either).
 template <typename T>
 __device__ __forceinline__ T erf_diff(T a, T b)
 {
-    const T ea = FM<T>::erfc_(fabs(a));
-    const T eb = FM<T>::erfc_(fabs(b));
+    const T ea = FM<T>::erfc_scaled(fabs(a));
+    const T eb = FM<T>::erfc_scaled(fabs(b));
     if (a >= (T)0 && b >= (T)0) return ea - eb;
     if (a <= (T)0 && b <= (T)0) return eb - ea;
     const T t = (T)2 - ea - eb;
@@ -126,7 +130,8 @@ __device__ __forceinline__ T erf_diff(T a, T b)
 
 // Per staged record: meta A (dv, 1/b scaled for the profile, half the
 // length of the segment ending here -- negative when that segment takes the
-// semi-analytic form -- and its 1/b-bar), read by the solve as one broadcast;
+// semi-analytic form -- and its 1/b-bar times erf_scale), read by the solve
+// as one broadcast;
 // meta B (b, point index, and for a semi-analytic segment the lane-
 // independent factor of its optical depth, dx sqrt(pi)/4 / (dv_Q - dv_P))
 // only feeds the line gather.  Per record and line of the chunk: chi', S', chi' b (the
@@ -366,7 +371,7 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
                 ma.dv = rc.dv;
                 ma.ib = ibpt[p];
                 ma.hdx = rc.ps < 0 ? -(rc.dx * half) : rc.dx * half;
-                ma.ibb = rc.ibb;
+                ma.ibb = rc.ibb * (T)FM<T>::erf_scale;
                 s_a[t] = ma;
                 MetaB<T> mb;
                 mb.b = bpt[p];
