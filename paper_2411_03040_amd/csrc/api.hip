@@ -214,6 +214,38 @@ extern "C" mgx_status mgx_load_model(mgx_ctx *ctx, const mgx_model *m)
                        (hi3[2] - lo3[2]) * (hi3[2] - lo3[2]));
     ctx->L_unit = diag > 0 ? diag / cbrt((double)N) : 1.0;
 
+    // Origins in Morton (Z-curve) order of their positions, 10 bits per axis
+    // over the bounding box, ties by index -- kept only where the formal
+    // solution uses it: when the line table (chi' and S' in the solve
+    // precision) outgrows one XCD's 4 MB L2.
+    ctx->order.release();
+    const size_t table = (size_t)N * m->nlines * 2 * (ctx->fp32() ? sizeof(float) : sizeof(double));
+    if (table > ((size_t)4 << 20)) {
+        auto spread = [](uint32_t v) {
+            uint64_t x = v & 0x3ff;
+            x = (x | (x << 16)) & 0x030000ffull;
+            x = (x | (x << 8)) & 0x0300f00full;
+            x = (x | (x << 4)) & 0x030c30c3ull;
+            x = (x | (x << 2)) & 0x09249249ull;
+            return x;
+        };
+        std::vector<std::pair<uint64_t, int32_t>> key((size_t)N);
+        for (int i = 0; i < N; i++) {
+            uint64_t code = 0;
+            for (int k = 0; k < 3; k++) {
+                const double w = hi3[k] - lo3[k];
+                const double f = w > 0 ? (m->pos[(size_t)k * N + i] - lo3[k]) / w : 0.0;
+                const uint32_t c = (uint32_t)std::min(1023.0, std::max(0.0, f * 1024.0));
+                code |= spread(c) << k;
+            }
+            key[i] = {code, i};
+        }
+        std::sort(key.begin(), key.end());
+        std::vector<int32_t> ord((size_t)N);
+        for (int i = 0; i < N; i++) ord[i] = key[i].second;
+        upload(ctx, ctx->order, ord.data(), ord.size());
+        ctx->sync();
+    }
     upload(ctx, ctx->pos, m->pos, 3 * (size_t)N);
     upload(ctx, ctx->vel, m->vel, 3 * (size_t)N);
     upload(ctx, ctx->nbs_off, m->nbs_off, (size_t)N + 1);
@@ -533,6 +565,7 @@ FSArgs<T> mgxh::fs_args(mgx_ctx *ctx)
     a.tau_floor = ctx->opt.tau_floor;
     a.J = ctx->J.as<double>();
     a.L = ctx->L.as<double>();
+    a.order = ctx->order.as<int32_t>();  // null where the table fits the L2
     return a;
 }
 template FSArgs<float> mgxh::fs_args<float>(mgx_ctx *);
@@ -1029,7 +1062,7 @@ size_t mgxh::ctx_bytes(const mgx_ctx *c)
                          &c->b, &c->bf, &c->ibf, &c->bd, &c->ibd, &c->xf, &c->W, &c->Bul,
                          &c->Blu, &c->hnu4pi, &c->chiscale, &c->Iref, &c->acmb, &c->pair_r,
                          &c->pair_a, &c->pair_w, &c->pops, &c->pops_new, &c->J, &c->L, &c->S64,
-                         &c->chiT, &c->ST, &c->counters, &c->counts, &c->offsets, &c->r_idx,
+                         &c->chiT, &c->ST, &c->counters, &c->order, &c->counts, &c->offsets, &c->r_idx,
                          &c->r_semi, &c->r_Z, &c->r_dv, &c->r_dx, &c->r_ibb, &c->rec, &c->ng_G,
                          &c->ng_coef, &c->ng_status, &c->ng_partial, &c->ng_pred, &c->ng_prev,
                          &c->ng_bits};

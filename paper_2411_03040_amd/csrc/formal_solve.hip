@@ -131,11 +131,11 @@ __device__ __forceinline__ T erf_diff(T a, T b)
 // Per staged record: meta A (dv, 1/b scaled for the profile, half the
 // length of the segment ending here -- negative when that segment takes the
 // semi-analytic form -- and its 1/b-bar times erf_scale), read by the solve
-// as one broadcast;
-// meta B (b, point index, and for a semi-analytic segment the lane-
-// independent factor of its optical depth, dx sqrt(pi)/4 / (dv_Q - dv_P))
-// only feeds the line gather.  Per record and line of the chunk: chi', S', chi' b (the
-// semi-analytic segment's weight) and that factor again.
+// as one broadcast; meta B (b, point index, the semi-analytic factor below)
+// only feeds the line gather.  Per record and line of the
+// chunk: chi', S', chi' b (the semi-analytic segment's weight) and, for a
+// semi-analytic segment, the lane-independent factor of its optical depth,
+// dx sqrt(pi)/4 / (dv_Q - dv_P).
 template <typename T>
 struct alignas(4 * sizeof(T)) MetaA {
     T dv, ib, hdx, ibb;
@@ -274,7 +274,7 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
     const T cb_o = chi[ol] * bpt[o];
     const T tau_floor = (T)a.tau_floor;
     const T half = (T)0.5;
-    const T spi4 = (T)(kSqrtPi / 4.0);
+    const T spi2 = (T)(kSqrtPi / 2.0);
 
     auto bdy_I = [&](T dv) -> T {
         const T r = k1 * ((T)1 + dv * inv_c);
@@ -376,10 +376,16 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
                 MetaB<T> mb;
                 mb.b = bpt[p];
                 mb.p = p;
+                // semi-analytic: dx sqrt(pi)/4 / (dv_prev - dv) with the walk
+                // predecessor's dv read from the trace (the origin's 0 before
+                // the first record).  The re-read costs trace traffic (the
+                // neighbouring lane's streamed load does not stay in L2) but
+                // measured faster than taking it from LDS after a barrier or
+                // from the neighbouring lane, which serialise the staging.
                 mb.rw = (T)0;
-                if (rc.ps < 0) {  // semi-analytic: the walk predecessor's dv
+                if (rc.ps < 0) {
                     const T dv_prev = k > 0 ? rec[base + k - 1].dv : (T)0;
-                    mb.rw = rc.dx * spi4 * FM<T>::rcp(dv_prev - rc.dv);
+                    mb.rw = rc.dx * half * spi2 * FM<T>::rcp(dv_prev - rc.dv);
                 }
                 s_b[t] = mb;
             }
@@ -454,11 +460,28 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
     }
 }
 
-template <typename T, int MAXT>
+// Workgroups are dealt round-robin to the XCDs in launch order.  With an
+// origin order (given when the line table outgrows an XCD's L2), each XCD
+// gets a contiguous run of the origins' Morton order, so the workgroups that
+// share an L2 solve neighbouring origins, whose walks gather the same points.
+// Smaller tables stay L2-resident anyway and keep the launch order, which
+// measured faster there (costs of neighbouring origins are correlated).
+constexpr int kXcds = 8;
+
+template <typename T, int MAXT, bool ORDERED>
 __global__ __launch_bounds__(MAXT) void k_formal_solve(FSArgs<T> a, int ch)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    solve_origin<T>(a, blockIdx.x, blockIdx.y, ch, smem);
+    if (ORDERED) {
+        const int G = gridDim.x, b = blockIdx.x;
+        const int x = b % kXcds, q = G / kXcds, r = G % kXcds;
+        // loaded, so uniform only by construction: say so, or every address
+        // derived from the origin becomes per-lane
+        const int o = __builtin_amdgcn_readfirstlane(a.order[x * q + min(x, r) + b / kXcds]);
+        solve_origin<T>(a, o, blockIdx.y, ch, smem);
+    } else {
+        solve_origin<T>(a, blockIdx.x, blockIdx.y, ch, smem);
+    }
 }
 
 // Batched launch: one workgroup per work item (model, origin, line chunk) of
@@ -523,10 +546,18 @@ hipError_t launch_formal_solve(const FSArgs<T> &a, hipStream_t s)
     dim3 grid(a.N, nchunks);
     // double keeps more state live per lane: a 512-thread bound leaves it 256
     // VGPRs (no spills); 1024 only when one line has more than 512 bins
-    if (sizeof(T) == 8 && a.nthreads <= 512)
-        k_formal_solve<T, 512><<<grid, a.nthreads, L.total, s>>>(a, ch);
-    else
-        k_formal_solve<T, 1024><<<grid, a.nthreads, L.total, s>>>(a, ch);
+    const bool ordered = a.order != nullptr;
+    if (sizeof(T) == 8 && a.nthreads <= 512) {
+        if (ordered)
+            k_formal_solve<T, 512, true><<<grid, a.nthreads, L.total, s>>>(a, ch);
+        else
+            k_formal_solve<T, 512, false><<<grid, a.nthreads, L.total, s>>>(a, ch);
+    } else {
+        if (ordered)
+            k_formal_solve<T, 1024, true><<<grid, a.nthreads, L.total, s>>>(a, ch);
+        else
+            k_formal_solve<T, 1024, false><<<grid, a.nthreads, L.total, s>>>(a, ch);
+    }
     return hipGetLastError();
 }
 

@@ -144,6 +144,7 @@ struct mgx_ctx {
     DMem pair_r, pair_a, pair_w;
     DMem pops, pops_new, J, L, S64, chiT, ST;
     DMem counters;
+    DMem order;  // origins in Morton order of their positions
     // trace
     DMem counts, offsets;
     void *scan_tmp = nullptr;

@@ -80,6 +80,7 @@ struct FSArgs {
     const double *Iref;     // [nlines] 2 h nu^3 / c^2
     double tau_floor;
     double *J, *L;          // [N][nlines]
+    const int32_t *order;   // [N] origins in Morton order of their positions
 };
 
 struct LineArgs {
