@@ -169,7 +169,14 @@ def converge(mgx, torch, m, precision, tol, max_iter, time_limit):
             "seconds_per_iteration": dt / it, "pops": pops}
 
 
-def cpu_baseline(m, seconds):
+def cpu_baseline(m, seconds, gpu_J=None, converged=None):
+    """The oracle (all host cores) on a seeded sample of origins of the same
+    model from LTE populations, as updates/s.  With the GPU's J-bar from the
+    same LTE populations (gpu_J), also its largest relative error on the
+    sample; with converged populations ({name: (pops, iterations)}), the
+    oracle's own Lambda-iteration step from them at sampled points (how far
+    they are from the oracle's fixed point) and, for the FP64 form, the
+    oracle's converged-model time extrapolated from the sampled rate."""
     import oracle
     from paper_2411_03040_amd import synth
     orc = oracle.Oracle(m)
@@ -180,15 +187,44 @@ def cpu_baseline(m, seconds):
     while True:
         origins = synth.origin_sample(m.npoints, n, seed=99)
         t0 = time.perf_counter()
-        orc.solve_origins(pops, origins)
+        J, _ = orc.solve_origins(pops, origins)
         t = time.perf_counter() - t0
         if t > 0.25 * seconds or n >= m.npoints:
             break
         n = min(m.npoints, int(n * max(2.0, 0.3 * seconds / max(t, 1e-3))))
     rate = n * m.nrays * lanes / t
-    return {"value": rate, "unit": "updates/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"formal solution (line coefficients + all rays, lines, bins) of {n} "
-                      f"seeded origins of the same model from LTE populations, {t:.1f} s"}
+    out = {"value": rate, "unit": "updates/s", "cores": oracle.num_threads(), "kind": "oracle",
+           "sample": f"formal solution (line coefficients + all rays, lines, bins) of {n} "
+                     f"seeded origins of the same model from LTE populations, {t:.1f} s"}
+    if gpu_J is not None:
+        g = np.asarray(gpu_J)[origins]
+        out["gpu_Jbar_max_rel_err"] = float(np.max(np.abs(g - J) / np.abs(J)))
+    for name, (p, iters) in (converged or {}).items():
+        sub = synth.origin_sample(m.npoints, 16, seed=98)
+        Jc, Lc = orc.solve_origins(p, sub)
+        _, _, Sc, _ = orc.line_coeffs(p)
+        res = 0.0
+        for k, o in enumerate(sub):
+            _, new = orc.stateq_point(int(o), Jc[k], Lc[k], Sc[o])
+            res = max(res, float(np.max(np.abs(new - p[o]) / np.maximum(p[o], 1e-12))))
+        out[f"{name}_pops_oracle_step_max_rel"] = res
+        if name == "fp64":
+            per_iter = m.npoints * m.nrays * lanes / rate
+            if per_iter * iters < 0.5 * seconds:
+                # small enough: the oracle converges the model itself (same
+                # tolerance and Ng schedule as the FP64 GPU form)
+                t0 = time.perf_counter()
+                r = orc.iterate(tol=1e-10, max_iter=2000, ng_mode=1, ng_param=4)
+                out["oracle_converged_seconds"] = time.perf_counter() - t0
+                out["oracle_converged_iterations"] = r["iters"]
+                out["fp64_pops_max_rel_vs_oracle"] = float(
+                    np.max(np.abs(p - r["pops"]) / np.maximum(r["pops"], 1e-12)))
+            else:
+                out["oracle_converged_seconds_extrapolated"] = per_iter * iters
+                out["oracle_converged_note"] = (
+                    f"{iters} iterations (those of the FP64 GPU form) x {per_iter:.1f} s per "
+                    "iteration at the sampled rate")
+    return out
 
 
 def ng_study(mgx, torch):
@@ -468,14 +504,20 @@ def main():
     th = rng.uniform(0, np.pi)
     view = [np.sin(th), 0.0, np.cos(th)]
     nu_r = m.nu[min(1, m.nlines - 1)]
-    ctx.render_image(view, 256, 256, nu_r * (1 - 5e-5), nu_r * (1 + 5e-5), 63)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    nrep = 3
-    for _ in range(nrep):
+    render = None
+    if m.dim == 3:  # images of point clouds only
         ctx.render_image(view, 256, 256, nu_r * (1 - 5e-5), nu_r * (1 + 5e-5), 63)
-    torch.cuda.synchronize()
-    render_ms = (time.perf_counter() - t0) / nrep * 1e3
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        nrep = 3
+        for _ in range(nrep):
+            ctx.render_image(view, 256, 256, nu_r * (1 - 5e-5), nu_r * (1 + 5e-5), 63)
+        torch.cuda.synchronize()
+        render_ms = (time.perf_counter() - t0) / nrep * 1e3
+        render = {"pixels": 256 * 256, "bins": 63, "ms": render_ms,
+                  "pixel_bins_per_s": 256 * 256 * 63 / (render_ms * 1e-3),
+                  "includes": "line coefficients, pixel entry search, walks, integration, "
+                              "copy of the float image to the host"}
     roof = alu_roofline(ctx, m, fs_ms, args.precision)
     if args.precision == "fp32":
         roof["traffic"] = committed_traffic(args.workload)
@@ -488,10 +530,7 @@ def main():
                    "lines": m.nlines, "bins": m.nbins, "levels": m.nlev,
                    "formal_solve": args.precision, "stateq": "f64", "ng": "classical order 4"},
         "formal_solve_ms": fs_ms, "trace_ms": trace_ms,
-        "render": {"pixels": 256 * 256, "bins": 63, "ms": render_ms,
-                   "pixel_bins_per_s": 256 * 256 * 63 / (render_ms * 1e-3),
-                   "includes": "line coefficients, pixel entry search, walks, integration, "
-                               "copy of the float image to the host"},
+        "render": render,
         "ray_pair_solves_per_s": value / 2.0,
         "roofline": roof,
     }
@@ -504,6 +543,8 @@ def main():
                          time_limit=args.converge_seconds)
             conv[name] = r
         a, b = conv["fp32_bulk"].pop("pops"), conv["fp64"].pop("pops")
+        conv_pops = {"fp32_bulk": (a, conv["fp32_bulk"]["iterations"]),
+                     "fp64": (b, conv["fp64"]["iterations"])}
         conv["fp32_vs_fp64_pops_max_rel"] = float(np.max(np.abs(a - b) / np.maximum(b, 1e-12)))
         conv["speedup_fp32_bulk_over_fp64"] = (conv["fp64"]["seconds_per_iteration"] /
                                                conv["fp32_bulk"]["seconds_per_iteration"])
@@ -511,7 +552,14 @@ def main():
     log(f"bench: timed steps {ms_step:.2f} ms/step")
     if not args.no_cpu:
         log("bench: CPU oracle baseline")
-        out["cpu_baseline"] = cpu_baseline(m, args.cpu_seconds)
+        cx = mgx.Context(device=0, precision=prec)
+        cx.load_model(m)
+        cx.trace_rays()
+        cx.set_lte_populations()
+        gpu_J, _ = cx.formal_solve()
+        del cx
+        out["cpu_baseline"] = cpu_baseline(m, args.cpu_seconds, gpu_J=gpu_J,
+                                           converged=None if args.no_converge else conv_pops)
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
