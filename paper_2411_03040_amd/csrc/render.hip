@@ -14,10 +14,9 @@
 //   I1 = I0 e^-t + S0 ((1 - e^-t)/t - e^-t) + S1 (1 - (1 - e^-t)/t),
 // with a short series for small t.
 //
-// Launch shape: lanes are frequencies; one pixel per group of
-// ceil(nfreq / 64) waves, several pixels per 256-thread block when nfreq
-// <= 128.  The walk's point data are read by all lanes of a pixel at once
-// (one broadcast per wave).
+// Launch shape: lanes are frequencies, one wave per 64 frequencies of one
+// pixel, up to four waves per block.  The walk's point data are read by all
+// lanes of a wave at once (one broadcast per wave).
 
 #include "mgx_internal.h"
 
@@ -30,8 +29,26 @@ struct RM<float> {
     static __device__ __forceinline__ float ex(float x) { return __expf(x); }
     static __device__ __forceinline__ float em1(float x) { return expm1f(x); }
     static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-    static __device__ __forceinline__ float erfc_(float x) { return erfcf(x); }
+    // erfc for x >= 0, branch-free (Numerical Recipes' Chebyshev form
+    // erfc(x) = t exp(-x^2 + P(t)), t = 1/(1 + x/2), fractional error
+    // < 1.2e-7), so the bins of a wave never diverge
+    static __device__ __forceinline__ float erfc_(float x)
+    {
+        const float t = __builtin_amdgcn_rcpf(fmaf(0.5f, x, 1.0f));
+        float p = 0.17087277f;
+        p = fmaf(p, t, -0.82215223f);
+        p = fmaf(p, t, 1.48851587f);
+        p = fmaf(p, t, -1.13520398f);
+        p = fmaf(p, t, 0.27886807f);
+        p = fmaf(p, t, -0.18628806f);
+        p = fmaf(p, t, 0.09678418f);
+        p = fmaf(p, t, 0.37409196f);
+        p = fmaf(p, t, 1.00002368f);
+        p = fmaf(p, t, -1.26551223f);
+        return t * __expf(fmaf(-x, x, p));
+    }
     static constexpr float series_below = 0.1f;
+    static constexpr float tiny = 1e-30f;  // smallest opacity sum used as a divisor
 };
 template <>
 struct RM<double> {
@@ -40,6 +57,7 @@ struct RM<double> {
     static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
     static __device__ __forceinline__ double erfc_(double x) { return erfc(x); }
     static constexpr double series_below = 1e-4;
+    static constexpr double tiny = 1e-290;
 };
 
 template <typename T>
@@ -70,21 +88,55 @@ __device__ __forceinline__ void lin_weights(T t, T &att, T &w0, T &w1)
     w1 = (T)1 - a;
 }
 
+// Per lane (frequency nu) and line l, the two frequency factors of the
+// offset x = (cd - rr w) / b, rr = nu / nu_l and cd = c (nu - nu_l) / nu_l,
+// computed once per pixel in double and kept in LDS (each lane reads only
+// its own entries).  Lines beyond what LDS holds are computed per point.
 template <typename T>
-__global__ __launch_bounds__(1024) void k_render_integrate(RenderArgs<T> a, int lanes_per_pixel,
-                                                         int pix_per_block)
+struct LineLane {
+    T cd, rr;
+};
+
+template <typename T, bool TAB>
+__global__ __launch_bounds__(256) void k_render_integrate(RenderArgs<T> a, int nslices)
 {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const int t = threadIdx.x;
-    const int pix = blockIdx.x * pix_per_block + t / lanes_per_pixel;
-    const int f = t % lanes_per_pixel;
+    const int nl = a.nlines;
+    // per-line intensity scale Iref_l / I_img, shared by the block
+    T *s_sc = (T *)smem;
+    for (int l = t; l < nl; l += blockDim.x) s_sc[l] = (T)(a.Iref[l] / a.I_img);
+    __syncthreads();
+    // 64 frequencies of one pixel per wave
+    const int64_t slice = ((int64_t)blockIdx.x * blockDim.x + t) >> 6;
+    const int64_t pix = slice / nslices;
+    const int f = (int)(slice % nslices) * 64 + (t & 63);
     const int npix = a.npx * a.npy;
     if (pix >= npix || f >= a.nfreq) return;
-    const int nl = a.nlines;
     const double nu = (a.nfreq == 1) ? a.f_min
                                      : a.f_min + (a.f_max - a.f_min) * f / (a.nfreq - 1);
     const double f_mid = 0.5 * (a.f_min + a.f_max);
+    LineLane<T> *tab = (LineLane<T> *)(smem + ((sizeof(T) * nl + 15) & ~(size_t)15)) +
+                       (size_t)t * nl;
+    auto line_lane = [&](int l) -> LineLane<T> {
+        LineLane<T> e;
+        if (TAB) {
+            e = tab[l];
+        } else {
+            e.cd = (T)(kC * (nu - a.nu_line[l]) / a.nu_line[l]);
+            e.rr = (T)(nu / a.nu_line[l]);
+        }
+        return e;
+    };
+    if (TAB)
+        for (int l = 0; l < nl; l++) {
+            LineLane<T> e;
+            e.cd = (T)(kC * (nu - a.nu_line[l]) / a.nu_line[l]);
+            e.rr = (T)(nu / a.nu_line[l]);
+            tab[l] = e;
+        }
     const int64_t o0 = a.off[pix], n = a.off[pix + 1] - o0;
-    float *out = a.img + (int64_t)pix * a.nfreq + f;
+    float *out = a.img + pix * a.nfreq + f;
     auto planck_n = [&](double nup) -> double {  // B_nu(Tcmb) / I_img
         const double r = nup / f_mid;
         return r * r * r / expm1(kH * nup / (kKB * a.Tcmb));
@@ -101,29 +153,43 @@ __global__ __launch_bounds__(1024) void k_render_integrate(RenderArgs<T> a, int 
     for (int64_t k = 0; k < n; k++) {
         const int p = a.walk[o0 + k];
         const double wd = a.w[p];
+        const T w = (T)wd;
         const T ib = (T)a.ib[p];
-        // opacity (sum over lines) and source function: the profile-weighted
-        // mean of the line source functions with weights relative to the
-        // nearest line, exp(-(x_l^2 - x_min^2)), so S keeps its value where
-        // every profile underflows
-        T chi1 = (T)0, x2min = (T)INFINITY;
+        const T *chi_p = a.chi + (int64_t)p * nl;
+        const T *S_p = a.S + (int64_t)p * nl;
+        // opacity (sum over lines) and the profile-weighted mean of the line
+        // source functions, in one pass; where every profile underflows the
+        // source function is the same mean with weights relative to the
+        // nearest line, exp(-(x_l^2 - x_min^2)) (the limit of eta / chi)
+        T chi1 = (T)0, sws = (T)0;
         for (int l = 0; l < nl; l++) {
-            const double nul = a.nu_line[l];
-            const T x = (T)(kC * (nu - nul) / nul - (nu / nul) * wd) * ib;
-            const T x2 = x * x;
-            x2min = x2 < x2min ? x2 : x2min;
-            chi1 += a.chi[(int64_t)p * nl + l] * RM<T>::ex(-x2);
+            const LineLane<T> e = line_lane(l);
+            const T x = (e.cd - e.rr * w) * ib;
+            const T c = chi_p[l] * RM<T>::ex(-(x * x));
+            chi1 += c;
+            sws += c * S_p[l] * s_sc[l];
         }
-        T sw = (T)0, sws = (T)0;
-        for (int l = 0; l < nl; l++) {
-            const double nul = a.nu_line[l];
-            const T x = (T)(kC * (nu - nul) / nul - (nu / nul) * wd) * ib;
-            // chi' already holds the profile's 1 / dnu = c / (nu_l b)
-            const T wt = a.chi[(int64_t)p * nl + l] * RM<T>::ex(-(x * x - x2min));
-            sw += wt;
-            sws += wt * a.S[(int64_t)p * nl + l] * (T)(a.Iref[l] / a.I_img);
+        T S1;
+        if (chi1 > RM<T>::tiny) {
+            S1 = sws / chi1;
+        } else {
+            T x2min = (T)INFINITY;
+            for (int l = 0; l < nl; l++) {
+                const LineLane<T> e = line_lane(l);
+                const T x = (e.cd - e.rr * w) * ib;
+                x2min = fmin(x2min, x * x);
+            }
+            T sw = (T)0;
+            sws = (T)0;
+            for (int l = 0; l < nl; l++) {
+                const LineLane<T> e = line_lane(l);
+                const T x = (e.cd - e.rr * w) * ib;
+                const T wt = chi_p[l] * RM<T>::ex(-(x * x - x2min));
+                sw += wt;
+                sws += wt * S_p[l] * s_sc[l];
+            }
+            S1 = sw > (T)0 ? sws / sw : (T)0;
         }
-        const T S1 = sw > (T)0 ? sws / sw : (T)0;
         if (k == 0) {
             I = (T)planck_n(nu * (1.0 - wd / kC));
         } else {
@@ -134,13 +200,15 @@ __global__ __launch_bounds__(1024) void k_render_integrate(RenderArgs<T> a, int 
             if (semi) {
                 const T ibb = (T)(1.0 / sqrt((a.b2[p0] + a.b2[p]) * 0.5));
                 const T b0 = (T)a.b[p0], b1 = (T)a.b[p];
+                const T w0 = (T)w0d;
+                const T *chi_q = a.chi + (int64_t)p0 * nl;
+                const T ddt = (T)dd;
                 for (int l = 0; l < nl; l++) {
-                    const double nul = a.nu_line[l];
-                    const double cd = kC * (nu - nul) / nul, rr = nu / nul;
-                    const T xa = (T)(cd - rr * w0d) * ibb;
-                    const T xb = (T)(cd - rr * wd) * ibb;
-                    const T dxb = (T)(-rr * dd) * ibb;
-                    const T cb = a.chi[(int64_t)p0 * nl + l] * b0 + a.chi[(int64_t)p * nl + l] * b1;
+                    const LineLane<T> e = line_lane(l);
+                    const T xa = (e.cd - e.rr * w0) * ibb;
+                    const T xb = (e.cd - e.rr * w) * ibb;
+                    const T dxb = -e.rr * ddt * ibb;
+                    const T cb = chi_q[l] * b0 + chi_p[l] * b1;
                     dt += dx * cb * spi4 * ibb * erf_diff_r<T>(xa, xb) * RM<T>::rcp(dxb);
                 }
             } else {
@@ -161,17 +229,20 @@ __global__ __launch_bounds__(1024) void k_render_integrate(RenderArgs<T> a, int 
 template <typename T>
 hipError_t launch_render_integrate(const RenderArgs<T> &a, hipStream_t s)
 {
-    const int lanes = ((a.nfreq + 63) / 64) * 64;
-    const int ppb = lanes >= 256 ? 1 : 256 / lanes;
-    const int threads = lanes >= 256 ? lanes : 256;
-    const int npix = a.npx * a.npy;
-    const int blocks = (npix + ppb - 1) / ppb;
-    if (threads > 256) {
-        // one pixel with more than 256 frequencies: a larger block
-        k_render_integrate<T><<<npix, lanes, 0, s>>>(a, lanes, 1);
-    } else {
-        k_render_integrate<T><<<blocks, threads, 0, s>>>(a, lanes, ppb);
-    }
+    const int nslices = (a.nfreq + 63) / 64;
+    const int64_t waves = (int64_t)a.npx * a.npy * nslices;
+    const size_t head = (sizeof(T) * a.nlines + 15) & ~(size_t)15;
+    const size_t per_thread = sizeof(LineLane<T>) * (size_t)a.nlines;
+    // the largest block (256, 128 or 64 threads) whose line tables fit 40 KB
+    int threads = 256;
+    while (threads > 64 && head + per_thread * threads > (40u << 10)) threads /= 2;
+    const bool tab = head + per_thread * threads <= (64u << 10);
+    const size_t lds = tab ? head + per_thread * threads : head;
+    const int64_t blocks = (waves * 64 + threads - 1) / threads;
+    if (tab)
+        k_render_integrate<T, true><<<(unsigned)blocks, threads, lds, s>>>(a, nslices);
+    else
+        k_render_integrate<T, false><<<(unsigned)blocks, threads, lds, s>>>(a, nslices);
     return hipGetLastError();
 }
 

@@ -291,12 +291,38 @@ __global__ void k_render_project(RenderGeom g)
     g.w[j] = (g.vx[j] * g.d[0] + g.vy[j] * g.d[1]) + g.vz[j] * g.d[2];
 }
 
-// min / max of u and v (exact operations: any order gives the same result)
-__global__ void k_render_extent(int N, const double *u, const double *v, double *ext)
+// order-preserving map of a double to unsigned 64 bits
+__device__ __forceinline__ unsigned long long ordered(double x)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+    return (b & 0x8000000000000000ull) ? ~b : (b | 0x8000000000000000ull);
+}
+
+__device__ __forceinline__ double unordered(unsigned long long k)
+{
+    const unsigned long long b = (k & 0x8000000000000000ull) ? (k & 0x7fffffffffffffffull) : ~k;
+    return __longlong_as_double((long long)b);
+}
+
+// min / max of u and v over all points (exact operations: any order gives
+// the same result).  Blocks reduce their share, then combine through atomic
+// min / max on order-preserving keys held in the ext slots; a last one-thread
+// kernel turns the keys back into doubles.
+__global__ void k_render_extent_init(unsigned long long *key)
+{
+    if (threadIdx.x == 0) {
+        key[0] = ~0ull;  // min u
+        key[1] = 0ull;   // max u
+        key[2] = ~0ull;  // min v
+        key[3] = 0ull;   // max v
+    }
+}
+
+__global__ void k_render_extent(int N, const double *u, const double *v, unsigned long long *key)
 {
     __shared__ double r[4][256];
     double a = INFINITY, b = -INFINITY, c = INFINITY, d = -INFINITY;
-    for (int j = threadIdx.x; j < N; j += 256) {
+    for (int j = blockIdx.x * 256 + threadIdx.x; j < N; j += gridDim.x * 256) {
         a = fmin(a, u[j]);
         b = fmax(b, u[j]);
         c = fmin(c, v[j]);
@@ -316,7 +342,20 @@ __global__ void k_render_extent(int N, const double *u, const double *v, double 
         }
         __syncthreads();
     }
-    if (threadIdx.x < 4) ext[threadIdx.x] = r[threadIdx.x][0];
+    if (threadIdx.x == 0) {
+        atomicMin(&key[0], ordered(r[0][0]));
+        atomicMax(&key[1], ordered(r[1][0]));
+        atomicMin(&key[2], ordered(r[2][0]));
+        atomicMax(&key[3], ordered(r[3][0]));
+    }
+}
+
+__global__ void k_render_extent_final(unsigned long long *key)
+{
+    if (threadIdx.x < 4) {
+        const double x = unordered(key[threadIdx.x]);
+        ((double *)key)[threadIdx.x] = x;
+    }
 }
 
 struct PixGrid {
@@ -334,13 +373,6 @@ __device__ __forceinline__ PixGrid pix_grid(const RenderGeom &g)
     if (g.h > R) R = g.h;
     p.R2 = R * R;
     return p;
-}
-
-// order-preserving map of a double to unsigned 64 bits
-__device__ __forceinline__ unsigned long long ordered(double x)
-{
-    const unsigned long long b = (unsigned long long)__double_as_longlong(x);
-    return (b & 0x8000000000000000ull) ? ~b : (b | 0x8000000000000000ull);
 }
 
 // Entry search, scattered from the boundary points: every boundary point
@@ -391,7 +423,11 @@ hipError_t launch_render_geometry(RenderGeom &g, hipStream_t s)
 {
     const int npix = g.npx * g.npy;
     k_render_project<<<(g.N + 255) / 256, 256, 0, s>>>(g);
-    k_render_extent<<<1, 256, 0, s>>>(g.N, g.u, g.v, g.ext);
+    unsigned long long *key = (unsigned long long *)g.ext;
+    const int eblocks = std::min(1024, std::max(1, (g.N + 255) / 256));
+    k_render_extent_init<<<1, 64, 0, s>>>(key);
+    k_render_extent<<<eblocks, 256, 0, s>>>(g.N, g.u, g.v, key);
+    k_render_extent_final<<<1, 64, 0, s>>>(key);
     k_render_entry_init<<<(npix + 255) / 256, 256, 0, s>>>(npix, g.key, g.entry);
     k_render_entry<<<(g.N + 255) / 256, 256, 0, s>>>(g, 0);
     k_render_entry<<<(g.N + 255) / 256, 256, 0, s>>>(g, 1);
