@@ -327,6 +327,7 @@ def bench_batch(args, mgx, torch):
                                  for k in range(16) if st["class_items"][k]]},
         "generate_seconds": gen_s, "prepare_seconds": prep_s,
         "converged": {"seconds": conv_s, "models_converged": nconv, "tol": tol,
+                      "seconds_to_last_converged": b.stats()["last_converged_seconds"],
                       "replays": int(its.max()), "iterations_median": float(np.median(its)),
                       "iterations_max": int(its.max()), "not_converged": stuck},
         "roofline": roof,

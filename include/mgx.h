@@ -281,6 +281,7 @@ typedef struct {
     int class_chunk[MGX_BATCH_CLASSES];    /* tuned LDS records per half            */
     double tune_seconds;      /* time spent tuning the schedule                  */
     double iterate_seconds;   /* wall time of the last mgx_batch_iterate        */
+    double last_converged_seconds;  /* ... until its last converged model stopped */
     /* work of one iteration over all models (lanes = lines x bins of a model) */
     int64_t updates_per_iteration;  /* sum of N x rays x lanes                  */
     int64_t lane_records;           /* sum of lanes x trace records             */

@@ -442,9 +442,13 @@ extern "C" mgx_status mgx_batch_iterate(mgx_batch *b, double tol, int max_iter, 
     batch_push_mask(b);
     int replays = 0;
     std::vector<int> finished;
+    b->st.last_converged_seconds = 0.0;
     while (std::any_of(b->runs.begin(), b->runs.end(), [](const BatchRun &r) { return r.active; })) {
+        finished.clear();
         batch_step(b, finished);
         replays++;
+        for (int i : finished)
+            if (b->runs[i].status == MGX_OK) b->st.last_converged_seconds = wall_seconds() - t0;
     }
     b->st.iterate_seconds = wall_seconds() - t0;
     b->st.iterations = replays;

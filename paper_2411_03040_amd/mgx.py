@@ -59,7 +59,8 @@ class BatchStats(C.Structure):
                 ("class_items", C.c_int * 16), ("class_threads", C.c_int * 16),
                 ("class_chunk", C.c_int * 16),
                 ("tune_seconds", C.c_double),
-                ("iterate_seconds", C.c_double), ("updates_per_iteration", C.c_int64),
+                ("iterate_seconds", C.c_double), ("last_converged_seconds", C.c_double),
+                ("updates_per_iteration", C.c_int64),
                 ("lane_records", C.c_int64), ("lane_semi", C.c_int64),
                 ("lane_origin_pairs", C.c_int64), ("fs_launches", C.c_int64),
                 ("fs_ms_total", C.c_double), ("fs_ms_last", C.c_double)]
