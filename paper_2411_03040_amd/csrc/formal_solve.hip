@@ -57,6 +57,13 @@ struct FM<float> {
     {
         return __builtin_amdgcn_exp2f(-(xs * xs));
     }
+    // chi' exp(-x^2) as exp2(log2 chi' - xs^2), xs = x sqrt(log2 e): the
+    // staged line record carries log2 chi'
+    static __device__ __forceinline__ float log_scale(float chi) { return __builtin_amdgcn_logf(chi); }
+    static __device__ __forceinline__ float chi_phi(float lchi, float xs)
+    {
+        return __builtin_amdgcn_exp2f(fmaf(-xs, xs, lchi));
+    }
     static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
     // erfc for x >= 0, branch-free: the Chebyshev-fitted form of Numerical
     // Recipes (Press et al., 2nd ed., Sec. 6.2, "erfcc"),
@@ -103,6 +110,11 @@ struct FM<float> {
 template <>
 struct FM<double> {
     static __device__ __forceinline__ double phi_scaled(double x) { return exp(-(x * x)); }
+    static __device__ __forceinline__ double log_scale(double chi) { return chi; }
+    static __device__ __forceinline__ double chi_phi(double chi, double x)
+    {
+        return chi * exp(-(x * x));
+    }
     static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
     static constexpr double erf_scale = 1.0;
     static __device__ __forceinline__ double erfc_scaled(double x) { return erfc(x); }
@@ -148,7 +160,7 @@ struct alignas(2 * sizeof(T)) MetaB {
 };
 template <typename T>
 struct alignas(4 * sizeof(T)) LineRec {
-    T chi, S, cb, rw;
+    T lchi, S, cb, rw;  // lchi: chi' in the form FM::chi_phi takes (log2 chi' in FP32)
 };
 
 struct LDSLayout {
@@ -339,7 +351,7 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
             // (the profile is evaluated even where both segments at Q are
             // semi-analytic and never read it: a branch around it measured
             // 12 % slower)
-            const T chiQ = lr.chi * FM<T>::phi_scaled(uQ * ma.ib);
+            const T chiQ = FM<T>::chi_phi(lr.lchi, uQ * ma.ib);
             if (far_end)
                 s.eps = bdy_I(dvQ);
             else
@@ -396,9 +408,10 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
                 const MetaB<T> mb = s_b[e];
                 const int64_t idx = (int64_t)mb.p * nl + l0 + li;
                 LineRec<T> lr;
-                lr.chi = chi[idx];
+                const T chi_l = chi[idx];
+                lr.lchi = FM<T>::log_scale(chi_l);
                 lr.S = S[idx];
-                lr.cb = lr.chi * mb.b;
+                lr.cb = chi_l * mb.b;
                 lr.rw = mb.rw;
                 s_line[e * nlc + li] = lr;
             }
