@@ -103,11 +103,22 @@ def alu_roofline(ctx, m, ms_per_launch, precision):
             lanes * m.npoints * npairs * FLOP_PER_ORIGIN_ROW)
     achieved = flop / (ms_per_launch * 1e-3) / 1e12
     peak = PEAK_FP32_TFLOPS if precision == "fp32" else PEAK_FP64_TFLOPS
+    # algorithmic HBM bytes of one launch: the packed trace once, the trace
+    # offsets, the per-point line table (chi', S' in the solve precision)
+    # and per-point widths once, J-bar and Lambda* written once (FP64)
+    tsz = 4 if precision == "fp32" else 8
+    rec_bytes = 16 if precision == "fp32" else 32
+    alg_bytes = (c["total_records"] * rec_bytes + (m.npoints * m.nrays + 1) * 8 +
+                 m.npoints * m.nlines * 2 * tsz + m.npoints * 2 * tsz +
+                 m.npoints * m.nlines * 2 * 8)
     return {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
             "frac": round(achieved / peak, 4), "traffic": None,
             "kernel": "k_formal_solve<%s>" % ("float" if precision == "fp32" else "double"),
             "flop_per_launch": flop, "elements_per_launch": elements,
-            "semi_segments": c["semi_segments"], "ms_per_launch": round(ms_per_launch, 4)}
+            "semi_segments": c["semi_segments"], "ms_per_launch": round(ms_per_launch, 4),
+            "algorithmic_bytes_per_launch": alg_bytes,
+            "hbm_GBps_algorithmic": round(alg_bytes / (ms_per_launch * 1e-3) / 1e9, 1),
+            "hbm_frac_algorithmic": round(alg_bytes / (ms_per_launch * 1e-3) / 8e12, 5)}
 
 
 def committed_traffic(workload):
@@ -486,6 +497,13 @@ def main():
     fs_ms = c["fs_ms_total"] / max(c["fs_launches"], 1)
     updates = m.npoints * m.nrays * m.nlines * m.nbins
     value = updates / (ms_step * 1e-3)
+    # the formal solution alone (line coefficients excluded, trace cached):
+    # median of per-launch event times over 10 more steps, outside the timing
+    fs_each = []
+    for i in range(10):
+        step(args.warmup + args.steps + i)
+        fs_each.append(ctx.counters()["fs_ms_last"])
+    fs_median = float(np.median(fs_each))
     if args.profile_steps:
         # calibration for hardware byte counters: a plain elementwise kernel
         # that reads 256 MiB and writes 256 MiB (larger than every cache level
@@ -522,6 +540,8 @@ def main():
     roof = alu_roofline(ctx, m, fs_ms, args.precision)
     if args.precision == "fp32":
         roof["traffic"] = committed_traffic(args.workload)
+        if roof["traffic"]:
+            roof["hbm_GBps_measured"] = round(roof["traffic"] / (fs_ms * 1e-3) / 1e9, 1)
     out = {
         "metric": METRIC, "value": value, "unit": "updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
@@ -533,6 +553,9 @@ def main():
         "formal_solve_ms": fs_ms, "trace_ms": trace_ms,
         "render": render,
         "ray_pair_solves_per_s": value / 2.0,
+        "formal_solve_only": {"ms_median": fs_median,
+                              "updates_per_s": updates / (fs_median * 1e-3),
+                              "ray_pair_solves_per_s": updates / (fs_median * 1e-3) / 2.0},
         "roofline": roof,
     }
     del ctx
