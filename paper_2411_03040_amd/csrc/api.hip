@@ -247,6 +247,17 @@ extern "C" mgx_status mgx_load_model(mgx_ctx *ctx, const mgx_model *m)
         ctx->sync();
     }
     upload(ctx, ctx->pos, m->pos, 3 * (size_t)N);
+    {
+        std::vector<double> p4(4 * (size_t)N);
+        for (int i = 0; i < N; i++) {
+            p4[4 * (size_t)i + 0] = m->pos[i];
+            p4[4 * (size_t)i + 1] = m->pos[(size_t)N + i];
+            p4[4 * (size_t)i + 2] = m->pos[2 * (size_t)N + i];
+            p4[4 * (size_t)i + 3] = 0.0;
+        }
+        upload(ctx, ctx->pos4, p4.data(), p4.size());
+        ctx->sync();  // the host copy goes out of scope
+    }
     upload(ctx, ctx->vel, m->vel, 3 * (size_t)N);
     upload(ctx, ctx->nbs_off, m->nbs_off, (size_t)N + 1);
     upload(ctx, ctx->nbs, m->nbs, (size_t)m->nbs_off[N]);
@@ -342,6 +353,7 @@ extern "C" mgx_status mgx_trace_rays(mgx_ctx *ctx, int64_t *total_records_out)
     a.vx = vel;
     a.vy = vel + ctx->N;
     a.vz = vel + 2 * (size_t)ctx->N;
+    a.p4 = (const double4 *)ctx->pos4.p;
     a.nbs_off = ctx->nbs_off.as<int32_t>();
     a.nbs = ctx->nbs.as<int32_t>();
     a.bdy = ctx->bdy.as<uint8_t>();

@@ -52,6 +52,7 @@ struct alignas(16) Rec<double> {
 struct TraceArgs {
     int dim, N, R;
     const double *x, *y, *z, *vx, *vy, *vz;
+    const double4 *p4;     // [N] {x, y, z, 0}: one gather per neighbour candidate
     const int32_t *nbs_off, *nbs;
     const uint8_t *bdy;
     const double *ray_dir;
@@ -121,7 +122,7 @@ hipError_t launch_pack_trace(int64_t n, const int32_t *idx, const uint8_t *semi,
 hipError_t launch_line_coeffs(const LineArgs &a, hipStream_t s);
 template <typename T>
 hipError_t launch_formal_solve(const FSArgs<T> &a, hipStream_t s);
-// batched: persistent grid over (model, origin, chunk) items from a queue
+// batched: one workgroup per (model, origin, line chunk) item of a lane class
 template <typename T>
 size_t formal_solve_lds(int ch, int nlc, int nthreads);
 template <typename T>

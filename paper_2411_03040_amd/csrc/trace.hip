@@ -106,9 +106,10 @@ __global__ __launch_bounds__(256) void k_trace3d(TraceArgs a)
             const int q = qb + l16;
             if (q < q1) {
                 const int j = a.nbs[q];
-                const double ddx = a.x[j] - xo;
-                const double ddy = a.y[j] - yo;
-                const double ddz = a.z[j] - zo;
+                const double4 pj = a.p4[j];
+                const double ddx = pj.x - xo;
+                const double ddy = pj.y - yo;
+                const double ddz = pj.z - zo;
                 const double Zj = (ddx * nx + ddy * ny) + ddz * nz;
                 if (Zj > Zc) {
                     const double ex = ddx - Zj * nx;
