@@ -303,6 +303,9 @@ extern "C" mgx_status mgx_load_model(mgx_ctx *ctx, const mgx_model *m)
                                ctx->b2.as<double>(), ctx->b.as<double>(), ctx->bf.as<float>(),
                                ctx->ibf.as<float>(), ctx->bd.as<double>(), ctx->ibd.as<double>(),
                                ctx->stream));
+    ctx->vel4.ensure(sizeof(double) * 4 * (size_t)N);
+    HIPCHK(launch_pack_vel4(N, ctx->vel.as<double>(), ctx->b2.as<double>(),
+                            (double4 *)ctx->vel4.p, ctx->stream));
     ctx->xf.ensure(sizeof(double) * m->nbins);
     ctx->W.ensure(sizeof(double) * m->nbins);
     HIPCHK(launch_bin_table(m->nbins, m->xmax, ctx->xf.as<double>(), ctx->W.as<double>(),
@@ -354,6 +357,7 @@ extern "C" mgx_status mgx_trace_rays(mgx_ctx *ctx, int64_t *total_records_out)
     a.vy = vel + ctx->N;
     a.vz = vel + 2 * (size_t)ctx->N;
     a.p4 = (const double4 *)ctx->pos4.p;
+    a.v4 = (const double4 *)ctx->vel4.p;
     a.nbs_off = ctx->nbs_off.as<int32_t>();
     a.nbs = ctx->nbs.as<int32_t>();
     a.bdy = ctx->bdy.as<uint8_t>();

@@ -139,6 +139,7 @@ struct mgx_ctx {
 
     DMem pos, vel, nbs_off, nbs, bdy, T, vturb2, nspec, ncoll, ray_dir, ray_w, antipode;
     DMem pos4;  // positions as {x, y, z, 0} for the neighbour gathers of the walk
+    DMem vel4;  // {vx, vy, vz, b^2} per point, one load per walk step
     DMem E, g, up, lo, A, nu, cu, cl, K0;
     DMem b2, b, bf, ibf, bd, ibd, xf, W;
     DMem Bul, Blu, hnu4pi, chiscale, Iref, acmb;

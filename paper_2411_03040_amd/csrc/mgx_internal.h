@@ -53,6 +53,7 @@ struct TraceArgs {
     int dim, N, R;
     const double *x, *y, *z, *vx, *vy, *vz;
     const double4 *p4;     // [N] {x, y, z, 0}: one gather per neighbour candidate
+    const double4 *v4;     // [N] {vx, vy, vz, b2}: one load per step
     const int32_t *nbs_off, *nbs;
     const uint8_t *bdy;
     const double *ray_dir;
@@ -116,6 +117,8 @@ hipError_t launch_point_widths(int N, const double *T, const double *vturb2, dou
                                double *b2, double *b, float *bf, float *ibf_scaled,
                                double *bd, double *ibd, hipStream_t s);
 hipError_t launch_trace(const TraceArgs &a, bool fill, hipStream_t s);
+hipError_t launch_pack_vel4(int N, const double *vel, const double *b2, double4 *out,
+                            hipStream_t s);
 hipError_t launch_pack_trace(int64_t n, const int32_t *idx, const uint8_t *semi,
                              const double *dx, const double *dv, const double *ibb,
                              double inv_L, bool fp32, void *out, hipStream_t s);

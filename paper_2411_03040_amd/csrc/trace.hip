@@ -64,10 +64,9 @@ __device__ __forceinline__ bool use_semi(double dv0, double b20, double dv1, dou
 template <bool FILL>
 __device__ __forceinline__ void emit(const TraceArgs &a, int64_t pos, int j, double Z,
                                      double dv, double Zprev, double dvprev, double b2prev,
-                                     unsigned long long &nsemi)
+                                     unsigned long long &nsemi, double b2j)
 {
     if (!FILL) return;
-    const double b2j = a.b2[j];
     const bool semi = use_semi(dvprev, b2prev, dv, b2j, a.thr);
     a.r_idx[pos] = j;
     a.r_Z[pos] = Z;
@@ -142,13 +141,14 @@ __global__ __launch_bounds__(256) void k_trace3d(TraceArgs a)
             if (FILL && l16 == 0 && !a.bdy[c]) atomicAdd(&a.cnt->holes, 1ull);
             break;
         }
-        const double dv = ((a.vx[bj] - vxo) * nx + (a.vy[bj] - vyo) * ny) + (a.vz[bj] - vzo) * nz;
-        if (l16 == 0) emit<FILL>(a, base + n, bj, bZ, dv, Zc, dvc, b2c, nsemi);
+        const double4 vj = a.v4[bj];
+        const double dv = ((vj.x - vxo) * nx + (vj.y - vyo) * ny) + (vj.z - vzo) * nz;
+        if (l16 == 0) emit<FILL>(a, base + n, bj, bZ, dv, Zc, dvc, b2c, nsemi, vj.w);
         n++;
         c = bj;
         Zc = bZ;
         dvc = dv;
-        if (FILL) b2c = a.b2[c];
+        if (FILL) b2c = vj.w;
         if (a.bdy[c]) break;
     }
     if (l16 == 0) {
@@ -180,7 +180,7 @@ __global__ __launch_bounds__(256) void k_trace1d(TraceArgs a)
     auto rec = [&](int k, double s) {
         const double Z = s - so;
         const double dv = a.vx[k] * (s / a.x[k]) - vo * mu;
-        emit<FILL>(a, base + n, k, Z, dv, Zp, dvp, b2p, nsemi);
+        emit<FILL>(a, base + n, k, Z, dv, Zp, dvp, b2p, nsemi, FILL ? a.b2[k] : 0.0);
         n++;
         Zp = Z;
         dvp = dv;
@@ -224,6 +224,21 @@ hipError_t launch_trace(const TraceArgs &a, bool fill, hipStream_t s)
         else
             k_trace3d<false><<<blocks, 256, 0, s>>>(a);
     }
+    return hipGetLastError();
+}
+
+// {vx, vy, vz, b^2} per point for the walk step (one 32-byte load).
+__global__ void k_pack_vel4(int N, const double *vel, const double *b2, double4 *out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= N) return;
+    out[i] = make_double4(vel[i], vel[(size_t)N + i], vel[2 * (size_t)N + i], b2[i]);
+}
+
+hipError_t launch_pack_vel4(int N, const double *vel, const double *b2, double4 *out,
+                            hipStream_t s)
+{
+    k_pack_vel4<<<(N + 255) / 256, 256, 0, s>>>(N, vel, b2, out);
     return hipGetLastError();
 }
 
