@@ -141,13 +141,14 @@ __device__ __forceinline__ T erf_diff(T a, T b)
 }
 
 // Per staged record: meta A (dv, 1/b scaled for the profile, half the
-// length of the segment ending here -- negative when that segment takes the
+// length of the segment ending here -- -1 when that segment takes the
 // semi-analytic form -- and its 1/b-bar times erf_scale), read by the solve
 // as one broadcast; meta B (b, point index, the semi-analytic factor below)
-// only feeds the line gather.  Per record and line of the
-// chunk: chi', S', chi' b (the semi-analytic segment's weight) and, for a
-// semi-analytic segment, the lane-independent factor of its optical depth,
-// dx sqrt(pi)/4 / (dv_Q - dv_P).
+// only feeds the line gather.  Per record and line of the chunk: chi' (in
+// the form chi_phi takes), S', chi' b (the semi-analytic segment's weight)
+// and, for a semi-analytic segment, the lane-independent factor of its
+// optical depth, dx sqrt(pi)/4 / (dv_Q - dv_P), which the trace computed in
+// FP64 and stored in place of the segment length.
 template <typename T>
 struct alignas(4 * sizeof(T)) MetaA {
     T dv, ib, hdx, ibb;
@@ -286,7 +287,6 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
     const T cb_o = chi[ol] * bpt[o];
     const T tau_floor = (T)a.tau_floor;
     const T half = (T)0.5;
-    const T spi2 = (T)(kSqrtPi / 2.0);
 
     auto bdy_I = [&](T dv) -> T {
         const T r = k1 * ((T)1 + dv * inv_c);
@@ -307,8 +307,8 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
     // length, so the trapezoid needs no factor 1/2.  Semi-analytic:
     //   dt = dx sqrt(pi)/4 (cb_P + cb_Q) (erf x_Q - erf x_P) / (b-bar (x_Q - x_P))
     // with x = u / b-bar and x_Q - x_P = (dvQ - dvP) k1 / b-bar, so b-bar
-    // cancels outside the erf arguments; dx sqrt(pi)/4 / (dvQ - dvP) is
-    // staged with the record (rw).
+    // cancels outside the erf arguments; dx sqrt(pi)/4 / (dvQ - dvP) comes
+    // with the record (rw).
     auto segment = [&](HalfState<T> &st, T chiQ, T uQ, T cbQ) -> T {
         T dt;
         if (signbit(st.hdx)) {
@@ -382,23 +382,15 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
                 MetaA<T> ma;
                 ma.dv = rc.dv;
                 ma.ib = ibpt[p];
-                ma.hdx = rc.ps < 0 ? -(rc.dx * half) : rc.dx * half;
+                // half the trapezoid's length, or -1 marking a semi-analytic
+                // segment (whose record carries its optical-depth factor)
+                ma.hdx = rc.ps < 0 ? (T)-1 : rc.dx * half;
                 ma.ibb = rc.ibb * (T)FM<T>::erf_scale;
                 s_a[t] = ma;
                 MetaB<T> mb;
                 mb.b = bpt[p];
                 mb.p = p;
-                // semi-analytic: dx sqrt(pi)/4 / (dv_prev - dv) with the walk
-                // predecessor's dv read from the trace (the origin's 0 before
-                // the first record).  The re-read costs trace traffic (the
-                // neighbouring lane's streamed load does not stay in L2) but
-                // measured faster than taking it from LDS after a barrier or
-                // from the neighbouring lane, which serialise the staging.
-                mb.rw = (T)0;
-                if (rc.ps < 0) {
-                    const T dv_prev = k > 0 ? rec[base + k - 1].dv : (T)0;
-                    mb.rw = rc.dx * half * spi2 * FM<T>::rcp(dv_prev - rc.dv);
-                }
+                mb.rw = rc.ps < 0 ? rc.dx : (T)0;
                 s_b[t] = mb;
             }
             __syncthreads();

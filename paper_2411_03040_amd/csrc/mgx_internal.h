@@ -32,9 +32,10 @@ struct Counters {
 };
 
 // Packed trace record used by the formal solution: point index with the
-// semi-analytic flag in bit 31, the segment length (scaled by 1/L_unit)
-// from the previous record (or the origin), the projected velocity
-// difference to the origin, and 1/b-bar of that segment.
+// semi-analytic flag in bit 31; for a trapezoidal segment its length from
+// the previous record (or the origin), for a semi-analytic one
+// dx sqrt(pi)/4 / (dv_prev - dv) (both scaled by 1/L_unit); the projected
+// velocity difference to the origin; 1/b-bar of the segment.
 template <typename T>
 struct Rec;
 template <>

@@ -71,7 +71,10 @@ __device__ __forceinline__ void emit(const TraceArgs &a, int64_t pos, int j, dou
     a.r_idx[pos] = j;
     a.r_Z[pos] = Z;
     a.r_dv[pos] = dv;
-    a.r_dx[pos] = Z - Zprev;
+    // the segment length, or for a semi-analytic segment the lane-independent
+    // factor of its optical depth, dx sqrt(pi)/4 / (dv_prev - dv) (the solve
+    // needs nothing else of its length)
+    a.r_dx[pos] = semi ? (Z - Zprev) * (kSqrtPi / 4.0) / (dvprev - dv) : Z - Zprev;
     a.r_ibb[pos] = 1.0 / sqrt((b2prev + b2j) * 0.5);
     a.r_semi[pos] = semi ? 1 : 0;
     nsemi += semi ? 1 : 0;
