@@ -382,7 +382,9 @@ typedef struct {
    (0: the device's total memory), render slots 1..8. */
 mgx_status mgx_server_create(mgx_server **out, int device, const mgx_options *opt,
                              uint64_t hbm_budget, int render_slots);
-/* Stop the workers (requests not finished end with MGX_ESTATE) and free. */
+/* Stop the workers (requests not finished end with MGX_ESTATE) and free.
+   No other call on `s` may be in progress or follow: a thread blocked in
+   mgx_server_wait must have returned first. */
 void mgx_server_destroy(mgx_server *s);
 const char *mgx_server_last_error(const mgx_server *s);
 

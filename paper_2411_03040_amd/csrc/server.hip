@@ -193,8 +193,21 @@ void iterate_worker(mgx_server *s)
                          run.status == MGX_OK ? std::string() : std::string("converge failed"));
                 s->conv_running[i] = nullptr;
             }
-        } catch (const Err &e) {
-            // a device or runtime failure ends every converge request in flight
+        } catch (...) {
+            // a device, runtime or host failure ends every converge request in
+            // flight (no exception may leave the worker thread)
+            mgx_status st = MGX_EHIP;
+            std::string msg = "unexpected internal error";
+            try {
+                throw;
+            } catch (const Err &e) {
+                st = e.st;
+                msg = e.msg;
+            } catch (const std::bad_alloc &) {
+                st = MGX_ENOMEM;
+                msg = "host allocation failed";
+            } catch (...) {
+            }
             std::lock_guard<std::mutex> lk(s->mu);
             for (int i = 0; i < M; i++) {
                 if (b->runs[i].active) {
@@ -202,13 +215,13 @@ void iterate_worker(mgx_server *s)
                     b->host_active[i] = 0;
                 }
                 if (s->conv_running[i]) {
-                    complete(s, s->conv_running[i], e.st, e.msg);
+                    complete(s, s->conv_running[i], st, msg);
                     s->conv_running[i] = nullptr;
                 }
             }
             try {
                 batch_push_mask(b);
-            } catch (const Err &) {
+            } catch (...) {
             }
         }
     }
@@ -270,6 +283,9 @@ void render_worker(mgx_server *s, int j)
         } catch (const std::bad_alloc &) {
             status = MGX_ENOMEM;
             msg = "host allocation failed";
+        } catch (...) {
+            status = MGX_EHIP;
+            msg = "unexpected internal error";
         }
         std::lock_guard<std::mutex> lk(s->mu);
         s->render_busy += s->now() - t;
