@@ -204,9 +204,21 @@ def cpu_baseline(m, seconds, gpu_J=None, converged=None):
             break
         n = min(m.npoints, int(n * max(2.0, 0.3 * seconds / max(t, 1e-3))))
     rate = n * m.nrays * lanes / t
-    out = {"value": rate, "unit": "updates/s", "cores": oracle.num_threads(), "kind": "oracle",
+    cores = oracle.num_threads()
+    out = {"value": rate, "unit": "updates/s", "cores": cores, "kind": "oracle",
            "sample": f"formal solution (line coefficients + all rays, lines, bins) of {n} "
                      f"seeded origins of the same model from LTE populations, {t:.1f} s"}
+    # the same origins' first few on one thread: the single-core rate
+    n1 = max(1, min(n, int(n * 0.1 * seconds / max(t * cores, 1e-3))))
+    oracle.set_num_threads(1)
+    try:
+        t0 = time.perf_counter()
+        orc.solve_origins(pops, origins[:n1])
+        t1 = time.perf_counter() - t0
+    finally:
+        oracle.set_num_threads(cores)
+    out["single_thread_value"] = n1 * m.nrays * lanes / t1
+    out["single_thread_sample"] = f"the first {n1} of those origins on one thread, {t1:.1f} s"
     if gpu_J is not None:
         g = np.asarray(gpu_J)[origins]
         out["gpu_Jbar_max_rel_err"] = float(np.max(np.abs(g - J) / np.abs(J)))

@@ -76,6 +76,7 @@ def lib():
         L.orc_ng.argtypes = [C.c_int, C.c_int64, P, P, P]
         L.orc_iterate.argtypes = [P, P, C.c_double, C.c_int, C.c_int, C.c_int, P, P, P]
         L.orc_num_threads.restype = C.c_int
+        L.orc_set_num_threads.argtypes = [C.c_int]
         L.orc_render_pixel.argtypes = [P, P, P, P, C.c_int, C.c_int, C.c_double, C.c_double,
                                        C.c_int, C.c_int, C.c_int, P, P, C.c_int, P]
         _lib = L
@@ -116,6 +117,11 @@ def erf_difference(a, b):
 
 def num_threads():
     return lib().orc_num_threads()
+
+
+def set_num_threads(n):
+    """Threads of the oracle's parallel loops (n >= 1)."""
+    lib().orc_set_num_threads(int(n))
 
 
 def ng(hist):

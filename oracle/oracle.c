@@ -59,6 +59,16 @@ int orc_num_threads(void)
 #endif
 }
 
+/* Threads used by later parallel loops (n >= 1). */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------
  * Line width (line width equation):  delta nu = (nu / c) sqrt(2 k T / m +
  * v_turb^2).  b^2 = 2 k T / m + v_turb^2 is the squared Doppler speed.

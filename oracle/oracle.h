@@ -101,5 +101,6 @@ void orc_render_pixel(const orc_model *m, const double *chi_ij, const double *S,
                       int *nwalk);
 
 int orc_num_threads(void);
+void orc_set_num_threads(int n);
 
 #endif

@@ -758,3 +758,21 @@ def test_render_steep_gradient_column_closed_form():
         exp_I = Bg * math.exp(-tau) + S[0, 0] * (1 - math.exp(-tau))
         assert abs(I[0, i] / exp_I - 1) < 1e-9, (i, I[0, i], exp_I, tau)
     assert max(walks[0].size for _ in [0]) == n
+
+
+def test_oracle_threads_do_not_change_results(orc):
+    """The oracle's origins are independent: one thread and all threads give
+    the same J-bar and Lambda* bit for bit (the single-core timing rests on
+    this)."""
+    m = synth.tiny_cloud(npoints=200, seed=21, k=12, nside=2)
+    o = orc.Oracle(m)
+    pops = o.lte()
+    n = orc.num_threads()
+    J_all, L_all = o.solve_origins(pops)
+    orc.set_num_threads(1)
+    try:
+        J_one, L_one = o.solve_origins(pops)
+    finally:
+        orc.set_num_threads(n)
+    assert orc.num_threads() == n
+    assert np.array_equal(J_all, J_one) and np.array_equal(L_all, L_one)
