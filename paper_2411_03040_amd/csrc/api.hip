@@ -507,7 +507,7 @@ extern "C" mgx_status mgx_set_lte_populations(mgx_ctx *ctx)
 }
 
 void mgxh::line_coeffs_into(mgx_ctx *ctx, const double *pops, void *chiT, void *ST,
-                            double *S64, Counters *cnt, hipStream_t s)
+                            double *S64, Counters *cnt, hipStream_t s, double S_unit)
 {
     LineArgs la{};
     la.N = ctx->N;
@@ -525,6 +525,7 @@ void mgxh::line_coeffs_into(mgx_ctx *ctx, const double *pops, void *chiT, void *
     la.chiscale = ctx->chiscale.as<double>();
     la.Iref = ctx->Iref.as<double>();
     la.chi_min = ctx->opt.chi_min;
+    la.S_unit = S_unit;
     la.S64 = S64;
     la.chiT = chiT;
     la.ST = ST;
@@ -972,8 +973,10 @@ void mgxh::render_image(mgx_ctx *ctx, RenderBufs &rb, const double *pops, hipStr
     rb.ST.ensure(tsz * ctx->nrad());
     rb.S64.ensure(sizeof(double) * ctx->nrad());
     rb.cnt.ensure(sizeof(Counters));
+    // intensities in units of I_img = 2 h f_mid^3 / c^2 (source functions too)
+    const double I_img = 2.0 * kH * pow(0.5 * (f_min + f_max), 3) / (kC * kC);
     line_coeffs_into(ctx, pops, rb.chiT.p, rb.ST.p, rb.S64.as<double>(), rb.cnt.as<Counters>(),
-                     s);
+                     s, I_img);
     const int64_t npix = (int64_t)npx * npy;
     RenderGeom g{};
     g.N = N;
@@ -1015,7 +1018,6 @@ void mgxh::render_image(mgx_ctx *ctx, RenderBufs &rb, const double *pops, hipStr
     g.walk = rb.walk.as<int32_t>();
     HIPCHK(launch_render_walk(g, true, s));
     rb.img.ensure(sizeof(float) * (size_t)npix * nfreq);
-    const double I_img = 2.0 * kH * pow(0.5 * (f_min + f_max), 3) / (kC * kC);
     auto fill_args = [&](auto &ra) {
         ra.npx = npx;
         ra.npy = npy;
@@ -1028,7 +1030,6 @@ void mgxh::render_image(mgx_ctx *ctx, RenderBufs &rb, const double *pops, hipStr
         ra.b = ctx->bd.as<double>();
         ra.ib = ctx->ibd.as<double>();
         ra.nu_line = ctx->nu.as<double>();
-        ra.Iref = ctx->Iref.as<double>();
         ra.inv_L = 1.0 / ctx->L_unit;
         ra.f_min = f_min;
         ra.f_max = f_max;

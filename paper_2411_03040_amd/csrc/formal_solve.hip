@@ -24,7 +24,10 @@
 //      u = (D_o S_o + eps_- + eps_+) / (D_o + g_- + g_+),
 //      Lambda*_oo = D_o / (D_o + g_- + g_+);
 //    an empty half keeps (dm, g, eps) = (0, 1, I_boundary at the origin), so
-//    boundary origins and isolated points need no special case.
+//    boundary origins and isolated points need no special case.  The kernel
+//    carries h = dt/2 and G = 2g instead of dt and g: D = h_m + h,
+//    G <- (2D + G) inv with inv = 1 / (1 + (2D + G) h), one operation fewer
+//    per step, and, the factors being powers of two, the same roundings.
 //  * J-bar = sum_pairs 2 w_r sum_f W_f u, Lambda-bar* likewise.
 //
 // Launch shape: one workgroup per (origin, chunk of lines); one lane per
@@ -65,30 +68,31 @@ struct FM<float> {
         return __builtin_amdgcn_exp2f(fmaf(-xs, xs, lchi));
     }
     static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-    // erfc for x >= 0, branch-free: the Chebyshev-fitted form of Numerical
-    // Recipes (Press et al., 2nd ed., Sec. 6.2, "erfcc"),
-    //   erfc(x) = t exp(-x^2 + P(t)),  t = 1 / (1 + x/2),
-    // fractional error below 1.2e-7 for all x >= 0.  One reciprocal, one
-    // exp2 and a degree-9 Horner chain, the same for every lane (the library
-    // erfcf branches by argument range, which diverges across the bins of a
-    // wave).  Evaluated in base 2: the argument comes scaled by sqrt(log2 e)
-    // (xs = x sqrt(log2 e), see erf_scale) and the coefficients below are the
-    // published ones times log2 e, so exp2 takes -xs^2 + log2(e) P(t)
-    // directly.
+    // erfc for x >= 0, branch-free, in the product form of Numerical Recipes
+    // (Press et al., 2nd ed., Sec. 6.2),
+    //   erfc(x) = t exp(-x^2 + P(t)),  t = 1 / (1 + p x),
+    // with our own fit (fit_erfc.py in the package reproduces it): p = 0.475
+    // and a degree-7 P, fitted for least maximum relative error of erfc on x
+    // in [0, 9.6] (2.8e-7 in exact arithmetic; in FP32 the rounding of the
+    // exponent argument dominates at large x, as for the published degree-9
+    // form).  One reciprocal, one exp2 and seven
+    // multiply-adds, the same for every lane (the library erfcf branches by
+    // argument range, which diverges across the bins of a wave).  Evaluated
+    // in base 2: the argument comes scaled by sqrt(log2 e) (xs = x sqrt(log2 e),
+    // see erf_scale), P is fitted to log2(erfc(x) / t) + xs^2 directly and
+    // p is divided by sqrt(log2 e).
     static constexpr float erf_scale = 1.2011224f;  // sqrt(log2 e)
     static __device__ __forceinline__ float erfc_scaled(float xs)
     {
-        const float t = __builtin_amdgcn_rcpf(fmaf(xs, 0.41627732f, 1.0f));
-        float p = 0.2465173f;
-        p = fmaf(p, t, -1.1861149f);
-        p = fmaf(p, t, 2.1474745f);
-        p = fmaf(p, t, -1.6377531f);
-        p = fmaf(p, t, 0.40232158f);
-        p = fmaf(p, t, -0.26875687f);
-        p = fmaf(p, t, 0.13963005f);
-        p = fmaf(p, t, 0.5397006f);
-        p = fmaf(p, t, 1.4427292f);
-        p = fmaf(p, t, -1.8257482f);
+        const float t = __builtin_amdgcn_rcpf(fmaf(xs, 0.39546344f, 1.0f));
+        float p = -0.28171604f;
+        p = fmaf(p, t, 1.22523776f);
+        p = fmaf(p, t, -1.86701982f);
+        p = fmaf(p, t, 0.97788950f);
+        p = fmaf(p, t, -0.22770730f);
+        p = fmaf(p, t, 0.63901249f);
+        p = fmaf(p, t, 1.43362935f);
+        p = fmaf(p, t, -1.89932635f);
         return t * __builtin_amdgcn_exp2f(fmaf(-xs, xs, p));
     }
     // e^x - 1 for the CMB boundary intensity: exp2 away from zero, a
@@ -140,18 +144,19 @@ __device__ __forceinline__ T erf_diff(T a, T b)
     return (b > a) ? t : -t;
 }
 
-// Per staged record: meta A (dv, 1/b scaled for the profile, half the
-// length of the segment ending here -- -1 when that segment takes the
+// Per staged record: meta A (dv, 1/b scaled for the profile, a quarter of
+// the length of the segment ending here -- -1 when that segment takes the
 // semi-analytic form -- and its 1/b-bar times erf_scale), read by the solve
 // as one broadcast; meta B (b, point index, the semi-analytic factor below)
 // only feeds the line gather.  Per record and line of the chunk: chi' (in
 // the form chi_phi takes), S', chi' b (the semi-analytic segment's weight)
-// and, for a semi-analytic segment, the lane-independent factor of its
+// and, for a semi-analytic segment, half the lane-independent factor of its
 // optical depth, dx sqrt(pi)/4 / (dv_Q - dv_P), which the trace computed in
-// FP64 and stored in place of the segment length.
+// FP64 and stored in place of the segment length.  (Halves and quarters:
+// the solve works with half optical depths.)
 template <typename T>
 struct alignas(4 * sizeof(T)) MetaA {
-    T dv, ib, hdx, ibb;
+    T dv, ib, qdx, ibb;
 };
 template <typename T>
 struct alignas(2 * sizeof(T)) MetaB {
@@ -190,25 +195,6 @@ __host__ __device__ inline LDSLayout lds_layout(int ch, int nlc, int nthreads)
 // temporal) so they do not evict the per-point line table the gathers reuse.
 typedef int v4i __attribute__((ext_vector_type(4)));
 
-// Global-memory pointers.  Every table the formal solution reads lives in
-// global memory; pointers loaded from device memory (the batched launch's
-// descriptors) are generic to the compiler and would otherwise become flat
-// accesses, which also wait on LDS traffic.
-template <typename X>
-using gptr = const __attribute__((address_space(1))) X *;
-template <typename X>
-using gptr_mut = __attribute__((address_space(1))) X *;
-template <typename X>
-__device__ __forceinline__ gptr<X> glob(const X *p)
-{
-    return (gptr<X>)p;
-}
-template <typename X>
-__device__ __forceinline__ gptr_mut<X> glob_mut(X *p)
-{
-    return (gptr_mut<X>)p;
-}
-
 __device__ __forceinline__ Rec<float> load_stream(gptr<Rec<float>> p)
 {
     const v4i v = __builtin_nontemporal_load((gptr<v4i>)p);
@@ -235,9 +221,9 @@ __device__ __forceinline__ Rec<double> load_stream(gptr<Rec<double>> p)
 
 template <typename T>
 struct HalfState {
-    T g, eps, dm;      // elimination state
+    T G, eps, hm;      // elimination state: 2g, eps, half the previous depth
     T chi, S, u, cb;   // previous point: opacity, source, xb + dv k1, chi'*b
-    T hdx, sibb, rw;   // segment data stored with the previous record
+    T qdx, sibb, rw;   // segment data stored with the previous record
 };
 
 template <typename T>
@@ -285,7 +271,7 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
     const T chi_o = chi[ol] * (T)exp(-xfd * xfd);
     const T S_o = S[ol];
     const T cb_o = chi[ol] * bpt[o];
-    const T tau_floor = (T)a.tau_floor;
+    const T half_floor = (T)(0.5 * a.tau_floor);
     const T half = (T)0.5;
 
     auto bdy_I = [&](T dv) -> T {
@@ -293,32 +279,34 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
         return r * r * r * FM<T>::rcp(FM<T>::expm1_(acmb * r));
     };
 
-    auto row = [&](HalfState<T> &st, T dt) {
-        const T D = (st.dm + dt) * half;
-        const T q = D + st.g;
-        const T inv = FM<T>::rcp((T)1 + q * dt);
-        st.g = q * inv;
+    // one elimination step across the previous point, h = half the depth of
+    // the segment that follows it (q2 = 2q, and q2 h = q dt exactly)
+    auto row = [&](HalfState<T> &st, T h) {
+        const T D = st.hm + h;
+        const T q2 = D * (T)2 + st.G;
+        const T inv = FM<T>::rcp((T)1 + q2 * h);
+        st.G = q2 * inv;
         st.eps = (D * st.S + st.eps) * inv;
-        st.dm = dt;
+        st.hm = h;
     };
 
-    // segment from the previous point of st (farther out) to Q, whose
-    // unscaled offset is uQ = xb + dvQ k1; hdx carries half the segment
-    // length, so the trapezoid needs no factor 1/2.  Semi-analytic:
+    // half the optical depth of the segment from the previous point of st
+    // (farther out) to Q, whose unscaled offset is uQ = xb + dvQ k1; qdx
+    // carries a quarter of the segment length.  Semi-analytic:
     //   dt = dx sqrt(pi)/4 (cb_P + cb_Q) (erf x_Q - erf x_P) / (b-bar (x_Q - x_P))
     // with x = u / b-bar and x_Q - x_P = (dvQ - dvP) k1 / b-bar, so b-bar
-    // cancels outside the erf arguments; dx sqrt(pi)/4 / (dvQ - dvP) comes
-    // with the record (rw).
+    // cancels outside the erf arguments; half of dx sqrt(pi)/4 / (dvQ - dvP)
+    // comes with the record (rw).  Floored at tau_floor / 2.
     auto segment = [&](HalfState<T> &st, T chiQ, T uQ, T cbQ) -> T {
-        T dt;
-        if (signbit(st.hdx)) {
+        T h;
+        if (signbit(st.qdx)) {
             const T xP = st.u * st.sibb;
             const T xQ = uQ * st.sibb;
-            dt = (st.cb + cbQ) * erf_diff<T>(xP, xQ) * (st.rw * inv_k1);
+            h = (st.cb + cbQ) * erf_diff<T>(xP, xQ) * (st.rw * inv_k1);
         } else {
-            dt = st.hdx * (st.chi + chiQ);
+            h = st.qdx * (st.chi + chiQ);
         }
-        return FM<T>::at_least(dt, tau_floor);
+        return FM<T>::at_least(h, half_floor);
     };
 
     double accJ = 0.0, accL = 0.0;
@@ -335,11 +323,11 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
         const bool a_minus = nm >= np;
         const int nA = a_minus ? nm : np, nB = a_minus ? np : nm;
         HalfState<T> A, B;
-        A.g = B.g = (T)1;
-        A.dm = B.dm = (T)0;
+        A.G = B.G = (T)2;
+        A.hm = B.hm = (T)0;
         A.eps = B.eps = bdy_I((T)0);  // replaced at the far end of a non-empty half
-        A.chi = A.S = A.u = A.cb = A.hdx = A.sibb = A.rw = (T)0;
-        B.chi = B.S = B.u = B.cb = B.hdx = B.sibb = B.rw = (T)0;
+        A.chi = A.S = A.u = A.cb = A.qdx = A.sibb = A.rw = (T)0;
+        B.chi = B.S = B.u = B.cb = B.qdx = B.sibb = B.rw = (T)0;
 
         // point Q (staged record e) of a half: its profile, then either the
         // far-end boundary intensity or one elimination row
@@ -360,7 +348,7 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
             s.S = lr.S;
             s.u = uQ;
             s.cb = lr.cb;
-            s.hdx = ma.hdx;
+            s.qdx = ma.qdx;
             s.sibb = ma.ibb;
             s.rw = lr.rw;
         };
@@ -382,15 +370,16 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
                 MetaA<T> ma;
                 ma.dv = rc.dv;
                 ma.ib = ibpt[p];
-                // half the trapezoid's length, or -1 marking a semi-analytic
-                // segment (whose record carries its optical-depth factor)
-                ma.hdx = rc.ps < 0 ? (T)-1 : rc.dx * half;
+                // a quarter of the trapezoid's length, or -1 marking a
+                // semi-analytic segment (whose record carries its
+                // optical-depth factor)
+                ma.qdx = rc.ps < 0 ? (T)-1 : rc.dx * (T)0.25;
                 ma.ibb = rc.ibb * (T)FM<T>::erf_scale;
                 s_a[t] = ma;
                 MetaB<T> mb;
                 mb.b = bpt[p];
                 mb.p = p;
-                mb.rw = rc.ps < 0 ? rc.dx : (T)0;
+                mb.rw = rc.ps < 0 ? rc.dx * half : (T)0;
                 s_b[t] = mb;
             }
             __syncthreads();
@@ -438,8 +427,8 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
         if (nB > 0) row(B, segment(B, chi_o, xb, cb_o));
         // combine in the order minus, plus
         const HalfState<T> &Hm = a_minus ? A : B, &Hp = a_minus ? B : A;
-        const T Do = (Hm.dm + Hp.dm) * half;
-        const T inv_den = FM<T>::rcp(Do + Hm.g + Hp.g);
+        const T Do = Hm.hm + Hp.hm;
+        const T inv_den = FM<T>::rcp(Do + Hm.G * half + Hp.G * half);
         const T u = (Do * S_o + Hm.eps + Hp.eps) * inv_den;
         const T lam = Do * inv_den;
         const double w = pair_w[pi];
@@ -523,6 +512,7 @@ hipError_t launch_formal_solve_batch(const FSArgs<T> *descs, const int4 *items, 
                                      size_t lds, hipStream_t s)
 {
     if (blocks <= 0) return hipSuccess;
+    if (ch < 1) return hipErrorInvalidValue;
     if (sizeof(T) == 8 && nthreads <= 512)
         k_formal_solve_batch<T, 512><<<blocks, nthreads, lds, s>>>(descs, items, count, active,
                                                                    ch);
@@ -627,7 +617,8 @@ hipError_t launch_bin_table(int nbins, double xmax, double *xf, double *W, hipSt
 
 // chi^ij = (h nu / 4 pi)(n_l B_lu - n_u B_ul), eta^ij = (h nu / 4 pi) n_u A,
 // S = eta^ij / chi^ij; stored as chi' = chi^ij c L_unit / (nu b sqrt(pi)) and
-// S / Iref in the solve precision, S in double for statistical equilibrium.
+// S / Iref (S / I_img for images) in the solve precision, S in double for
+// statistical equilibrium.
 __global__ void k_line_coeffs(LineArgs a)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -646,7 +637,7 @@ __global__ void k_line_coeffs(LineArgs a)
     const double S = eta / chi;
     a.S64[i] = S;
     const double chis = chi * a.chiscale[l] / a.b[p];
-    const double Ss = S / a.Iref[l];
+    const double Ss = S / (a.S_unit > 0.0 ? a.S_unit : a.Iref[l]);
     if (a.fp32) {
         ((float *)a.chiT)[i] = (float)chis;
         ((float *)a.ST)[i] = (float)Ss;

@@ -269,8 +269,9 @@ inline void upload(mgx_ctx *c, DMem &d, const T *src, size_t n)
 
 // context internals used by the batch and server sources
 void run_line_coeffs(mgx_ctx *ctx);
+// (S_unit > 0: the solve-precision source function is S / S_unit, else S / Iref)
 void line_coeffs_into(mgx_ctx *ctx, const double *pops, void *chiT, void *ST, double *S64,
-                      Counters *cnt, hipStream_t s);
+                      Counters *cnt, hipStream_t s, double S_unit = 0.0);
 template <typename T>
 FSArgs<T> fs_args(mgx_ctx *ctx);
 StateqArgs stateq_args(mgx_ctx *ctx);

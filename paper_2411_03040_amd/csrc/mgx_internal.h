@@ -20,6 +20,26 @@ constexpr int kMaxLevels = 64;
 constexpr int kMaxBins = 1024;
 constexpr int kNgMaxHist = 32;
 
+// Global-memory pointers.  Every table the kernels read lives in global
+// memory; pointers loaded from device memory (the batched launch's
+// descriptors) or carried in by-value argument blocks are generic to the
+// compiler and would otherwise become flat accesses, which also wait on LDS
+// traffic and cannot become scalar loads.
+template <typename X>
+using gptr = const __attribute__((address_space(1))) X *;
+template <typename X>
+using gptr_mut = __attribute__((address_space(1))) X *;
+template <typename X>
+__device__ __forceinline__ gptr<X> glob(const X *p)
+{
+    return (gptr<X>)p;
+}
+template <typename X>
+__device__ __forceinline__ gptr_mut<X> glob_mut(X *p)
+{
+    return (gptr_mut<X>)p;
+}
+
 // Device counters (reset per pass by k_reset_counters).
 struct Counters {
     unsigned long long masing;
@@ -92,6 +112,7 @@ struct LineArgs {
     const int32_t *up, *lo;
     const double *A, *Bul, *Blu, *hnu4pi, *chiscale, *Iref;
     double chi_min;
+    double S_unit;          // > 0: the solve-precision S is S / S_unit (images), else S / Iref
     double *S64;            // [N][nlines] physical source function
     void *chiT, *ST;        // [N][nlines] in the solve precision
     int fp32;
@@ -181,9 +202,9 @@ struct RenderArgs {
     const int64_t *off;
     const int32_t *walk;
     const double *Z, *w;       // [N] (double; scaled inside)
-    const T *chi, *S;          // [N][nlines] scaled opacity factor and S / Iref
+    const T *chi, *S;          // [N][nlines] scaled opacity factor and S / I_img
     const double *b, *ib;      // [N] b and 1/b
-    const double *nu_line, *Iref;  // [nlines]
+    const double *nu_line;     // [nlines]
     double inv_L, f_min, f_max, Tcmb, I_img;
     double thr;                // branch threshold (widths)
     const double *b2;          // [N] squared Doppler speed (branch rule in FP64)

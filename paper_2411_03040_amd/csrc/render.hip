@@ -15,8 +15,14 @@
 // with a short series for small t.
 //
 // Launch shape: lanes are frequencies, one wave per 64 frequencies of one
-// pixel, up to four waves per block.  The walk's point data are read by all
-// lanes of a wave at once (one broadcast per wave).
+// pixel, up to four waves per block.  The pixel, its walk and every point
+// datum are the same for all lanes of a wave: they are read with scalar loads
+// into scalar registers, and only the per-frequency arithmetic is per lane.
+// Source functions arrive in units of the image's intensity unit, and the
+// profile offsets are scaled by sqrt(log2 e) in FP32 so that each Gaussian is
+// one base-2 exponential.  On semi-analytic segments, lines that lie in one
+// far wing at both ends for the whole wave (both erfc exactly zero) are
+// skipped by a wave vote.
 
 #include "mgx_internal.h"
 
@@ -27,6 +33,10 @@ struct RM;
 template <>
 struct RM<float> {
     static __device__ __forceinline__ float ex(float x) { return __expf(x); }
+    // Gaussian profiles take offsets pre-scaled by sqrt(log2 e), so that
+    // exp(-x^2) is one base-2 exponential of the scaled square
+    static constexpr double gauss_k = 1.2011224087864498;  // sqrt(log2 e)
+    static __device__ __forceinline__ float gauss(float xs2) { return __builtin_amdgcn_exp2f(-xs2); }
     static __device__ __forceinline__ float em1(float x) { return expm1f(x); }
     static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
     // erfc for x >= 0, branch-free (Numerical Recipes' Chebyshev form
@@ -49,15 +59,22 @@ struct RM<float> {
     }
     static constexpr float series_below = 0.1f;
     static constexpr float tiny = 1e-30f;  // smallest opacity sum used as a divisor
+    // erfc_ returns exactly 0 beyond this (its exponential is below the
+    // smallest denormal)
+    static constexpr float erfc_zero = 10.5f;
 };
 template <>
 struct RM<double> {
     static __device__ __forceinline__ double ex(double x) { return exp(x); }
+    static constexpr double gauss_k = 1.0;
+    static __device__ __forceinline__ double gauss(double x2) { return exp(-x2); }
     static __device__ __forceinline__ double em1(double x) { return expm1(x); }
     static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
     static __device__ __forceinline__ double erfc_(double x) { return erfc(x); }
     static constexpr double series_below = 1e-4;
     static constexpr double tiny = 1e-290;
+    // the library erfc is exactly 0 beyond this (erfc(27.3) < 5e-324)
+    static constexpr double erfc_zero = 27.5;
 };
 
 template <typename T>
@@ -103,40 +120,43 @@ __global__ __launch_bounds__(256) void k_render_integrate(RenderArgs<T> a, int n
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const int t = threadIdx.x;
     const int nl = a.nlines;
-    // per-line intensity scale Iref_l / I_img, shared by the block
-    T *s_sc = (T *)smem;
-    for (int l = t; l < nl; l += blockDim.x) s_sc[l] = (T)(a.Iref[l] / a.I_img);
-    __syncthreads();
-    // 64 frequencies of one pixel per wave
-    const int64_t slice = ((int64_t)blockIdx.x * blockDim.x + t) >> 6;
-    const int64_t pix = slice / nslices;
-    const int f = (int)(slice % nslices) * 64 + (t & 63);
+    const gptr<double> nu_line = glob(a.nu_line);
+    // 64 frequencies of one pixel per wave: the pixel, its walk and every
+    // point datum are wave-uniform (scalar registers and loads)
+    const int slice =
+        __builtin_amdgcn_readfirstlane((int)(((int64_t)blockIdx.x * blockDim.x + t) >> 6));
+    const int pix = slice / nslices;
+    const int f = (slice - pix * nslices) * 64 + (t & 63);
     const int npix = a.npx * a.npy;
     if (pix >= npix || f >= a.nfreq) return;
     const double nu = (a.nfreq == 1) ? a.f_min
                                      : a.f_min + (a.f_max - a.f_min) * f / (a.nfreq - 1);
     const double f_mid = 0.5 * (a.f_min + a.f_max);
-    LineLane<T> *tab = (LineLane<T> *)(smem + ((sizeof(T) * nl + 15) & ~(size_t)15)) +
-                       (size_t)t * nl;
+    LineLane<T> *tab = (LineLane<T> *)smem + (size_t)t * nl;
     auto line_lane = [&](int l) -> LineLane<T> {
         LineLane<T> e;
         if (TAB) {
             e = tab[l];
         } else {
-            e.cd = (T)(kC * (nu - a.nu_line[l]) / a.nu_line[l]);
-            e.rr = (T)(nu / a.nu_line[l]);
+            e.cd = (T)(kC * (nu - nu_line[l]) / nu_line[l]);
+            e.rr = (T)(nu / nu_line[l]);
         }
         return e;
     };
     if (TAB)
         for (int l = 0; l < nl; l++) {
             LineLane<T> e;
-            e.cd = (T)(kC * (nu - a.nu_line[l]) / a.nu_line[l]);
-            e.rr = (T)(nu / a.nu_line[l]);
+            e.cd = (T)(kC * (nu - nu_line[l]) / nu_line[l]);
+            e.rr = (T)(nu / nu_line[l]);
             tab[l] = e;
         }
-    const int64_t o0 = a.off[pix], n = a.off[pix + 1] - o0;
-    float *out = a.img + pix * a.nfreq + f;
+    const gptr<int64_t> off = glob(a.off);
+    const gptr<int32_t> walk = glob(a.walk);
+    const gptr<double> Wv = glob(a.w), Zv = glob(a.Z), bv = glob(a.b), ibv = glob(a.ib);
+    const gptr<double> b2v = glob(a.b2);
+    const gptr<T> chi = glob(a.chi), Sv = glob(a.S);
+    const int64_t o0 = off[pix], n = off[pix + 1] - o0;
+    float *out = a.img + (int64_t)pix * a.nfreq + f;
     auto planck_n = [&](double nup) -> double {  // B_nu(Tcmb) / I_img
         const double r = nup / f_mid;
         return r * r * r / expm1(kH * nup / (kKB * a.Tcmb));
@@ -149,14 +169,17 @@ __global__ __launch_bounds__(256) void k_render_integrate(RenderArgs<T> a, int n
     const double thr2 = a.thr * a.thr;
     T I = (T)0, chi0 = (T)0, S0 = (T)0;
     int p0 = -1;
-    double w0d = 0.0;
+    double w0d = 0.0, Z0 = 0.0, b20 = 0.0;
+    // the next walk index is fetched one point ahead
+    int p_next = walk[o0];
     for (int64_t k = 0; k < n; k++) {
-        const int p = a.walk[o0 + k];
-        const double wd = a.w[p];
+        const int p = p_next;
+        if (k + 1 < n) p_next = walk[o0 + k + 1];
+        const double wd = Wv[p];
         const T w = (T)wd;
-        const T ib = (T)a.ib[p];
-        const T *chi_p = a.chi + (int64_t)p * nl;
-        const T *S_p = a.S + (int64_t)p * nl;
+        const T ibg = (T)(ibv[p] * RM<T>::gauss_k);
+        const gptr<T> chi_p = chi + (int64_t)p * nl;
+        const gptr<T> S_p = Sv + (int64_t)p * nl;
         // opacity (sum over lines) and the profile-weighted mean of the line
         // source functions, in one pass; where every profile underflows the
         // source function is the same mean with weights relative to the
@@ -164,10 +187,10 @@ __global__ __launch_bounds__(256) void k_render_integrate(RenderArgs<T> a, int n
         T chi1 = (T)0, sws = (T)0;
         for (int l = 0; l < nl; l++) {
             const LineLane<T> e = line_lane(l);
-            const T x = (e.cd - e.rr * w) * ib;
-            const T c = chi_p[l] * RM<T>::ex(-(x * x));
+            const T x = (e.cd - e.rr * w) * ibg;
+            const T c = chi_p[l] * RM<T>::gauss(x * x);
             chi1 += c;
-            sws += c * S_p[l] * s_sc[l];
+            sws += c * S_p[l];
         }
         T S1;
         if (chi1 > RM<T>::tiny) {
@@ -176,37 +199,43 @@ __global__ __launch_bounds__(256) void k_render_integrate(RenderArgs<T> a, int n
             T x2min = (T)INFINITY;
             for (int l = 0; l < nl; l++) {
                 const LineLane<T> e = line_lane(l);
-                const T x = (e.cd - e.rr * w) * ib;
+                const T x = (e.cd - e.rr * w) * ibg;
                 x2min = fmin(x2min, x * x);
             }
             T sw = (T)0;
             sws = (T)0;
             for (int l = 0; l < nl; l++) {
                 const LineLane<T> e = line_lane(l);
-                const T x = (e.cd - e.rr * w) * ib;
-                const T wt = chi_p[l] * RM<T>::ex(-(x * x - x2min));
+                const T x = (e.cd - e.rr * w) * ibg;
+                const T wt = chi_p[l] * RM<T>::gauss(x * x - x2min);
                 sw += wt;
-                sws += wt * S_p[l] * s_sc[l];
+                sws += wt * S_p[l];
             }
             S1 = sw > (T)0 ? sws / sw : (T)0;
         }
+        const double Zd = Zv[p], b2d = b2v[p];
         if (k == 0) {
             I = (T)planck_n(nu * (1.0 - wd / kC));
         } else {
             const double dd = wd - w0d;
-            const bool semi = dd * dd >= thr2 * ((a.b2[p0] + a.b2[p]) * 0.5);
-            const T dx = (T)((a.Z[p] - a.Z[p0]) * a.inv_L);
+            const bool semi = dd * dd >= thr2 * ((b20 + b2d) * 0.5);
+            const T dx = (T)((Zd - Z0) * a.inv_L);
             T dt = (T)0;
             if (semi) {
-                const T ibb = (T)(1.0 / sqrt((a.b2[p0] + a.b2[p]) * 0.5));
-                const T b0 = (T)a.b[p0], b1 = (T)a.b[p];
+                const T ibb = (T)(1.0 / sqrt((b20 + b2d) * 0.5));
+                const T b0 = (T)bv[p0], b1 = (T)bv[p];
                 const T w0 = (T)w0d;
-                const T *chi_q = a.chi + (int64_t)p0 * nl;
+                const gptr<T> chi_q = chi + (int64_t)p0 * nl;
                 const T ddt = (T)dd;
                 for (int l = 0; l < nl; l++) {
                     const LineLane<T> e = line_lane(l);
                     const T xa = (e.cd - e.rr * w0) * ibb;
                     const T xb = (e.cd - e.rr * w) * ibb;
+                    // both ends in the same far wing for every lane of the
+                    // wave: both erfc are exactly zero, so is the term
+                    const bool far = (xa > RM<T>::erfc_zero && xb > RM<T>::erfc_zero) ||
+                                     (xa < -RM<T>::erfc_zero && xb < -RM<T>::erfc_zero);
+                    if (__all(far)) continue;
                     const T dxb = -e.rr * ddt * ibb;
                     const T cb = chi_q[l] * b0 + chi_p[l] * b1;
                     dt += dx * cb * spi4 * ibb * erf_diff_r<T>(xa, xb) * RM<T>::rcp(dxb);
@@ -222,6 +251,8 @@ __global__ __launch_bounds__(256) void k_render_integrate(RenderArgs<T> a, int n
         S0 = S1;
         p0 = p;
         w0d = wd;
+        Z0 = Zd;
+        b20 = b2d;
     }
     *out = (float)((double)I * a.I_img);
 }
@@ -231,13 +262,12 @@ hipError_t launch_render_integrate(const RenderArgs<T> &a, hipStream_t s)
 {
     const int nslices = (a.nfreq + 63) / 64;
     const int64_t waves = (int64_t)a.npx * a.npy * nslices;
-    const size_t head = (sizeof(T) * a.nlines + 15) & ~(size_t)15;
     const size_t per_thread = sizeof(LineLane<T>) * (size_t)a.nlines;
     // the largest block (256, 128 or 64 threads) whose line tables fit 40 KB
     int threads = 256;
-    while (threads > 64 && head + per_thread * threads > (40u << 10)) threads /= 2;
-    const bool tab = head + per_thread * threads <= (64u << 10);
-    const size_t lds = tab ? head + per_thread * threads : head;
+    while (threads > 64 && per_thread * threads > (40u << 10)) threads /= 2;
+    const bool tab = per_thread * threads <= (64u << 10);
+    const size_t lds = tab ? per_thread * threads : 0;
     const int64_t blocks = (waves * 64 + threads - 1) / threads;
     if (tab)
         k_render_integrate<T, true><<<(unsigned)blocks, threads, lds, s>>>(a, nslices);

@@ -171,6 +171,20 @@ def _ptr(a) -> int:
     raise TypeError(type(a))
 
 
+def _host_image(npy: int, npx: int, nfreq: int) -> np.ndarray:
+    """Host array for an image: page-locked when torch can provide it (the
+    device-to-host copy then runs at DMA speed, and torch's caching host
+    allocator reuses freed buffers), else plain memory."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            return torch.empty((npy, npx, nfreq), dtype=torch.float32,
+                               pin_memory=True).numpy()
+    except ImportError:
+        pass
+    return np.empty((npy, npx, nfreq), np.float32)
+
+
 def _torch_stream(device: int):
     try:
         import torch
@@ -353,7 +367,7 @@ class Context:
                      nfreq: int, out=None):
         d = (C.c_double * 3)(*[float(x) for x in direction])
         if out is None:
-            out = np.zeros((npy, npx, nfreq), np.float32)
+            out = _host_image(npy, npx, nfreq)
         self._check(lib().mgx_render_image(self._h, d, npx, npy, f_min, f_max, nfreq,
                                            _ptr(out)))
         return out
@@ -509,7 +523,7 @@ class Server:
                       f_max: float, nfreq: int, out=None) -> int:
         d = (C.c_double * 3)(*[float(x) for x in direction])
         if out is None:
-            out = np.zeros((npy, npx, nfreq), np.float32)
+            out = _host_image(npy, npx, nfreq)
         rid = C.c_int64()
         self._check(lib().mgx_server_submit_render(self._h, model, d, npx, npy, f_min, f_max,
                                                    nfreq, _ptr(out), C.byref(rid)))

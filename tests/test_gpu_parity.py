@@ -213,6 +213,21 @@ def test_formal_solve_many_line_chunks(mgx):
     fs_compare(mgx, m, mgx.FP32, tolJ=1e-5, tolL=1e-5)
 
 
+def test_formal_solve_maximum_bins(mgx):
+    """The largest bin count (1024): one line per 1024-lane workgroup, the
+    widest launch of either precision; steep velocities, so semi-analytic
+    segments are mixed in."""
+    m = synth.tiny_cloud(npoints=40, seed=30, k=8, nside=1, nlev=3, nbins=1024, vmax=6e3)
+    ctx, _, _ = fs_compare(mgx, m, mgx.FP64, tolJ=1e-10, tolL=1e-10)
+    assert ctx.counters()["semi_segments"] > 0
+    fs_compare(mgx, m, mgx.FP32, tolJ=1e-5, tolL=1e-5)
+    m.nbins = 1025
+    c = mgx.Context()
+    with pytest.raises(mgx.MgxError) as e:
+        c.load_model(m)
+    assert e.value.status == mgx.MGX_EINVAL
+
+
 def test_formal_solve_single_bin_and_boundary_only(mgx):
     m = synth.tiny_cloud(npoints=20, seed=25, nside=1, nlev=2, nbins=1)
     fs_compare(mgx, m, mgx.FP64, tolJ=1e-10, tolL=1e-10)
@@ -457,6 +472,42 @@ def test_render_clumpy_full_sampled(mgx, clumpy, prec, tol):
     pix = [(int(a), int(b)) for a, b in zip(rng.integers(0, 48, 12), rng.integers(0, 48, 12))]
     render_compare(mgx, m, prec, [0.5, 0.5, 0.7071], 48, 48, nu0 * (1 - 6e-5),
                    nu0 * (1 + 6e-5), 31, pix, tol)
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 2e-7), (1, 2e-5)])
+def test_render_frequency_slices(mgx, prec, tol):
+    """More frequencies than one wave (three 64-lane slices per pixel, the
+    last ragged) and a single frequency."""
+    m = synth.tiny_cloud(npoints=300, seed=54, k=12, nside=1, nlev=3, nbins=5, vmax=4e3,
+                         tau_scale=20.0)
+    nu0 = m.nu[0]
+    pix = [(ix, iy) for ix in range(7) for iy in range(5)]
+    render_compare(mgx, m, prec, [0.3, 0.2, -0.9], 7, 5, nu0 * (1 - 2e-5), nu0 * (1 + 2e-5),
+                   130, pix, tol)
+    render_compare(mgx, m, prec, [0.3, 0.2, -0.9], 7, 5, nu0 * (1 + 3e-6), nu0 * (1 + 3e-6),
+                   1, pix, tol)
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 2e-7), (1, 2e-5)])
+def test_render_many_lines(mgx, prec, tol):
+    """Every level pair of an 18-level rotor as a line (153 lines): more
+    lines than the per-lane LDS table holds, so the line factors are formed
+    per point.  The window is centred on 6B, where the 2-0 and 3-2 lines
+    coincide and their opacities add."""
+    m = synth.tiny_cloud(npoints=120, seed=55, k=10, nside=1, nlev=18, nbins=5, vmax=3e3,
+                         tau_scale=5.0)
+    u, l = np.array([(u, l) for u in range(1, 18) for l in range(u)], np.int32).T
+    nu = (m.E[u] - m.E[l]) / 6.62607015e-34
+    m.up, m.lo, m.nu = u, l, nu
+    m.A = 1e-6 * (nu / 1e11) ** 3 / (u - l)
+    assert m.nlines == 153 and 8 * m.nlines * 64 > 64 * 1024
+    nu0 = nu[(u == 2) & (l == 0)][0]
+    assert abs(nu[(u == 3) & (l == 2)][0] / nu0 - 1) < 1e-12
+    pix = [(ix, iy) for ix in range(6) for iy in range(6)]
+    img, _ = render_compare(mgx, m, prec, [0.6, -0.3, 0.74], 6, 6, nu0 * (1 - 3e-5),
+                            nu0 * (1 + 3e-5), 70, pix, tol)
+    # the lines are seen: the image is not the CMB everywhere
+    assert np.ptp(img) > 1e-3 * np.max(np.abs(img))
 
 
 def test_render_steep_gradient_column(mgx):
