@@ -42,8 +42,13 @@ METRIC = ("formal-solve point·ray·freq updates/s, converged-model time vs FP64
 # A semi-analytic segment adds: 2 offsets (4), divided difference (sub, 2
 # mul, div 4), 2 erfc (~2 x 12), opacity average (fma 2, 3 mul)  ->  ~38 FLOP.
 # The origin row per (pair, lane) adds 8.
+# In a model with one Doppler width everywhere an erfc value at a point is
+# shared by the semi-analytic segments on both sides of it, so such a model is
+# credited one erfc per semi-analytic segment (a lower bound of its unique
+# work: a run of k such segments needs k + 1).
 FLOP_PER_ELEMENT = 20.0
 FLOP_PER_SEMI = 38.0
+FLOP_PER_SEMI_ONE_WIDTH = 26.0
 FLOP_PER_ORIGIN_ROW = 8.0
 # Peak: 256 CUs x 4 SIMD x 16 lanes x 2 FLOP (FMA) x 2.4 GHz = 78.6 TFLOP/s for
 # FP32 without packed (dual) FP32 instructions, which this build does not use;
@@ -99,7 +104,9 @@ def alu_roofline(ctx, m, ms_per_launch, precision):
     lanes = m.nlines * m.nbins
     npairs = m.nrays // 2
     elements = lanes * c["total_records"]
-    flop = (elements * FLOP_PER_ELEMENT + lanes * c["semi_segments"] * FLOP_PER_SEMI +
+    one_width = bool(np.ptp(m.T) == 0 and np.ptp(m.vturb2) == 0)
+    per_semi = FLOP_PER_SEMI_ONE_WIDTH if one_width else FLOP_PER_SEMI
+    flop = (elements * FLOP_PER_ELEMENT + lanes * c["semi_segments"] * per_semi +
             lanes * m.npoints * npairs * FLOP_PER_ORIGIN_ROW)
     achieved = flop / (ms_per_launch * 1e-3) / 1e12
     peak = PEAK_FP32_TFLOPS if precision == "fp32" else PEAK_FP64_TFLOPS
@@ -115,7 +122,8 @@ def alu_roofline(ctx, m, ms_per_launch, precision):
             "frac": round(achieved / peak, 4), "traffic": None,
             "kernel": "k_formal_solve<%s>" % ("float" if precision == "fp32" else "double"),
             "flop_per_launch": flop, "elements_per_launch": elements,
-            "semi_segments": c["semi_segments"], "ms_per_launch": round(ms_per_launch, 4),
+            "semi_segments": c["semi_segments"], "one_width": one_width,
+            "ms_per_launch": round(ms_per_launch, 4),
             "algorithmic_bytes_per_launch": alg_bytes,
             "hbm_GBps_algorithmic": round(alg_bytes / (ms_per_launch * 1e-3) / 1e9, 1),
             "hbm_frac_algorithmic": round(alg_bytes / (ms_per_launch * 1e-3) / 8e12, 5)}

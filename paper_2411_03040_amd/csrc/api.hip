@@ -264,6 +264,19 @@ extern "C" mgx_status mgx_load_model(mgx_ctx *ctx, const mgx_model *m)
     upload(ctx, ctx->bdy, m->bdy, (size_t)N);
     upload(ctx, ctx->T, m->T, (size_t)N);
     upload(ctx, ctx->vturb2, m->vturb2, (size_t)N);
+    // one Doppler width everywhere (bit-identical T and v_turb^2): every
+    // segment's averaged width is then the same number, which the formal
+    // solution exploits
+    ctx->one_width = true;
+    for (int i = 1; i < N && ctx->one_width; i++)
+        ctx->one_width = m->T[i] == m->T[0] && m->vturb2[i] == m->vturb2[0];
+    // bounds for the images' line culling
+    ctx->vmax = ctx->bmax = 0.0;
+    for (int i = 0; i < N; i++) {
+        const double vx = m->vel[i], vy = m->vel[(size_t)N + i], vz = m->vel[2 * (size_t)N + i];
+        ctx->vmax = std::max(ctx->vmax, std::sqrt(vx * vx + vy * vy + vz * vz));
+        ctx->bmax = std::max(ctx->bmax, std::sqrt(2.0 * kKB * m->T[i] / m->mass + m->vturb2[i]));
+    }
     upload(ctx, ctx->nspec, m->nspec, (size_t)N);
     upload(ctx, ctx->ncoll, m->ncoll, (size_t)N);
     upload(ctx, ctx->ray_dir, m->ray_dir, 3 * (size_t)R);
@@ -275,6 +288,7 @@ extern "C" mgx_status mgx_load_model(mgx_ctx *ctx, const mgx_model *m)
     upload(ctx, ctx->lo, m->lo, (size_t)m->nlines);
     upload(ctx, ctx->A, m->A, (size_t)m->nlines);
     upload(ctx, ctx->nu, m->nu, (size_t)m->nlines);
+    ctx->nu_host.assign(m->nu, m->nu + m->nlines);
     upload(ctx, ctx->cu, m->cu, (size_t)m->ncoll_tr);
     upload(ctx, ctx->cl, m->cl, (size_t)m->ncoll_tr);
     upload(ctx, ctx->K0, m->K0, (size_t)m->ncoll_tr);
@@ -583,6 +597,7 @@ FSArgs<T> mgxh::fs_args(mgx_ctx *ctx)
     a.J = ctx->J.as<double>();
     a.L = ctx->L.as<double>();
     a.order = ctx->order.as<int32_t>();  // null where the table fits the L2
+    a.one_width = ctx->one_width ? 1 : 0;
     return a;
 }
 template FSArgs<float> mgxh::fs_args<float>(mgx_ctx *);
@@ -1018,6 +1033,32 @@ void mgxh::render_image(mgx_ctx *ctx, RenderBufs &rb, const double *pops, hipStr
     g.walk = rb.walk.as<int32_t>();
     HIPCHK(launch_render_walk(g, true, s));
     rb.img.ensure(sizeof(float) * (size_t)npix * nfreq);
+    // Lines whose profile can reach the band.  At a point moving with w
+    // (|w| <= vmax) and width b (<= bmax) the offset of frequency nu from line
+    // l is |x| = (c - w) |nu - c nu_l / (c - w)| / (nu_l b), so a line whose
+    // shifted centres c nu_l / (c +- vmax) all lie further than
+    // X nu_l bmax / (c - vmax) from the band has |x| > X everywhere: beyond
+    // X = 10.5 (FP32) or 27.5 (FP64) its Gaussian and erfc are exactly zero
+    // in the working precision, so its terms are skipped without changing a
+    // bit (1 % margin for the rounding of the offsets).
+    {
+        const double X = ctx->fp32() ? 10.5 : 27.5, vm = ctx->vmax;
+        rb.act_host.clear();
+        for (int l = 0; l < ctx->nlines; l++) {
+            const double nl = ctx->nu_host[l];
+            bool seen = true;
+            if (vm < 0.5 * kC) {
+                const double lo = kC * nl / (kC + vm), hi = kC * nl / (kC - vm);
+                const double d = 1.01 * X * nl * ctx->bmax / (kC - vm);
+                seen = f_max >= lo - d && f_min <= hi + d;
+            }
+            if (seen) rb.act_host.push_back(l);
+        }
+        rb.act.ensure(sizeof(int32_t) * std::max<size_t>(1, rb.act_host.size()));
+        if (!rb.act_host.empty())
+            HIPCHK(hipMemcpyAsync(rb.act.p, rb.act_host.data(),
+                                  sizeof(int32_t) * rb.act_host.size(), hipMemcpyHostToDevice, s));
+    }
     auto fill_args = [&](auto &ra) {
         ra.npx = npx;
         ra.npy = npy;
@@ -1030,6 +1071,8 @@ void mgxh::render_image(mgx_ctx *ctx, RenderBufs &rb, const double *pops, hipStr
         ra.b = ctx->bd.as<double>();
         ra.ib = ctx->ibd.as<double>();
         ra.nu_line = ctx->nu.as<double>();
+        ra.act = rb.act.as<int32_t>();
+        ra.nact = (int)rb.act_host.size();
         ra.inv_L = 1.0 / ctx->L_unit;
         ra.f_min = f_min;
         ra.f_max = f_max;

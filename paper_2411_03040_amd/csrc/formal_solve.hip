@@ -129,15 +129,13 @@ struct FM<double> {
     }
 };
 
-// erf(b) - erf(a) from two erfc evaluations (arguments scaled by erf_scale),
-// without cancellation for arguments of equal sign (the semi-analytic branch
-// guarantees |b - a| is at least about the branch threshold, so the
-// opposite-sign form 2 - erfc - erfc never cancels either).
+// erf(b) - erf(a) from ea = erfc(|a|) and eb = erfc(|b|) (arguments scaled
+// by erf_scale), without cancellation for arguments of equal sign (the
+// semi-analytic branch guarantees |b - a| is at least about the branch
+// threshold, so the opposite-sign form 2 - erfc - erfc never cancels either).
 template <typename T>
-__device__ __forceinline__ T erf_diff(T a, T b)
+__device__ __forceinline__ T erf_diff(T a, T b, T ea, T eb)
 {
-    const T ea = FM<T>::erfc_scaled(fabs(a));
-    const T eb = FM<T>::erfc_scaled(fabs(b));
     if (a >= (T)0 && b >= (T)0) return ea - eb;
     if (a <= (T)0 && b <= (T)0) return eb - ea;
     const T t = (T)2 - ea - eb;
@@ -224,6 +222,8 @@ struct HalfState {
     T G, eps, hm;      // elimination state: 2g, eps, half the previous depth
     T chi, S, u, cb;   // previous point: opacity, source, xb + dv k1, chi'*b
     T qdx, sibb, rw;   // segment data stored with the previous record
+    T ec;              // erfc(|u sibb|) of the previous point, if ec_ok
+    bool ec_ok;
 };
 
 template <typename T>
@@ -231,8 +231,11 @@ constexpr int kUnrollBoth = sizeof(T) == 8 ? 2 : 1;
 
 // One origin x line chunk, executed by the whole workgroup (blockDim.x
 // threads, at least nlc * nbins).  Shared by the single-model launch and the
-// persistent batched launch, so both give bit-identical results.
-template <typename T>
+// persistent batched launch, so both give bit-identical results.  ONE_WIDTH:
+// the model has one Doppler width everywhere (erfc values are then reused
+// between consecutive semi-analytic segments; exact, so results do not
+// depend on it).
+template <typename T, bool ONE_WIDTH>
 __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, const int chunk,
                                              const int ch, unsigned char *smem)
 {
@@ -296,15 +299,29 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
     //   dt = dx sqrt(pi)/4 (cb_P + cb_Q) (erf x_Q - erf x_P) / (b-bar (x_Q - x_P))
     // with x = u / b-bar and x_Q - x_P = (dvQ - dvP) k1 / b-bar, so b-bar
     // cancels outside the erf arguments; half of dx sqrt(pi)/4 / (dvQ - dvP)
-    // comes with the record (rw).  Floored at tau_floor / 2.
+    // comes with the record (rw).  Floored at tau_floor / 2.  With one
+    // Doppler width everywhere every b-bar is the same number, so erfc at Q
+    // is also erfc at the near end of a following semi-analytic segment: it
+    // is kept (ec) and not evaluated twice.  (A template parameter, not a
+    // run-time test: the bookkeeping measured 9 % slower where it never
+    // applies.)
     auto segment = [&](HalfState<T> &st, T chiQ, T uQ, T cbQ) -> T {
         T h;
         if (signbit(st.qdx)) {
             const T xP = st.u * st.sibb;
             const T xQ = uQ * st.sibb;
-            h = (st.cb + cbQ) * erf_diff<T>(xP, xQ) * (st.rw * inv_k1);
+            T eP;
+            if (ONE_WIDTH && st.ec_ok)
+                eP = st.ec;
+            else
+                eP = FM<T>::erfc_scaled(fabs(xP));
+            const T eQ = FM<T>::erfc_scaled(fabs(xQ));
+            h = (st.cb + cbQ) * erf_diff<T>(xP, xQ, eP, eQ) * (st.rw * inv_k1);
+            st.ec = eQ;
+            st.ec_ok = ONE_WIDTH;
         } else {
             h = st.qdx * (st.chi + chiQ);
+            st.ec_ok = false;
         }
         return FM<T>::at_least(h, half_floor);
     };
@@ -326,8 +343,9 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
         A.G = B.G = (T)2;
         A.hm = B.hm = (T)0;
         A.eps = B.eps = bdy_I((T)0);  // replaced at the far end of a non-empty half
-        A.chi = A.S = A.u = A.cb = A.qdx = A.sibb = A.rw = (T)0;
-        B.chi = B.S = B.u = B.cb = B.qdx = B.sibb = B.rw = (T)0;
+        A.chi = A.S = A.u = A.cb = A.qdx = A.sibb = A.rw = A.ec = (T)0;
+        B.chi = B.S = B.u = B.cb = B.qdx = B.sibb = B.rw = B.ec = (T)0;
+        A.ec_ok = B.ec_ok = false;
 
         // point Q (staged record e) of a half: its profile, then either the
         // far-end boundary intensity or one elimination row
@@ -340,9 +358,10 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
             // semi-analytic and never read it: a branch around it measured
             // 12 % slower)
             const T chiQ = FM<T>::chi_phi(lr.lchi, uQ * ma.ib);
-            if (far_end)
+            if (far_end) {
                 s.eps = bdy_I(dvQ);
-            else
+                s.ec_ok = false;
+            } else
                 row(s, segment(s, chiQ, uQ, lr.cb));
             s.chi = chiQ;
             s.S = lr.S;
@@ -462,7 +481,7 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
 // measured faster there (costs of neighbouring origins are correlated).
 constexpr int kXcds = 8;
 
-template <typename T, int MAXT, bool ORDERED>
+template <typename T, int MAXT, bool ORDERED, bool ONE_WIDTH>
 __global__ __launch_bounds__(MAXT) void k_formal_solve(FSArgs<T> a, int ch)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -472,9 +491,9 @@ __global__ __launch_bounds__(MAXT) void k_formal_solve(FSArgs<T> a, int ch)
         // loaded, so uniform only by construction: say so, or every address
         // derived from the origin becomes per-lane
         const int o = __builtin_amdgcn_readfirstlane(a.order[x * q + min(x, r) + b / kXcds]);
-        solve_origin<T>(a, o, blockIdx.y, ch, smem);
+        solve_origin<T, ONE_WIDTH>(a, o, blockIdx.y, ch, smem);
     } else {
-        solve_origin<T>(a, blockIdx.x, blockIdx.y, ch, smem);
+        solve_origin<T, ONE_WIDTH>(a, blockIdx.x, blockIdx.y, ch, smem);
     }
 }
 
@@ -482,7 +501,9 @@ __global__ __launch_bounds__(MAXT) void k_formal_solve(FSArgs<T> a, int ch)
 // one lane class, items ordered longest first so the dispatcher hands out the
 // heavy ones early; workgroups past the live item count or of converged
 // (inactive) models return at once.  The descriptor of the item's model
-// replaces the kernel-argument descriptor of the single-model launch.
+// replaces the kernel-argument descriptor of the single-model launch.  (Lane
+// classes mix models, so the one-width reuse is not used here; it changes
+// no result.)
 template <typename T, int MAXT>
 __global__ __launch_bounds__(MAXT) void k_formal_solve_batch(const FSArgs<T> *__restrict__ descs,
                                                              const int4 *__restrict__ items,
@@ -495,7 +516,7 @@ __global__ __launch_bounds__(MAXT) void k_formal_solve_batch(const FSArgs<T> *__
     if (it >= *count) return;
     const int4 w = items[it];
     if (!active[w.x]) return;
-    solve_origin<T>(descs[w.x], w.y, w.z, ch, smem);
+    solve_origin<T, false>(descs[w.x], w.y, w.z, ch, smem);
 }
 
 template <typename T>
@@ -528,6 +549,20 @@ template hipError_t launch_formal_solve_batch<double>(const FSArgs<double> *, co
                                                       const int *, int, const int *, int, int,
                                                       size_t, hipStream_t);
 
+template <typename T, int MAXT>
+static void launch_fs_variant(const FSArgs<T> &a, dim3 grid, size_t lds, int ch, hipStream_t s)
+{
+    const bool ordered = a.order != nullptr, one = a.one_width != 0;
+    if (ordered && one)
+        k_formal_solve<T, MAXT, true, true><<<grid, a.nthreads, lds, s>>>(a, ch);
+    else if (ordered)
+        k_formal_solve<T, MAXT, true, false><<<grid, a.nthreads, lds, s>>>(a, ch);
+    else if (one)
+        k_formal_solve<T, MAXT, false, true><<<grid, a.nthreads, lds, s>>>(a, ch);
+    else
+        k_formal_solve<T, MAXT, false, false><<<grid, a.nthreads, lds, s>>>(a, ch);
+}
+
 template <typename T>
 hipError_t launch_formal_solve(const FSArgs<T> &a, hipStream_t s)
 {
@@ -541,18 +576,13 @@ hipError_t launch_formal_solve(const FSArgs<T> &a, hipStream_t s)
     dim3 grid(a.N, nchunks);
     // double keeps more state live per lane: a 512-thread bound leaves it 256
     // VGPRs (no spills); 1024 only when one line has more than 512 bins
-    const bool ordered = a.order != nullptr;
-    if (sizeof(T) == 8 && a.nthreads <= 512) {
-        if (ordered)
-            k_formal_solve<T, 512, true><<<grid, a.nthreads, L.total, s>>>(a, ch);
-        else
-            k_formal_solve<T, 512, false><<<grid, a.nthreads, L.total, s>>>(a, ch);
-    } else {
-        if (ordered)
-            k_formal_solve<T, 1024, true><<<grid, a.nthreads, L.total, s>>>(a, ch);
-        else
-            k_formal_solve<T, 1024, false><<<grid, a.nthreads, L.total, s>>>(a, ch);
+    if constexpr (sizeof(T) == 8) {
+        if (a.nthreads <= 512) {
+            launch_fs_variant<T, 512>(a, grid, L.total, ch, s);
+            return hipGetLastError();
+        }
     }
+    launch_fs_variant<T, 1024>(a, grid, L.total, ch, s);
     return hipGetLastError();
 }
 

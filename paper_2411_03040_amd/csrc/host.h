@@ -103,7 +103,8 @@ using namespace mgxh;
 // image is made from (own copies, so an image never races an iteration).
 struct RenderBufs {
     DMem proj, pix, off, walk, img;
-    DMem chiT, ST, S64, cnt;
+    DMem chiT, ST, S64, cnt, act;
+    std::vector<int32_t> act_host;  // lines that can be seen in the image's band
     void *scan_tmp = nullptr;
     size_t scan_tmp_bytes = 0;
     RenderBufs() = default;
@@ -112,7 +113,8 @@ struct RenderBufs {
     ~RenderBufs() { release(); }
     void release()
     {
-        for (DMem *m : {&proj, &pix, &off, &walk, &img, &chiT, &ST, &S64, &cnt}) m->release();
+        for (DMem *m : {&proj, &pix, &off, &walk, &img, &chiT, &ST, &S64, &cnt, &act})
+            m->release();
         if (scan_tmp) (void)hipFree(scan_tmp);
         scan_tmp = nullptr;
         scan_tmp_bytes = 0;
@@ -120,7 +122,7 @@ struct RenderBufs {
     size_t bytes() const
     {
         return proj.bytes + pix.bytes + off.bytes + walk.bytes + img.bytes + chiT.bytes +
-               ST.bytes + S64.bytes + cnt.bytes + scan_tmp_bytes;
+               ST.bytes + S64.bytes + cnt.bytes + act.bytes + scan_tmp_bytes;
     }
 };
 
@@ -135,6 +137,9 @@ struct mgx_ctx {
     bool loaded = false, traced = false, have_pops = false, have_rad = false;
     int dim = 3, N = 0, R = 0, nlev = 0, nlines = 0, ncoll_tr = 0, nbins = 0, npairs = 0;
     double mass = 0, xmax = 5, Tcmb = 2.72548, L_unit = 1;
+    bool one_width = false;  // T and v_turb^2 the same at every point
+    double vmax = 0, bmax = 0;  // largest |v| and Doppler width b over the points
+    std::vector<double> nu_host;  // line centres
     int64_t n_records = 0;
 
     DMem pos, vel, nbs_off, nbs, bdy, T, vturb2, nspec, ncoll, ray_dir, ray_w, antipode;

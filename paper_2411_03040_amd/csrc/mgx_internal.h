@@ -104,6 +104,7 @@ struct FSArgs {
     double tau_floor;
     double *J, *L;          // [N][nlines]
     const int32_t *order;   // [N] origins in Morton order of their positions
+    int one_width;          // every point has the same Doppler width b
 };
 
 struct LineArgs {
@@ -205,6 +206,8 @@ struct RenderArgs {
     const T *chi, *S;          // [N][nlines] scaled opacity factor and S / I_img
     const double *b, *ib;      // [N] b and 1/b
     const double *nu_line;     // [nlines]
+    const int32_t *act;        // [nact] lines that can reach the band (others add exact zeros)
+    int nact;
     double inv_L, f_min, f_max, Tcmb, I_img;
     double thr;                // branch threshold (widths)
     const double *b2;          // [N] squared Doppler speed (branch rule in FP64)

@@ -20,9 +20,13 @@
 // into scalar registers, and only the per-frequency arithmetic is per lane.
 // Source functions arrive in units of the image's intensity unit, and the
 // profile offsets are scaled by sqrt(log2 e) in FP32 so that each Gaussian is
-// one base-2 exponential.  On semi-analytic segments, lines that lie in one
-// far wing at both ends for the whole wave (both erfc exactly zero) are
-// skipped by a wave vote.
+// one base-2 exponential.  Opacities and semi-analytic terms are summed over
+// the lines that can reach the image's band (a list the host derives from
+// the model's largest speed and width; the others would add exact zeros),
+// and on semi-analytic segments lines that lie in one far wing at both ends
+// for the whole wave (both erfc exactly zero) are skipped by a wave vote.
+// The source-function fallback where every profile underflows still ranks
+// all lines.
 
 #include "mgx_internal.h"
 
@@ -121,6 +125,8 @@ __global__ __launch_bounds__(256) void k_render_integrate(RenderArgs<T> a, int n
     const int t = threadIdx.x;
     const int nl = a.nlines;
     const gptr<double> nu_line = glob(a.nu_line);
+    const gptr<int32_t> act = glob(a.act);
+    const int nact = a.nact;
     // 64 frequencies of one pixel per wave: the pixel, its walk and every
     // point datum are wave-uniform (scalar registers and loads)
     const int slice =
@@ -184,8 +190,11 @@ __global__ __launch_bounds__(256) void k_render_integrate(RenderArgs<T> a, int n
         // source functions, in one pass; where every profile underflows the
         // source function is the same mean with weights relative to the
         // nearest line, exp(-(x_l^2 - x_min^2)) (the limit of eta / chi)
+        // (only the lines that can reach the band: the others add exact
+        // zeros, in the same order)
         T chi1 = (T)0, sws = (T)0;
-        for (int l = 0; l < nl; l++) {
+        for (int j = 0; j < nact; j++) {
+            const int l = act[j];
             const LineLane<T> e = line_lane(l);
             const T x = (e.cd - e.rr * w) * ibg;
             const T c = chi_p[l] * RM<T>::gauss(x * x);
@@ -227,7 +236,8 @@ __global__ __launch_bounds__(256) void k_render_integrate(RenderArgs<T> a, int n
                 const T w0 = (T)w0d;
                 const gptr<T> chi_q = chi + (int64_t)p0 * nl;
                 const T ddt = (T)dd;
-                for (int l = 0; l < nl; l++) {
+                for (int j = 0; j < nact; j++) {
+                    const int l = act[j];
                     const LineLane<T> e = line_lane(l);
                     const T xa = (e.cd - e.rr * w0) * ibb;
                     const T xb = (e.cd - e.rr * w) * ibb;

@@ -95,6 +95,32 @@ def test_batch_equals_single_context(mgx, prec, tol):
         assert bits_equal(got, p1), (i, rel(got, p1))
 
 
+@pytest.mark.parametrize("prec,tol", [(0, 1e-12), (1, 1e-7)])
+def test_one_width_model_batch_equals_single(mgx, prec, tol):
+    """A moving model with one Doppler width everywhere: the single-model
+    launch reuses erfc values between consecutive semi-analytic segments, the
+    batched launch does not; the populations must still agree bit for bit."""
+    m = synth.outflow_3d(npoints=300, seed=5, nside=1, nlev=4, nbins=15)
+    m.T[:] = 300.0
+    assert np.ptp(m.vturb2) == 0
+    c = mgx.Context(precision=prec)
+    c.load_model(m)
+    c.trace_rays()
+    c.set_lte_populations()
+    c.formal_solve()
+    assert c.counters()["semi_segments"] > 0
+    b = mgx.Batch(precision=prec)
+    b.add_model(m)
+    b.prepare()
+    b.set_lte_populations()
+    its, chg, nconv = b.iterate(tol=tol, max_iter=800, ng_order=4)
+    assert nconv == 1
+    it1, p1 = single(mgx, m, prec, tol, 4)
+    got = b.get_populations(0)
+    say(f"  one width, precision {prec}: iters {its[0]} / {it1}, rel {rel(got, p1):.3e}")
+    assert its[0] == it1 and bits_equal(got, p1)
+
+
 @pytest.mark.parametrize("prec,tol,bar", [(0, 1e-12, 1e-10), (1, 1e-7, 1e-4)])
 def test_batch_against_oracle(mgx, prec, tol, bar):
     models = [synth.outflow_3d(npoints=300, seed=5, nside=1, nlev=4, nbins=15),

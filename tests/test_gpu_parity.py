@@ -213,6 +213,17 @@ def test_formal_solve_many_line_chunks(mgx):
     fs_compare(mgx, m, mgx.FP32, tolJ=1e-5, tolL=1e-5)
 
 
+def test_formal_solve_one_width_moving_cloud(mgx):
+    """One Doppler width everywhere (uniform T and v_turb) with steep
+    velocities: consecutive semi-analytic segments share erfc values."""
+    m = synth.tiny_cloud(npoints=300, seed=31, k=12, nside=2, nlev=4, nbins=15, vmax=6e3)
+    m.T[:] = 80.0
+    ctx, _, _ = fs_compare(mgx, m, mgx.FP64, tolJ=1e-10, tolL=1e-10)
+    c = ctx.counters()
+    assert c["semi_segments"] > 0.5 * c["total_records"]
+    fs_compare(mgx, m, mgx.FP32, tolJ=1e-5, tolL=1e-5)
+
+
 def test_formal_solve_maximum_bins(mgx):
     """The largest bin count (1024): one line per 1024-lane workgroup, the
     widest launch of either precision; steep velocities, so semi-analytic
@@ -508,6 +519,11 @@ def test_render_many_lines(mgx, prec, tol):
                             nu0 * (1 + 3e-5), 70, pix, tol)
     # the lines are seen: the image is not the CMB everywhere
     assert np.ptp(img) > 1e-3 * np.max(np.abs(img))
+    # a band between lines (all lie at even multiples of B): no line reaches
+    # it, every profile underflows, the pixels see the CMB
+    nu7 = 3.5 * nu0 / 3.0
+    render_compare(mgx, m, prec, [0.6, -0.3, 0.74], 6, 6, nu7 * (1 - 3e-5), nu7 * (1 + 3e-5), 9,
+                   pix, tol)
 
 
 def test_render_steep_gradient_column(mgx):
