@@ -216,7 +216,10 @@ __global__ __launch_bounds__(256) void k_render_integrate(RenderArgs<T> a, int n
             for (int l = 0; l < nl; l++) {
                 const LineLane<T> e = line_lane(l);
                 const T x = (e.cd - e.rr * w) * ibg;
-                const T wt = chi_p[l] * RM<T>::gauss(x * x - x2min);
+                // (clamped: the square of the nearest line's offset may be
+                // fused into this subtraction unrounded, leaving a residue of
+                // either sign, large where the offsets are)
+                const T wt = chi_p[l] * RM<T>::gauss(fmax(x * x - x2min, (T)0));
                 sw += wt;
                 sws += wt * S_p[l];
             }
