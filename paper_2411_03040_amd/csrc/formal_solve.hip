@@ -55,11 +55,6 @@ struct FM;
 
 template <>
 struct FM<float> {
-    // exp(-x^2) with x already multiplied by sqrt(log2 e)
-    static __device__ __forceinline__ float phi_scaled(float xs)
-    {
-        return __builtin_amdgcn_exp2f(-(xs * xs));
-    }
     // chi' exp(-x^2) as exp2(log2 chi' - xs^2), xs = x sqrt(log2 e): the
     // staged line record carries log2 chi'
     static __device__ __forceinline__ float log_scale(float chi) { return __builtin_amdgcn_logf(chi); }
@@ -113,7 +108,6 @@ struct FM<float> {
 
 template <>
 struct FM<double> {
-    static __device__ __forceinline__ double phi_scaled(double x) { return exp(-(x * x)); }
     static __device__ __forceinline__ double log_scale(double chi) { return chi; }
     static __device__ __forceinline__ double chi_phi(double chi, double x)
     {
