@@ -705,7 +705,9 @@ StateqArgs mgxh::stateq_args(mgx_ctx *ctx)
     s.nlev = ctx->nlev;
     s.nlines = ctx->nlines;
     s.ncoll_tr = ctx->ncoll_tr;
-    const size_t per_wave = sizeof(double) * ctx->nlev * (ctx->nlev + 1);
+    s.group = stateq_group(ctx->nlev);
+    const size_t per_wave =
+        sizeof(double) * ctx->nlev * (ctx->nlev + 1) * (size_t)(64 / s.group);
     s.wpb = (int)std::max<size_t>(1, std::min<size_t>(4, (48 * 1024) / per_wave));
     s.J = ctx->J.as<double>();
     s.L = ctx->L.as<double>();

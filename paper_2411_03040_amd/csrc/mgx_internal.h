@@ -121,7 +121,8 @@ struct LineArgs {
 };
 
 struct StateqArgs {
-    int N, nlev, nlines, ncoll_tr, wpb;
+    int N, nlev, nlines, ncoll_tr;
+    int group, wpb;        // lanes per point (stateq_group), waves per block
     const double *J, *L, *S64;
     const double *T, *ncoll;
     const double *E, *g;
@@ -165,6 +166,7 @@ hipError_t launch_copy_if_active(int64_t n, const double *src, double *dst, cons
 hipError_t launch_gather_changes(int M, Counters *const *cnt, double *out, hipStream_t s);
 hipError_t launch_lte(int N, int nlev, const double *T, const double *E, const double *g,
                       double *pops, hipStream_t s);
+int stateq_group(int nlev);  // lanes per point of the statistical-equilibrium kernel
 hipError_t launch_stateq(const StateqArgs &a, hipStream_t s);
 hipError_t launch_reset_counters(Counters *c, hipStream_t s);
 hipError_t launch_rel_change(int64_t n, const double *a, const double *b, double floor_,

@@ -72,21 +72,29 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
+// One group of G lanes per point (G the smallest of 8, 16, 32, 64 that is at
+// least the level count, so a wave solves 64 / G points side by side); the
+// point's rate matrix sits in LDS, row i belongs to lane i of the group.
+// Gaussian elimination with partial pivoting (largest magnitude, ties to
+// the lower row), then back substitution; singular systems keep the old
+// populations and are counted.
 __global__ __launch_bounds__(256) void k_stateq(StateqArgs a)
 {
     extern __shared__ double sm[];
     if (a.active && !a.active[a.model]) return;  // uniform over the grid
+    const int L = a.nlev, L1 = L + 1, G = a.group;
     const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int L = a.nlev, L1 = L + 1;
-    double *M = sm + (size_t)wid * L * L1;
-    const int p = blockIdx.x * a.wpb + wid;
+    const int grp = lane / G, gl = lane - grp * G;
+    const int ppw = 64 / G;
+    double *M = sm + ((size_t)wid * ppw + grp) * L * L1;
+    const int p = (blockIdx.x * a.wpb + wid) * ppw + grp;
     const bool valid = p < a.N;
     const int pp = valid ? p : 0;
 
-    for (int i = lane; i < L * L1; i += 64) M[i] = 0.0;
+    for (int i = gl; i < L * L1; i += G) M[i] = 0.0;
     __syncthreads();
     if (valid) {
-        for (int t = lane; t < a.nlines; t += 64) {
+        for (int t = gl; t < a.nlines; t += G) {
             const int u = a.up[t], lw = a.lo[t];
             const int64_t pl = (int64_t)pp * a.nlines + t;
             const double Ls = a.L[pl];
@@ -99,7 +107,7 @@ __global__ __launch_bounds__(256) void k_stateq(StateqArgs a)
     if (valid) {
         const double T = a.T[pp];
         const double sq = sqrt(T / 100.0);
-        for (int t = lane; t < a.ncoll_tr; t += 64) {
+        for (int t = gl; t < a.ncoll_tr; t += G) {
             const int u = a.cu[t], lw = a.cl[t];
             const double Cul = a.ncoll[pp] * a.K0[t] * sq;
             const double Clu = Cul * (a.g[u] / a.g[lw]) * exp(-(a.E[u] - a.E[lw]) / (kKB * T));
@@ -108,59 +116,58 @@ __global__ __launch_bounds__(256) void k_stateq(StateqArgs a)
         }
     }
     __syncthreads();
-    if (lane < L) {
+    if (gl < L) {
         double s = 0.0;
         for (int j = 0; j < L; j++)
-            if (j != lane) s += M[j * L1 + lane];
-        M[lane * L1 + lane] = -s;
+            if (j != gl) s += M[j * L1 + gl];
+        M[gl * L1 + gl] = -s;
     }
     __syncthreads();
-    if (lane < L) {
-        M[lane] = 1.0;                                   // row 0: sum f = 1
-        M[lane * L1 + L] = (lane == 0) ? 1.0 : 0.0;      // right-hand side
+    if (gl < L) {
+        M[gl] = 1.0;                                 // row 0: sum f = 1
+        M[gl * L1 + L] = (gl == 0) ? 1.0 : 0.0;      // right-hand side
     }
     __syncthreads();
 
-    bool singular = false;
+    bool singular = false;  // uniform over the group
     for (int k = 0; k < L; k++) {
-        double v = (lane >= k && lane < L) ? fabs(M[lane * L1 + k]) : -1.0;
-        int idx = lane;
-#pragma unroll
-        for (int m = 32; m >= 1; m >>= 1) {
-            const double ov = __shfl_xor(v, m, 64);
-            const int oi = __shfl_xor(idx, m, 64);
+        double v = (gl >= k && gl < L) ? fabs(M[gl * L1 + k]) : -1.0;
+        int idx = gl;
+        for (int m = G >> 1; m >= 1; m >>= 1) {
+            const double ov = __shfl_xor(v, m, G);
+            const int oi = __shfl_xor(idx, m, G);
             if (ov > v || (ov == v && oi < idx)) {
                 v = ov;
                 idx = oi;
             }
         }
-        if (!(v >= 1e-300)) singular = true;  // uniform across the wave
+        if (!(v >= 1e-300)) singular = true;
         if (!singular && idx != k) {
-            for (int j = lane; j <= L; j += 64) {
+            for (int j = gl; j <= L; j += G) {
                 const double t = M[k * L1 + j];
                 M[k * L1 + j] = M[idx * L1 + j];
                 M[idx * L1 + j] = t;
             }
         }
         __syncthreads();
-        if (!singular && lane > k && lane < L) {
-            const double fct = M[lane * L1 + k] / M[k * L1 + k];
-            for (int j = k; j <= L; j++) M[lane * L1 + j] -= fct * M[k * L1 + j];
+        if (!singular && gl > k && gl < L) {
+            const double fct = M[gl * L1 + k] / M[k * L1 + k];
+            for (int j = k; j <= L; j++) M[gl * L1 + j] -= fct * M[k * L1 + j];
         }
         __syncthreads();
     }
     for (int i = L - 1; i >= 0; i--) {
-        if (!singular && lane == i) M[i * L1 + L] /= M[i * L1 + i];
+        if (!singular && gl == i) M[i * L1 + L] /= M[i * L1 + i];
         __syncthreads();
-        if (!singular && lane < i) M[lane * L1 + L] -= M[lane * L1 + i] * M[i * L1 + L];
+        if (!singular && gl < i) M[gl * L1 + L] -= M[gl * L1 + i] * M[i * L1 + L];
         __syncthreads();
     }
 
     double ch = 0.0;
-    if (valid && lane < L) {
-        const int64_t pi = (int64_t)p * L + lane;
+    if (valid && gl < L) {
+        const int64_t pi = (int64_t)p * L + gl;
         const double old = a.pops_old[pi];
-        double nw = singular ? old : M[lane * L1 + L];
+        double nw = singular ? old : M[gl * L1 + L];
         if (!isfinite(nw)) {
             atomicAdd(&a.cnt->nonfinite, 1ull);
         }
@@ -168,17 +175,24 @@ __global__ __launch_bounds__(256) void k_stateq(StateqArgs a)
         const double den = nw > a.pop_floor ? nw : a.pop_floor;
         ch = fabs(nw - old) / den;
     }
+    if (valid && gl == 0 && singular) atomicAdd(&a.cnt->singular, 1ull);
     ch = wave_max(ch);
-    if (valid && lane == 0) {
-        atomic_max_nonneg(&a.cnt->change_bits, ch);
-        if (singular) atomicAdd(&a.cnt->singular, 1ull);
-    }
+    if (lane == 0) atomic_max_nonneg(&a.cnt->change_bits, ch);
+}
+
+int stateq_group(int nlev)
+{
+    return nlev <= 8 ? 8 : nlev <= 16 ? 16 : nlev <= 32 ? 32 : 64;
 }
 
 hipError_t launch_stateq(const StateqArgs &a, hipStream_t s)
 {
-    const size_t per_wave = sizeof(double) * a.nlev * (a.nlev + 1);
-    const int blocks = (a.N + a.wpb - 1) / a.wpb;
+    if (a.group != stateq_group(a.nlev) || a.wpb < 1) return hipErrorInvalidValue;
+    const int ppw = 64 / a.group;
+    const size_t per_wave = sizeof(double) * a.nlev * (a.nlev + 1) * ppw;
+    const int64_t per_block = (int64_t)a.wpb * ppw;
+    const int blocks = (int)((a.N + per_block - 1) / per_block);
+    if (blocks == 0) return hipSuccess;
     k_stateq<<<blocks, 64 * a.wpb, per_wave * a.wpb, s>>>(a);
     return hipGetLastError();
 }

@@ -262,6 +262,35 @@ def test_formal_solve_isolated_points_and_holes(mgx):
     fs_compare(mgx, m, mgx.FP32, tolJ=1e-5, tolL=1e-5)
 
 
+def _first_points(m, n):
+    """The model restricted to its first n points (neighbour lists cut to
+    them)."""
+    lists = [[j for j in m.nbs[m.nbs_off[i]:m.nbs_off[i + 1]] if j < n] for i in range(n)]
+    c = m.copy()
+    c.pos, c.vel = m.pos[:, :n].copy(), m.vel[:, :n].copy()
+    c.nbs_off = np.concatenate([[0], np.cumsum([len(x) for x in lists])]).astype(np.int32)
+    c.nbs = np.array([j for x in lists for j in x], np.int32)
+    for f in ("bdy", "T", "vturb2", "nspec", "ncoll"):
+        setattr(c, f, getattr(m, f)[:n].copy())
+    return c
+
+
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_formal_solve_smallest_models(mgx, n):
+    """Degenerate clouds: a single point (both halves of every pair empty),
+    two and three points; the Lambda-iteration runs on them too."""
+    m = _first_points(synth.tiny_cloud(npoints=8, seed=32, nside=1, nlev=3, nbins=7), n)
+    assert m.npoints == n
+    for prec, tol in ((mgx.FP64, 1e-10), (mgx.FP32, 1e-5)):
+        fs_compare(mgx, m, prec, tolJ=tol, tolL=tol)
+    r = oracle.Oracle(m).iterate(tol=1e-12, max_iter=500)
+    assert r["status"] == 0
+    c = make_ctx(mgx, m, mgx.FP64)
+    c.set_lte_populations()
+    it, ch, ok = c.iterate(tol=1e-12, max_iter=500)
+    assert ok and rel(c.get_populations(), r["pops"]) < 1e-10
+
+
 def test_formal_solve_deterministic(mgx):
     m = synth.tiny_cloud(npoints=400, seed=28, k=12, nside=2, nlev=5)
     orc = oracle.Oracle(m)
