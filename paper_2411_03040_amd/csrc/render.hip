@@ -41,8 +41,17 @@ struct RM<float> {
     // exp(-x^2) is one base-2 exponential of the scaled square
     static constexpr double gauss_k = 1.2011224087864498;  // sqrt(log2 e)
     static __device__ __forceinline__ float gauss(float xs2) { return __builtin_amdgcn_exp2f(-xs2); }
-    static __device__ __forceinline__ float em1(float x) { return expm1f(x); }
+    // e^x - 1 for x <= -0.1 only (the linear-source weights use a series
+    // above): exp2 - 1, relative error < 1e-6 there
+    static __device__ __forceinline__ float em1(float x)
+    {
+        return __builtin_amdgcn_exp2f(x * 1.44269504f) - 1.0f;
+    }
     static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+    static __device__ __forceinline__ float div(float a, float b) { return a * rcp(b); }
+    // 1 / sqrt(v) of the averaged squared width (the branch rule itself is
+    // decided in FP64)
+    static __device__ __forceinline__ float rsqrt_w(double v) { return __builtin_amdgcn_rsqf((float)v); }
     // erfc for x >= 0, branch-free (Numerical Recipes' Chebyshev form
     // erfc(x) = t exp(-x^2 + P(t)), t = 1/(1 + x/2), fractional error
     // < 1.2e-7), so the bins of a wave never diverge
@@ -74,6 +83,8 @@ struct RM<double> {
     static __device__ __forceinline__ double gauss(double x2) { return exp(-x2); }
     static __device__ __forceinline__ double em1(double x) { return expm1(x); }
     static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+    static __device__ __forceinline__ double div(double a, double b) { return a / b; }
+    static __device__ __forceinline__ double rsqrt_w(double v) { return 1.0 / sqrt(v); }
     static __device__ __forceinline__ double erfc_(double x) { return erfc(x); }
     static constexpr double series_below = 1e-4;
     static constexpr double tiny = 1e-290;
@@ -98,12 +109,15 @@ __device__ __forceinline__ void lin_weights(T t, T &att, T &w0, T &w1)
     if (t < RM<T>::series_below) {
         att = RM<T>::ex(-t);
         const T t2 = t * t, t3 = t2 * t, t4 = t3 * t, t5 = t4 * t;
-        w0 = t / 2 - t2 / 3 + t3 / 8 - t4 / 30 + t5 / 144;
-        w1 = t / 2 - t2 / 6 + t3 / 24 - t4 / 120 + t5 / 720;
+        // (coefficients as reciprocal constants: no division per point)
+        w0 = t * (T)0.5 - t2 * (T)(1.0 / 3) + t3 * (T)0.125 - t4 * (T)(1.0 / 30) +
+             t5 * (T)(1.0 / 144);
+        w1 = t * (T)0.5 - t2 * (T)(1.0 / 6) + t3 * (T)(1.0 / 24) - t4 * (T)(1.0 / 120) +
+             t5 * (T)(1.0 / 720);
         return;
     }
     const T em = RM<T>::em1(-t);
-    const T a = -em / t;
+    const T a = RM<T>::div(-em, t);
     att = (T)1 + em;
     w0 = a - att;
     w1 = (T)1 - a;
@@ -203,7 +217,7 @@ __global__ __launch_bounds__(256) void k_render_integrate(RenderArgs<T> a, int n
         }
         T S1;
         if (chi1 > RM<T>::tiny) {
-            S1 = sws / chi1;
+            S1 = RM<T>::div(sws, chi1);
         } else {
             T x2min = (T)INFINITY;
             for (int l = 0; l < nl; l++) {
@@ -223,6 +237,8 @@ __global__ __launch_bounds__(256) void k_render_integrate(RenderArgs<T> a, int n
                 sw += wt;
                 sws += wt * S_p[l];
             }
+            // (IEEE division: the weights may be denormal, where the
+            // hardware reciprocal flushes to infinity)
             S1 = sw > (T)0 ? sws / sw : (T)0;
         }
         const double Zd = Zv[p], b2d = b2v[p];
@@ -234,7 +250,7 @@ __global__ __launch_bounds__(256) void k_render_integrate(RenderArgs<T> a, int n
             const T dx = (T)((Zd - Z0) * a.inv_L);
             T dt = (T)0;
             if (semi) {
-                const T ibb = (T)(1.0 / sqrt((b20 + b2d) * 0.5));
+                const T ibb = RM<T>::rsqrt_w((b20 + b2d) * 0.5);
                 const T b0 = (T)bv[p0], b1 = (T)bv[p];
                 const T w0 = (T)w0d;
                 const gptr<T> chi_q = chi + (int64_t)p0 * nl;
