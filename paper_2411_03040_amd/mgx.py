@@ -523,7 +523,9 @@ class Server:
                       f_max: float, nfreq: int, out=None) -> int:
         d = (C.c_double * 3)(*[float(x) for x in direction])
         if out is None:
-            out = _host_image(npy, npx, nfreq)
+            # pageable: many requests may be in flight at once, and page-locked
+            # memory is a scarce host resource
+            out = np.empty((npy, npx, nfreq), np.float32)
         rid = C.c_int64()
         self._check(lib().mgx_server_submit_render(self._h, model, d, npx, npy, f_min, f_max,
                                                    nfreq, _ptr(out), C.byref(rid)))
