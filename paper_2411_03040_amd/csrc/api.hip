@@ -1025,15 +1025,37 @@ void mgxh::render_image(mgx_ctx *ctx, RenderBufs &rb, const double *pops, hipStr
     int64_t *off = g.counts + (npix + 1);
     HIPCHK(hipMemsetAsync(g.counts, 0, sizeof(int64_t) * (npix + 1), s));
     HIPCHK(launch_render_geometry(g, s));
-    HIPCHK(launch_render_walk(g, false, s));
-    HIPCHK(mgx_internal_scan(g.counts, off, npix + 1, &rb.scan_tmp, &rb.scan_tmp_bytes, s));
-    int64_t total = 0;
-    HIPCHK(hipMemcpyAsync(&total, off + npix, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    rb.walk.ensure(sizeof(int32_t) * (size_t)(total > 0 ? total : 1));
-    g.off = off;
-    g.walk = rb.walk.as<int32_t>();
-    HIPCHK(launch_render_walk(g, true, s));
+    // One pass into fixed slots of cap points (the expected walk length) when
+    // they fit 256 MiB.  A walk longer than its slot sends the image through
+    // the exact two-pass route (lengths, offsets, walks), whose lengths the
+    // first pass has already written.
+    const int64_t cap = render_walk_cap(N);
+    bool csr = (size_t)npix * (size_t)cap * sizeof(int32_t) > (size_t(256) << 20);
+    if (!csr) {
+        rb.walk.ensure(sizeof(int32_t) * (size_t)npix * (size_t)cap);
+        rb.maxn.ensure(sizeof(unsigned long long));
+        g.cap = cap;
+        g.maxn = rb.maxn.as<unsigned long long>();
+        g.walk = rb.walk.as<int32_t>();
+        HIPCHK(hipMemsetAsync(g.maxn, 0, sizeof(unsigned long long), s));
+        HIPCHK(launch_render_walk(g, WalkMode::capped, s));
+        unsigned long long longest = 0;
+        HIPCHK(hipMemcpyAsync(&longest, g.maxn, sizeof(longest), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        csr = (int64_t)longest > cap;
+    } else {
+        HIPCHK(launch_render_walk(g, WalkMode::count, s));
+    }
+    if (csr) {
+        HIPCHK(mgx_internal_scan(g.counts, off, npix + 1, &rb.scan_tmp, &rb.scan_tmp_bytes, s));
+        int64_t total = 0;
+        HIPCHK(hipMemcpyAsync(&total, off + npix, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        rb.walk.ensure(sizeof(int32_t) * (size_t)(total > 0 ? total : 1));
+        g.off = off;
+        g.walk = rb.walk.as<int32_t>();
+        HIPCHK(launch_render_walk(g, WalkMode::fill, s));
+    }
     rb.img.ensure(sizeof(float) * (size_t)npix * nfreq);
     // Lines whose profile can reach the band.  At a point moving with w
     // (|w| <= vmax) and width b (<= bmax) the offset of frequency nu from line
@@ -1066,7 +1088,9 @@ void mgxh::render_image(mgx_ctx *ctx, RenderBufs &rb, const double *pops, hipStr
         ra.npy = npy;
         ra.nfreq = nfreq;
         ra.nlines = ctx->nlines;
-        ra.off = off;
+        ra.off = csr ? off : nullptr;
+        ra.cnt = g.counts;
+        ra.cap = cap;
         ra.walk = g.walk;
         ra.Z = g.Z;
         ra.w = g.w;

@@ -103,7 +103,7 @@ using namespace mgxh;
 // image is made from (own copies, so an image never races an iteration).
 struct RenderBufs {
     DMem proj, pix, off, walk, img;
-    DMem chiT, ST, S64, cnt, act;
+    DMem chiT, ST, S64, cnt, act, maxn;
     std::vector<int32_t> act_host;  // lines that can be seen in the image's band
     void *scan_tmp = nullptr;
     size_t scan_tmp_bytes = 0;
@@ -113,7 +113,7 @@ struct RenderBufs {
     ~RenderBufs() { release(); }
     void release()
     {
-        for (DMem *m : {&proj, &pix, &off, &walk, &img, &chiT, &ST, &S64, &cnt, &act})
+        for (DMem *m : {&proj, &pix, &off, &walk, &img, &chiT, &ST, &S64, &cnt, &act, &maxn})
             m->release();
         if (scan_tmp) (void)hipFree(scan_tmp);
         scan_tmp = nullptr;
@@ -122,7 +122,7 @@ struct RenderBufs {
     size_t bytes() const
     {
         return proj.bytes + pix.bytes + off.bytes + walk.bytes + img.bytes + chiT.bytes +
-               ST.bytes + S64.bytes + cnt.bytes + act.bytes + scan_tmp_bytes;
+               ST.bytes + S64.bytes + cnt.bytes + act.bytes + maxn.bytes + scan_tmp_bytes;
     }
 };
 
@@ -284,6 +284,9 @@ void ng_reset(mgx_ctx *ctx, int capacity);
 void ng_append(mgx_ctx *ctx);
 int ng_predict(mgx_ctx *ctx, double *pred_change);
 void ng_apply(mgx_ctx *ctx, bool accepted);
+// expected points per pixel walk (4 N^(1/3) + 16): the slot size of the
+// one-pass walk and the server's footprint estimate
+inline int64_t render_walk_cap(int N) { return (int64_t)(4.0 * cbrt((double)N) + 16.0); }
 void check_render_args(const double dir[3], int npx, int npy, double f_min, double f_max,
                        int nfreq);
 // Synthetic image of populations `pops` of the model in ctx, on stream s,

@@ -195,14 +195,21 @@ struct RenderGeom {
     int64_t *counts;           // [npx npy + 1]
     const int64_t *off;        // [npx npy + 1]
     int32_t *walk;             // records
+    int64_t cap;               // capped fill: pixel i's walk at walk[i cap], at most cap points
+    unsigned long long *maxn;  // capped fill: longest walk (atomic max)
 };
 hipError_t launch_render_geometry(RenderGeom &g, hipStream_t s);  // project + extent + entry
-hipError_t launch_render_walk(const RenderGeom &g, bool fill, hipStream_t s);
+// walk lengths only (counts), walks at CSR offsets (off), or walks in slots of
+// g.cap points with exact lengths in counts and the longest in *maxn
+enum class WalkMode { count, fill, capped };
+hipError_t launch_render_walk(const RenderGeom &g, WalkMode mode, hipStream_t s);
 
 template <typename T>
 struct RenderArgs {
     int npx, npy, nfreq, nlines;
-    const int64_t *off;
+    const int64_t *off;        // CSR offsets of the walks, or null: slots of cap points
+    const int64_t *cnt;        // with off null: walk lengths
+    int64_t cap;
     const int32_t *walk;
     const double *Z, *w;       // [N] (double; scaled inside)
     const T *chi, *S;          // [N][nlines] scaled opacity factor and S / I_img

@@ -170,12 +170,14 @@ __global__ __launch_bounds__(256) void k_render_integrate(RenderArgs<T> a, int n
             e.rr = (T)(nu / nu_line[l]);
             tab[l] = e;
         }
-    const gptr<int64_t> off = glob(a.off);
+    const gptr<int64_t> off = glob(a.off), cnt = glob(a.cnt);
     const gptr<int32_t> walk = glob(a.walk);
     const gptr<double> Wv = glob(a.w), Zv = glob(a.Z), bv = glob(a.b), ibv = glob(a.ib);
     const gptr<double> b2v = glob(a.b2);
     const gptr<T> chi = glob(a.chi), Sv = glob(a.S);
-    const int64_t o0 = off[pix], n = off[pix + 1] - o0;
+    // the pixel's walk: at CSR offsets, or in its slot of cap points
+    const int64_t o0 = a.off ? off[pix] : (int64_t)pix * a.cap;
+    const int64_t n = a.off ? off[pix + 1] - o0 : cnt[pix];
     float *out = a.img + (int64_t)pix * a.nfreq + f;
     auto planck_n = [&](double nup) -> double {  // B_nu(Tcmb) / I_img
         const double r = nup / f_mid;

@@ -112,7 +112,7 @@ size_t render_footprint(const mgx_ctx *c, int npx, int npy, int nfreq)
 {
     const size_t npix = (size_t)npx * npy;
     const size_t tsz = c->fp32() ? sizeof(float) : sizeof(double);
-    const size_t walk = (size_t)(4.0 * cbrt((double)c->N) + 16.0);
+    const size_t walk = (size_t)render_walk_cap(c->N);
     return (size_t)c->nrad() * (2 * tsz + sizeof(double)) + 32 * (size_t)c->N + 12 * npix +
            16 * (npix + 1) + 4 * npix * walk + 4 * npix * (size_t)nfreq + (1 << 16);
 }

@@ -455,9 +455,13 @@ hipError_t launch_render_geometry(RenderGeom &g, hipStream_t s)
 
 // Pixel walk: 16 lanes per pixel as in the ray trace, distances measured
 // from the pixel line; the entry point is the first record.
-template <bool FILL>
+// MODE 0: lengths only; 1: walks at CSR offsets; 2: walks in fixed slots of
+// g.cap points (longer walks are cut there but their full lengths recorded,
+// with the longest in *g.maxn, so the caller can redo them exactly).
+template <int MODE>
 __global__ __launch_bounds__(256) void k_render_walk(RenderGeom g)
 {
+    constexpr bool FILL = MODE != 0;
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t pix = gid >> 4;
     const int l16 = threadIdx.x & 15;
@@ -469,7 +473,8 @@ __global__ __launch_bounds__(256) void k_render_walk(RenderGeom g)
         const PixGrid P = pix_grid(g);
         const int ix = (int)(pix % g.npx), iy = (int)(pix / g.npx);
         const double uc = P.umin + (ix + 0.5) * P.du, vc = P.vmin + (iy + 0.5) * P.dv;
-        const int64_t base = FILL ? g.off[pix] : 0;
+        const int64_t base = MODE == 1 ? g.off[pix] : MODE == 2 ? pix * g.cap : 0;
+        const int64_t lim = MODE == 2 ? g.cap : INT64_MAX;
         if (FILL && l16 == 0) g.walk[base] = e;
         n = 1;
         int c = e;
@@ -509,23 +514,27 @@ __global__ __launch_bounds__(256) void k_render_walk(RenderGeom g)
                 }
             }
             if (bj < 0) break;
-            if (FILL && l16 == 0) g.walk[base + n] = bj;
+            if (FILL && l16 == 0 && n < lim) g.walk[base + n] = bj;
             n++;
             c = bj;
             Zc = bZ;
         }
     }
-    if (!FILL && l16 == 0) g.counts[pix] = n;
+    if (MODE != 1 && l16 == 0) g.counts[pix] = n;
+    if (MODE == 2 && l16 == 0) atomicMax(g.maxn, (unsigned long long)n);
 }
 
-hipError_t launch_render_walk(const RenderGeom &g, bool fill, hipStream_t s)
+hipError_t launch_render_walk(const RenderGeom &g, WalkMode mode, hipStream_t s)
 {
     const int64_t npix = (int64_t)g.npx * g.npy;
     const int64_t blocks = (npix * 16 + 255) / 256;
-    if (fill)
-        k_render_walk<true><<<blocks, 256, 0, s>>>(g);
+    if (mode == WalkMode::capped && g.cap < 1) return hipErrorInvalidValue;
+    if (mode == WalkMode::count)
+        k_render_walk<0><<<blocks, 256, 0, s>>>(g);
+    else if (mode == WalkMode::fill)
+        k_render_walk<1><<<blocks, 256, 0, s>>>(g);
     else
-        k_render_walk<false><<<blocks, 256, 0, s>>>(g);
+        k_render_walk<2><<<blocks, 256, 0, s>>>(g);
     return hipGetLastError();
 }
 

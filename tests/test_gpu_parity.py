@@ -555,6 +555,35 @@ def test_render_many_lines(mgx, prec, tol):
                    pix, tol)
 
 
+def _chain(n, seed=56):
+    """n points along x (a little jitter across), neighbours i-1 and i+1,
+    the two ends boundary points: viewed along x every pixel walk that enters
+    runs the whole chain, far longer than the one-pass walk slots."""
+    m = synth.tiny_cloud(npoints=n, seed=seed, k=2, nside=1, nlev=3, nbins=5, vmax=2e3,
+                         tau_scale=20.0)
+    rng = np.random.default_rng(seed)
+    m.pos = np.stack([np.arange(n) * 1e11, rng.normal(0, 2e10, n), rng.normal(0, 2e10, n)])
+    lists = [[j for j in (i - 1, i + 1) if 0 <= j < n] for i in range(n)]
+    m.nbs_off = np.concatenate([[0], np.cumsum([len(x) for x in lists])]).astype(np.int32)
+    m.nbs = np.array([j for x in lists for j in x], np.int32)
+    m.bdy = np.zeros(n, np.uint8)
+    m.bdy[[0, n - 1]] = 1
+    return m
+
+
+@pytest.mark.parametrize("prec,tol", [(0, 2e-7), (1, 2e-5)])
+def test_render_walks_longer_than_slots(mgx, prec, tol):
+    """Walks longer than the one-pass slots (4 N^(1/3) + 16 points) take the
+    exact two-pass route; the image still matches the oracle."""
+    n = 300
+    m = _chain(n)
+    nu0 = m.nu[0]
+    pix = [(ix, iy) for ix in range(3) for iy in range(3)]
+    img, walks = render_compare(mgx, m, prec, [-1.0, 0.0, 0.0], 3, 3, nu0 * (1 - 2e-5),
+                                nu0 * (1 + 2e-5), 9, pix, tol)
+    assert max(len(w) for w in walks) > 4 * n ** (1 / 3) + 16
+
+
 def test_render_steep_gradient_column(mgx):
     n = 9
     m = synth.cubic_lattice(n=n, nbins=5)
