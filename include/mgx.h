@@ -71,6 +71,12 @@ typedef struct {
     double tau_floor;     /* lower bound on a segment optical depth (1e-15)  */
     double chi_min;       /* masing clamp on chi^ij [m^-1 Hz] (1e-30)         */
     double pop_floor;     /* floor of the relative-change denominator (1e-12) */
+    /* 3D traces search each walk once and keep its points in a temporary of
+       4 N^(1/3) + 16 points per walk when that temporary is at least this
+       many bytes (and fits 16 GiB and a quarter of the free memory); smaller
+       models search twice (lengths, then records).  Results are identical
+       either way.  Default 4 GiB; 0: whenever it fits; < 0: never. */
+    int64_t trace_slot_min_bytes;
 } mgx_options;
 
 /* Fills the defaults listed above (precision MGX_FP32). */

@@ -22,6 +22,7 @@ extern "C" void mgx_default_options(mgx_options *opt)
     opt->tau_floor = 1e-15;
     opt->chi_min = 1e-30;
     opt->pop_floor = 1e-12;
+    opt->trace_slot_min_bytes = int64_t(4) << 30;
 }
 
 extern "C" mgx_status mgx_create(mgx_ctx **out, int device, void *stream,
@@ -380,12 +381,51 @@ extern "C" mgx_status mgx_trace_rays(mgx_ctx *ctx, int64_t *total_records_out)
     a.thr = ctx->opt.branch_threshold;
     a.counts = ctx->counts.as<int64_t>();
     a.cnt = ctx->counters.as<Counters>();
-    HIPCHK(launch_trace(a, false, ctx->stream));
+    // Large 3D models: the searching pass also keeps each walk's points in a
+    // slot of the expected walk length (a temporary of at least
+    // trace_slot_min_bytes, at most 16 GiB and a quarter of the free memory);
+    // if no walk outgrew its slot, the records are then written from the
+    // slots without a second search.  Otherwise (small models, whose second
+    // search costs less than the temporary's allocation; 1D; no room) the
+    // search runs again to write them.
+    DMem slots, longest_d;
+    const int64_t cap = (int64_t)(4.0 * cbrt((double)ctx->N) + 16.0);
+    const size_t slot_bytes = sizeof(int32_t) * (size_t)NW * (size_t)cap;
+    bool use_slots = false;
+    if (ctx->dim == 3) {
+        size_t free_b = 0, total_b = 0;
+        const int64_t min_b = ctx->opt.trace_slot_min_bytes;
+        if (min_b >= 0 && slot_bytes >= (size_t)min_b &&
+            hipMemGetInfo(&free_b, &total_b) == hipSuccess &&
+            slot_bytes <= std::min(size_t(16) << 30, free_b / 4)) {
+            if (hipMalloc(&slots.p, slot_bytes) == hipSuccess) {
+                slots.bytes = slot_bytes;
+                use_slots = true;
+            } else {
+                slots.p = nullptr;
+                (void)hipGetLastError();  // no room after all: two passes
+            }
+        }
+    }
+    if (use_slots) {
+        longest_d.ensure(sizeof(unsigned long long));
+        HIPCHK(hipMemsetAsync(longest_d.p, 0, sizeof(unsigned long long), ctx->stream));
+        a.slot = slots.as<int32_t>();
+        a.cap = cap;
+        a.maxn = longest_d.as<unsigned long long>();
+        HIPCHK(launch_trace(a, TraceMode::slots, ctx->stream));
+    } else {
+        HIPCHK(launch_trace(a, TraceMode::count, ctx->stream));
+    }
     HIPCHK(mgx_internal_scan(ctx->counts.as<int64_t>(), ctx->offsets.as<int64_t>(), NW + 1,
                              &ctx->scan_tmp, &ctx->scan_tmp_bytes, ctx->stream));
     int64_t total = 0;
+    unsigned long long longest = 0;
     HIPCHK(hipMemcpyAsync(&total, ctx->offsets.as<int64_t>() + NW, sizeof(int64_t),
                           hipMemcpyDeviceToHost, ctx->stream));
+    if (use_slots)
+        HIPCHK(hipMemcpyAsync(&longest, longest_d.p, sizeof(longest), hipMemcpyDeviceToHost,
+                              ctx->stream));
     ctx->sync();
     ctx->n_records = total;
     const size_t n = (size_t)(total > 0 ? total : 1);
@@ -402,7 +442,10 @@ extern "C" mgx_status mgx_trace_rays(mgx_ctx *ctx, int64_t *total_records_out)
     a.r_dv = ctx->r_dv.as<double>();
     a.r_dx = ctx->r_dx.as<double>();
     a.r_ibb = ctx->r_ibb.as<double>();
-    HIPCHK(launch_trace(a, true, ctx->stream));
+    if (use_slots && (int64_t)longest <= cap)
+        HIPCHK(launch_trace_emit(a, ctx->stream));
+    else
+        HIPCHK(launch_trace(a, TraceMode::fill, ctx->stream));
     const bool f32 = ctx->fp32();
     ctx->rec.ensure((f32 ? sizeof(Rec<float>) : sizeof(Rec<double>)) * n);
     HIPCHK(launch_pack_trace(total, ctx->r_idx.as<int32_t>(), ctx->r_semi.as<uint8_t>(),

@@ -86,6 +86,9 @@ struct TraceArgs {
     uint8_t *r_semi;
     double *r_Z, *r_dv, *r_dx, *r_ibb;
     Counters *cnt;
+    int32_t *slot;             // slot pass: walk w's points at slot[w cap], at most cap
+    int64_t cap;
+    unsigned long long *maxn;  // slot pass: longest walk (atomic max)
 };
 
 template <typename T>
@@ -140,7 +143,13 @@ struct StateqArgs {
 hipError_t launch_point_widths(int N, const double *T, const double *vturb2, double mass,
                                double *b2, double *b, float *bf, float *ibf_scaled,
                                double *bd, double *ibd, hipStream_t s);
-hipError_t launch_trace(const TraceArgs &a, bool fill, hipStream_t s);
+// Walk lengths (counts) and hole count; records at CSR offsets (off); or, in
+// 3D, lengths, holes and the walks' point indices in slots of a.cap, with the
+// longest length in *a.maxn.  launch_trace_emit then writes the records of
+// walks that fit their slots without searching again.
+enum class TraceMode { count, fill, slots };
+hipError_t launch_trace(const TraceArgs &a, TraceMode mode, hipStream_t s);
+hipError_t launch_trace_emit(const TraceArgs &a, hipStream_t s);
 hipError_t launch_pack_vel4(int N, const double *vel, const double *b2, double4 *out,
                             hipStream_t s);
 hipError_t launch_pack_trace(int64_t n, const int32_t *idx, const uint8_t *semi,

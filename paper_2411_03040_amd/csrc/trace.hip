@@ -80,9 +80,12 @@ __device__ __forceinline__ void emit(const TraceArgs &a, int64_t pos, int j, dou
     nsemi += semi ? 1 : 0;
 }
 
-template <bool FILL>
+// MODE 0: lengths and holes; 1: records at CSR offsets; 2: lengths, holes and
+// the chosen points in fixed slots (see launch_trace).
+template <int MODE>
 __global__ __launch_bounds__(256) void k_trace3d(TraceArgs a)
 {
+    constexpr bool FILL = MODE == 1;
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t w = gid >> 4;
     const int l16 = threadIdx.x & 15;
@@ -141,12 +144,13 @@ __global__ __launch_bounds__(256) void k_trace3d(TraceArgs a)
             }
         }
         if (bj < 0) {
-            if (FILL && l16 == 0 && !a.bdy[c]) atomicAdd(&a.cnt->holes, 1ull);
+            if (!FILL && l16 == 0 && !a.bdy[c]) atomicAdd(&a.cnt->holes, 1ull);
             break;
         }
         const double4 vj = a.v4[bj];
         const double dv = ((vj.x - vxo) * nx + (vj.y - vyo) * ny) + (vj.z - vzo) * nz;
         if (l16 == 0) emit<FILL>(a, base + n, bj, bZ, dv, Zc, dvc, b2c, nsemi, vj.w);
+        if (MODE == 2 && l16 == 0 && n < a.cap) a.slot[w * a.cap + n] = bj;
         n++;
         c = bj;
         Zc = bZ;
@@ -156,8 +160,62 @@ __global__ __launch_bounds__(256) void k_trace3d(TraceArgs a)
     }
     if (l16 == 0) {
         if (!FILL) a.counts[w] = n;
+        if (MODE == 2) atomicMax(a.maxn, (unsigned long long)n);
         if (FILL && nsemi) atomicAdd(&a.cnt->semi, nsemi);
     }
+}
+
+// Records of walks kept in slots: 16 lanes per walk, lane l writes records
+// l, l + 16, ...; each record needs only its point and the one before it
+// (the origin for the first), whose projections are recomputed with the
+// walk's own expressions, so the records equal the searching pass's bit for
+// bit.
+__global__ __launch_bounds__(256) void k_trace_emit(TraceArgs a)
+{
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t w = gid >> 4;
+    const int l16 = threadIdx.x & 15;
+    const int64_t nwalk = (int64_t)a.N * a.R;
+    if (w >= nwalk) return;
+    const int o = (int)(w / a.R);
+    const int r = (int)(w - (int64_t)o * a.R);
+    const double nx = a.ray_dir[3 * r + 0];
+    const double ny = a.ray_dir[3 * r + 1];
+    const double nz = a.ray_dir[3 * r + 2];
+    const double xo = a.x[o], yo = a.y[o], zo = a.z[o];
+    const double vxo = a.vx[o], vyo = a.vy[o], vzo = a.vz[o];
+    const int64_t n = a.counts[w], base = a.off[w];
+    const int32_t *sl = a.slot + w * a.cap;
+    auto point = [&](int j, double &Z, double &dv, double &b2) {
+        const double4 pj = a.p4[j];
+        const double ddx = pj.x - xo;
+        const double ddy = pj.y - yo;
+        const double ddz = pj.z - zo;
+        Z = (ddx * nx + ddy * ny) + ddz * nz;
+        const double4 vj = a.v4[j];
+        dv = ((vj.x - vxo) * nx + (vj.y - vyo) * ny) + (vj.z - vzo) * nz;
+        b2 = vj.w;
+    };
+    unsigned long long nsemi = 0;
+    for (int64_t k = l16; k < n; k += 16) {
+        double Zp = 0.0, dvp = 0.0, b2p = a.b2[o];
+        if (k > 0) point(sl[k - 1], Zp, dvp, b2p);
+        const int j = sl[k];
+        double Z, dv, b2;
+        point(j, Z, dv, b2);
+        emit<true>(a, base + k, j, Z, dv, Zp, dvp, b2p, nsemi, b2);
+    }
+    for (int m = 8; m >= 1; m >>= 1) nsemi += __shfl_xor(nsemi, m, 16);
+    if (l16 == 0 && nsemi) atomicAdd(&a.cnt->semi, nsemi);
+}
+
+hipError_t launch_trace_emit(const TraceArgs &a, hipStream_t s)
+{
+    const int64_t nwalk = (int64_t)a.N * a.R;
+    if (a.dim != 3 || a.cap < 1) return hipErrorInvalidValue;
+    const int64_t blocks = (nwalk * 16 + 255) / 256;
+    k_trace_emit<<<blocks, 256, 0, s>>>(a);
+    return hipGetLastError();
 }
 
 // Spherical shells: one thread per (origin, mu).
@@ -211,21 +269,25 @@ __global__ __launch_bounds__(256) void k_trace1d(TraceArgs a)
     if (FILL && nsemi) atomicAdd(&a.cnt->semi, nsemi);
 }
 
-hipError_t launch_trace(const TraceArgs &a, bool fill, hipStream_t s)
+hipError_t launch_trace(const TraceArgs &a, TraceMode mode, hipStream_t s)
 {
     const int64_t nwalk = (int64_t)a.N * a.R;
     if (a.dim == 1) {
+        if (mode == TraceMode::slots) return hipErrorInvalidValue;
         const int64_t blocks = (nwalk + 255) / 256;
-        if (fill)
+        if (mode == TraceMode::fill)
             k_trace1d<true><<<blocks, 256, 0, s>>>(a);
         else
             k_trace1d<false><<<blocks, 256, 0, s>>>(a);
     } else {
         const int64_t blocks = (nwalk * 16 + 255) / 256;
-        if (fill)
-            k_trace3d<true><<<blocks, 256, 0, s>>>(a);
+        if (mode == TraceMode::slots && a.cap < 1) return hipErrorInvalidValue;
+        if (mode == TraceMode::fill)
+            k_trace3d<1><<<blocks, 256, 0, s>>>(a);
+        else if (mode == TraceMode::slots)
+            k_trace3d<2><<<blocks, 256, 0, s>>>(a);
         else
-            k_trace3d<false><<<blocks, 256, 0, s>>>(a);
+            k_trace3d<0><<<blocks, 256, 0, s>>>(a);
     }
     return hipGetLastError();
 }

@@ -36,7 +36,8 @@ class MgxError(RuntimeError):
 
 class Options(C.Structure):
     _fields_ = [("precision", C.c_int), ("branch_threshold", C.c_double),
-                ("tau_floor", C.c_double), ("chi_min", C.c_double), ("pop_floor", C.c_double)]
+                ("tau_floor", C.c_double), ("chi_min", C.c_double), ("pop_floor", C.c_double),
+                ("trace_slot_min_bytes", C.c_int64)]
 
 
 class ModelStruct(C.Structure):
@@ -195,7 +196,8 @@ def _torch_stream(device: int):
     return torch.cuda.current_stream(device).cuda_stream
 
 
-def _options(precision, branch_threshold, tau_floor, chi_min, pop_floor) -> Options:
+def _options(precision, branch_threshold, tau_floor, chi_min, pop_floor,
+             trace_slot_min_bytes=None) -> Options:
     opt = Options()
     lib().mgx_default_options(C.byref(opt))
     opt.precision = precision
@@ -203,6 +205,8 @@ def _options(precision, branch_threshold, tau_floor, chi_min, pop_floor) -> Opti
     opt.tau_floor = tau_floor
     opt.chi_min = chi_min
     opt.pop_floor = pop_floor
+    if trace_slot_min_bytes is not None:
+        opt.trace_slot_min_bytes = int(trace_slot_min_bytes)
     return opt
 
 
@@ -226,9 +230,11 @@ class Context:
 
     def __init__(self, device: int = 0, precision: int = FP32, stream: Optional[int] = None,
                  use_torch_stream: bool = True, branch_threshold: float = 0.35,
-                 tau_floor: float = 1e-15, chi_min: float = 1e-30, pop_floor: float = 1e-12):
+                 tau_floor: float = 1e-15, chi_min: float = 1e-30, pop_floor: float = 1e-12,
+                 trace_slot_min_bytes: Optional[int] = None):
         L = lib()
-        opt = _options(precision, branch_threshold, tau_floor, chi_min, pop_floor)
+        opt = _options(precision, branch_threshold, tau_floor, chi_min, pop_floor,
+                       trace_slot_min_bytes)
         if stream is None and use_torch_stream:
             stream = _torch_stream(device)
         h = C.c_void_p()

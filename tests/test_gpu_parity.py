@@ -105,6 +105,40 @@ def test_trace_lattice_ties(mgx):
     check_traces(ctx, m, all_pairs(m))
 
 
+def slot_ctx(mgx, model, precision, min_bytes):
+    c = mgx.Context(precision=precision, trace_slot_min_bytes=min_bytes)
+    c.load_model(model)
+    c.trace_rays()
+    return c
+
+
+def test_trace_walks_longer_than_slots(mgx):
+    """Walks longer than the searching pass's slots (4 N^(1/3) + 16 points)
+    send the trace through the second search; records still bit-exact, and
+    the semi-analytic count matches the oracle's."""
+    m = _chain(300)
+    ctx = slot_ctx(mgx, m, mgx.FP64, 0)
+    off = ctx.get_trace_offsets()
+    assert int(np.max(np.diff(off))) > 4 * m.npoints ** (1 / 3) + 16
+    n = check_traces(ctx, m, all_pairs(m))
+    assert ctx.counters()["semi_segments"] == n
+
+
+@pytest.mark.parametrize("min_bytes", [0, -1])
+def test_trace_slot_and_two_pass_records(mgx, min_bytes):
+    """The same small cloud traced from slots (one search) and with two
+    searches: records equal the oracle's bit for bit either way, with the
+    same semi-analytic and hole counts."""
+    m = synth.tiny_cloud(npoints=300, seed=57, k=6, nside=2, vmax=5e3)
+    ctx = slot_ctx(mgx, m, mgx.FP32, min_bytes)
+    n = check_traces(ctx, m, all_pairs(m))
+    c = ctx.counters()
+    assert c["semi_segments"] == n > 0
+    orc = oracle.Oracle(m)
+    holes = sum(orc.trace(o, r)[3] for o, r in all_pairs(m))
+    assert c["holes"] == holes > 0
+
+
 @pytest.mark.parametrize("variant", ["a", "b"])
 def test_trace_spherical_shells(mgx, variant):
     m = synth.spherical_shells(variant)
