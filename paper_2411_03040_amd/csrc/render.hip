@@ -75,6 +75,10 @@ struct RM<float> {
     // erfc_ returns exactly 0 beyond this (its exponential is below the
     // smallest denormal)
     static constexpr float erfc_zero = 10.5f;
+    // exp2(-y) is exactly zero (below the smallest denormal) for y > 150;
+    // squares of offsets carry a relative rounding of at most 6e-8
+    static constexpr float weight_zero = 151.0f;
+    static constexpr float sq_rel = 2e-7f;
 };
 template <>
 struct RM<double> {
@@ -90,6 +94,9 @@ struct RM<double> {
     static constexpr double tiny = 1e-290;
     // the library erfc is exactly 0 beyond this (erfc(27.3) < 5e-324)
     static constexpr double erfc_zero = 27.5;
+    // exp(-y) is exactly zero for y > 745.2
+    static constexpr double weight_zero = 746.0;
+    static constexpr double sq_rel = 1e-15;
 };
 
 template <typename T>
@@ -221,27 +228,45 @@ __global__ __launch_bounds__(256) void k_render_integrate(RenderArgs<T> a, int n
         if (chi1 > RM<T>::tiny) {
             S1 = RM<T>::div(sws, chi1);
         } else {
-            T x2min = (T)INFINITY;
+            // nearest line (smallest squared offset) and the next nearest
+            T x2min = (T)INFINITY, x2sec = (T)INFINITY;
+            int lmin = 0;
             for (int l = 0; l < nl; l++) {
                 const LineLane<T> e = line_lane(l);
                 const T x = (e.cd - e.rr * w) * ibg;
-                x2min = fmin(x2min, x * x);
+                const T y = x * x;
+                if (y < x2min) {
+                    x2sec = x2min;
+                    x2min = y;
+                    lmin = l;
+                } else {
+                    x2sec = fmin(x2sec, y);
+                }
             }
-            T sw = (T)0;
-            sws = (T)0;
-            for (int l = 0; l < nl; l++) {
-                const LineLane<T> e = line_lane(l);
-                const T x = (e.cd - e.rr * w) * ibg;
-                // (clamped: the square of the nearest line's offset may be
-                // fused into this subtraction unrounded, leaving a residue of
-                // either sign, large where the offsets are)
-                const T wt = chi_p[l] * RM<T>::gauss(fmax(x * x - x2min, (T)0));
-                sw += wt;
-                sws += wt * S_p[l];
+            // Where every other line's relative weight exp(-(y - y_min))
+            // underflows to zero, the mean is the nearest line's own,
+            // (c S) / c, as the full sum gives it (with a margin for the
+            // rounding of the squares); otherwise the full sum.
+            if (x2sec - x2min > RM<T>::weight_zero + RM<T>::sq_rel * x2sec) {
+                const T c = chi_p[lmin];
+                S1 = c > (T)0 ? (c * S_p[lmin]) / c : (T)0;
+            } else {
+                T sw = (T)0;
+                sws = (T)0;
+                for (int l = 0; l < nl; l++) {
+                    const LineLane<T> e = line_lane(l);
+                    const T x = (e.cd - e.rr * w) * ibg;
+                    // (clamped: the square of the nearest line's offset may
+                    // be fused into this subtraction unrounded, leaving a
+                    // residue of either sign, large where the offsets are)
+                    const T wt = chi_p[l] * RM<T>::gauss(fmax(x * x - x2min, (T)0));
+                    sw += wt;
+                    sws += wt * S_p[l];
+                }
+                // (IEEE division: the weights may be denormal, where the
+                // hardware reciprocal flushes to infinity)
+                S1 = sw > (T)0 ? sws / sw : (T)0;
             }
-            // (IEEE division: the weights may be denormal, where the
-            // hardware reciprocal flushes to infinity)
-            S1 = sw > (T)0 ? sws / sw : (T)0;
         }
         const double Zd = Zv[p], b2d = b2v[p];
         if (k == 0) {
