@@ -220,8 +220,12 @@ struct HalfState {
     bool ec_ok;
 };
 
-template <typename T>
-constexpr int kUnrollBoth = sizeof(T) == 8 ? 2 : 1;
+// Unrolling of the sweep loops, as measured: the both-halves loop twice in
+// FP64 and in one-width models (whose lighter semi-analytic segments leave
+// room for the extra registers), once otherwise; the longer half alone four
+// times.
+template <typename T, bool ONE_WIDTH>
+constexpr int kUnrollBoth = (sizeof(T) == 8 || ONE_WIDTH) ? 2 : 1;
 
 // One origin x line chunk, executed by the whole workgroup (blockDim.x
 // threads, at least nlc * nbins).  Shared by the single-model launch and the
@@ -419,7 +423,7 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
                 k--;
             }
             const int kAB = max(lo, nB);
-#pragma unroll 2
+#pragma unroll 4
             for (; k >= kAB; k--) visit(A, eA + k, false);
             // B's far end (A's too when the halves are equally long)
             if (k >= lo && k == nB - 1) {
@@ -427,9 +431,7 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
                 visit(B, eB + k, true);
                 k--;
             }
-            // (unrolled twice in FP64 only: measured faster there, slower in
-            // FP32 where the extra registers cost occupancy)
-#pragma unroll kUnrollBoth<T>
+#pragma unroll kUnrollBoth<T, ONE_WIDTH>
             for (; k >= lo; k--) {
                 visit(A, eA + k, false);
                 visit(B, eB + k, false);
