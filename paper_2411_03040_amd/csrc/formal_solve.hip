@@ -220,12 +220,14 @@ struct HalfState {
     bool ec_ok;
 };
 
-// Unrolling of the sweep loops, as measured: the both-halves loop twice in
-// FP64 and in one-width models (whose lighter semi-analytic segments leave
-// room for the extra registers), once otherwise; the longer half alone four
-// times.
+// Unrolling and occupancy, as measured: both sweep loops are unrolled twice
+// (no register copies between iterations).  FP32 launches other than
+// one-width models are held to 64 VGPRs, i.e. eight waves per SIMD: a few
+// bytes spill outside the sweeps, and the extra wave hides more of the
+// transcendental and LDS latency than the spills cost.  One-width models keep
+// their 72 registers (seven waves), which measured faster there than a cap.
 template <typename T, bool ONE_WIDTH>
-constexpr int kUnrollBoth = (sizeof(T) == 8 || ONE_WIDTH) ? 2 : 1;
+constexpr int kWavesPerEu = (sizeof(T) == 4 && !ONE_WIDTH) ? 8 : 1;
 
 // One origin x line chunk, executed by the whole workgroup (blockDim.x
 // threads, at least nlc * nbins).  Shared by the single-model launch and the
@@ -423,7 +425,7 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
                 k--;
             }
             const int kAB = max(lo, nB);
-#pragma unroll 4
+#pragma unroll 2
             for (; k >= kAB; k--) visit(A, eA + k, false);
             // B's far end (A's too when the halves are equally long)
             if (k >= lo && k == nB - 1) {
@@ -431,7 +433,7 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
                 visit(B, eB + k, true);
                 k--;
             }
-#pragma unroll kUnrollBoth<T, ONE_WIDTH>
+#pragma unroll 2
             for (; k >= lo; k--) {
                 visit(A, eA + k, false);
                 visit(B, eB + k, false);
@@ -478,7 +480,8 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
 constexpr int kXcds = 8;
 
 template <typename T, int MAXT, bool ORDERED, bool ONE_WIDTH>
-__global__ __launch_bounds__(MAXT) void k_formal_solve(FSArgs<T> a, int ch)
+__global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(kWavesPerEu<T, ONE_WIDTH>)))
+void k_formal_solve(FSArgs<T> a, int ch)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     if (ORDERED) {
@@ -501,11 +504,9 @@ __global__ __launch_bounds__(MAXT) void k_formal_solve(FSArgs<T> a, int ch)
 // classes mix models, so the one-width reuse is not used here; it changes
 // no result.)
 template <typename T, int MAXT>
-__global__ __launch_bounds__(MAXT) void k_formal_solve_batch(const FSArgs<T> *__restrict__ descs,
-                                                             const int4 *__restrict__ items,
-                                                             const int *__restrict__ count,
-                                                             const int *__restrict__ active,
-                                                             int ch)
+__global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(kWavesPerEu<T, false>)))
+void k_formal_solve_batch(const FSArgs<T> *__restrict__ descs, const int4 *__restrict__ items,
+                          const int *__restrict__ count, const int *__restrict__ active, int ch)
 {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const int it = blockIdx.x;
