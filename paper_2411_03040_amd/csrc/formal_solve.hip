@@ -349,9 +349,10 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
 
         // point Q (staged record e) of a half: its profile, then either the
         // far-end boundary intensity or one elimination row
-        auto visit = [&](HalfState<T> &s, int e, bool far_end) {
-            const MetaA<T> ma = s_a[e];
-            const LineRec<T> lr = s_line[e * nlc + ll];
+        auto visit = [&](HalfState<T> &s, const MetaA<T> *pa, const LineRec<T> *pl,
+                         bool far_end) {
+            const MetaA<T> ma = *pa;
+            const LineRec<T> lr = *pl;
             const T dvQ = ma.dv;
             const T uQ = xb + dvQ * k1;
             // (the profile is evaluated even where both segments at Q are
@@ -419,24 +420,33 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
             // record k of half A is staged at eA + k, of half B at eB + k
             const int eA = (a_minus ? 0 : cm) - lo, eB = (a_minus ? cm : 0) - lo;
             int k = hi - 1;
+            // the sweeps step pointers to the staged records down, so each
+            // LDS read takes its address as it is
+            const MetaA<T> *pa = s_a + (eA + k);
+            const LineRec<T> *la = s_line + (eA + k) * nlc + ll;
             // records beyond the end of B: A alone (its far end first)
             if (k >= nB && k == nA - 1) {
-                visit(A, eA + k, true);
+                visit(A, pa--, la, true);
+                la -= nlc;
                 k--;
             }
             const int kAB = max(lo, nB);
 #pragma unroll 2
-            for (; k >= kAB; k--) visit(A, eA + k, false);
+            for (; k >= kAB; k--, la -= nlc) visit(A, pa--, la, false);
+            const MetaA<T> *pb = s_a + (eB + k);
+            const LineRec<T> *lb = s_line + (eB + k) * nlc + ll;
             // B's far end (A's too when the halves are equally long)
             if (k >= lo && k == nB - 1) {
-                visit(A, eA + k, k == nA - 1);
-                visit(B, eB + k, true);
+                visit(A, pa--, la, k == nA - 1);
+                visit(B, pb--, lb, true);
+                la -= nlc;
+                lb -= nlc;
                 k--;
             }
 #pragma unroll 2
-            for (; k >= lo; k--) {
-                visit(A, eA + k, false);
-                visit(B, eB + k, false);
+            for (; k >= lo; k--, la -= nlc, lb -= nlc) {
+                visit(A, pa--, la, false);
+                visit(B, pb--, lb, false);
             }
         }
         // last segment of each non-empty half ends at the origin
