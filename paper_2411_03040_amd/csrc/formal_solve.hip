@@ -221,13 +221,14 @@ struct HalfState {
 };
 
 // Unrolling and occupancy, as measured: both sweep loops are unrolled twice
-// (no register copies between iterations).  FP32 launches other than
-// one-width models are held to 64 VGPRs, i.e. eight waves per SIMD: a few
-// bytes spill outside the sweeps, and the extra wave hides more of the
-// transcendental and LDS latency than the spills cost.  One-width models keep
-// their 72 registers (seven waves), which measured faster there than a cap.
+// (no register copies between iterations), the longer half alone four times
+// in FP64.  Launches other than one-width models are held to 64 VGPRs in FP32
+// (eight waves per SIMD) and 128 in FP64 (four waves): a few bytes spill
+// outside the sweeps, and the extra waves hide more of the transcendental
+// and LDS latency than the spills cost.  One-width models keep their
+// registers (seven waves in FP32), which measured faster there than a cap.
 template <typename T, bool ONE_WIDTH>
-constexpr int kWavesPerEu = (sizeof(T) == 4 && !ONE_WIDTH) ? 8 : 1;
+constexpr int kWavesPerEu = ONE_WIDTH ? 1 : (sizeof(T) == 4 ? 8 : 4);
 
 // One origin x line chunk, executed by the whole workgroup (blockDim.x
 // threads, at least nlc * nbins).  Shared by the single-model launch and the
@@ -431,7 +432,7 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
                 k--;
             }
             const int kAB = max(lo, nB);
-#pragma unroll 2
+#pragma unroll (sizeof(T) == 8 ? 4 : 2)
             for (; k >= kAB; k--, la -= nlc) visit(A, pa--, la, false);
             const MetaA<T> *pb = s_a + (eB + k);
             const LineRec<T> *lb = s_line + (eB + k) * nlc + ll;
