@@ -66,28 +66,29 @@ struct FM<float> {
     // erfc for x >= 0, branch-free, in the product form of Numerical Recipes
     // (Press et al., 2nd ed., Sec. 6.2),
     //   erfc(x) = t exp(-x^2 + P(t)),  t = 1 / (1 + p x),
-    // with our own fit (fit_erfc.py in the package reproduces it): p = 0.475
-    // and a degree-7 P, fitted for least maximum relative error of erfc on x
-    // in [0, 9.6] (2.8e-7 in exact arithmetic; in FP32 the rounding of the
+    // with our own fit (fit_erfc.py in the package reproduces it): p = 0.62
+    // and a degree-6 P, fitted for least maximum relative error of erfc on x
+    // in [0, 9.6] (2.0e-6 in exact arithmetic; in FP32 the rounding of the
     // exponent argument dominates at large x, as for the published degree-9
-    // form).  One reciprocal, one exp2 and seven
-    // multiply-adds, the same for every lane (the library erfcf branches by
-    // argument range, which diverges across the bins of a wave).  Evaluated
+    // form; degree 7 reaches 2.8e-7 for one more multiply-add per erfc, which
+    // measured 1.5-2.4 % slower for a J-bar error of 2e-7 instead of 8e-7).
+    // One reciprocal, one exp2 and six multiply-adds, the same for every
+    // lane (the library erfcf branches by argument range, which diverges
+    // across the bins of a wave).  Evaluated
     // in base 2: the argument comes scaled by sqrt(log2 e) (xs = x sqrt(log2 e),
     // see erf_scale), P is fitted to log2(erfc(x) / t) + xs^2 directly and
     // p is divided by sqrt(log2 e).
     static constexpr float erf_scale = 1.2011224f;  // sqrt(log2 e)
     static __device__ __forceinline__ float erfc_scaled(float xs)
     {
-        const float t = __builtin_amdgcn_rcpf(fmaf(xs, 0.39546344f, 1.0f));
-        float p = -0.28171604f;
-        p = fmaf(p, t, 1.22523776f);
-        p = fmaf(p, t, -1.86701982f);
-        p = fmaf(p, t, 0.97788950f);
-        p = fmaf(p, t, -0.22770730f);
-        p = fmaf(p, t, 0.63901249f);
-        p = fmaf(p, t, 1.43362935f);
-        p = fmaf(p, t, -1.89932635f);
+        const float t = __builtin_amdgcn_rcpf(fmaf(xs, 0.51618386f, 1.0f));
+        float p = -0.29999480f;
+        p = fmaf(p, t, 1.21250997f);
+        p = fmaf(p, t, -1.66093528f);
+        p = fmaf(p, t, 0.49260237f);
+        p = fmaf(p, t, 0.31400948f);
+        p = fmaf(p, t, 1.45791962f);
+        p = fmaf(p, t, -1.51611420f);
         return t * __builtin_amdgcn_exp2f(fmaf(-xs, xs, p));
     }
     // e^x - 1 for the CMB boundary intensity: exp2 away from zero, a

@@ -11,7 +11,7 @@ The fit minimises the maximum error of P on a dense grid of x in [0, xmax]
 minimax solution of a linear fit); an error dP in P is a relative error of
 dP ln 2 in erfc.  Reference values come from mpmath at 30 digits.
 
-Run:  python -m paper_2411_03040_amd.fit_erfc [--degree 7] [--p 0.475]
+Run:  python -m paper_2411_03040_amd.fit_erfc [--degree 6] [--p 0.62]
 prints the coefficients (highest degree first, the kernel's Horner order),
 p / sqrt(log2 e) (the kernel takes x already scaled by sqrt(log2 e)) and the
 maximum relative error of erfc in exact arithmetic.
@@ -56,8 +56,8 @@ def max_rel_error(c, p: float, xmax: float = 9.6, n: int = 20001) -> float:
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--degree", type=int, default=7)
-    ap.add_argument("--p", type=float, default=0.475)
+    ap.add_argument("--degree", type=int, default=6)
+    ap.add_argument("--p", type=float, default=0.62)
     args = ap.parse_args()
     c, err = fit(args.degree, args.p)
     print("coefficients, highest degree first:", ", ".join(f"{v:.8f}" for v in c[::-1]))
