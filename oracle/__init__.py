@@ -43,6 +43,14 @@ class _Model(C.Structure):
     ]
 
 
+# Ng schedule flag: after a used prediction only later regular iterates are
+# stored (the footnote of the paper's adaptive-Ng paragraph)
+NG_FRESH = 0x10
+# per-iteration Ng decisions logged by the schedule
+EV_NONE, EV_FORMED, EV_USED, EV_INVALID = 0, 1, 2, 3
+
+MAP_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double))
+
 _lib = None
 
 
@@ -75,6 +83,9 @@ def lib():
         L.orc_rel_change.restype = C.c_double
         L.orc_ng.argtypes = [C.c_int, C.c_int64, P, P, P]
         L.orc_iterate.argtypes = [P, P, C.c_double, C.c_int, C.c_int, C.c_int, P, P, P]
+        L.orc_iterate_ev.argtypes = [P, P, C.c_double, C.c_int, C.c_int, C.c_int, P, P, P, P]
+        L.orc_iterate_map.argtypes = [MAP_FN, P, C.c_int64, C.c_double, P, C.c_double, C.c_int,
+                                      C.c_int, C.c_int, P, P, P, P]
         L.orc_num_threads.restype = C.c_int
         L.orc_set_num_threads.argtypes = [C.c_int]
         L.orc_render_pixel.argtypes = [P, P, P, P, C.c_int, C.c_int, C.c_double, C.c_double,
@@ -113,6 +124,32 @@ def dtau_semi_analytic(dx, chi_ij0, chi_ij1, d0, d1, dnu_bar):
 
 def erf_difference(a, b):
     return lib().orc_erf_difference(a, b)
+
+
+def iterate_map(step, x0, tol, max_iter, ng_mode=0, ng_param=4, pop_floor=1e-12):
+    """Run the oracle's Ng schedule on an arbitrary fixed-point map.
+
+    step(x) -> next iterate (numpy in, numpy out, same length).  Returns
+    dict(status, x, iters, change, history, events) with events[i] the Ng
+    decision of iteration i + 1 (EV_*)."""
+    x = np.ascontiguousarray(x0, np.float64).copy()
+    n = x.size
+
+    def cb(_ud, pin, pout):
+        a = np.ctypeslib.as_array(pin, shape=(n,)).copy()
+        y = np.asarray(step(a), np.float64)
+        np.ctypeslib.as_array(pout, shape=(n,))[:] = y
+        return 0
+
+    fn = MAP_FN(cb)
+    iters, ch = C.c_int(), C.c_double()
+    hist = np.zeros(max_iter)
+    ev = np.zeros(max_iter, np.int8)
+    st = lib().orc_iterate_map(fn, None, n, pop_floor, _p(x), tol, max_iter, ng_mode, ng_param,
+                               C.byref(iters), C.byref(ch), _p(hist), _p(ev))
+    k = iters.value
+    return dict(status=st, x=x, iters=k, change=ch.value, history=hist[:k].copy(),
+                events=ev[:k].copy())
 
 
 def num_threads():
@@ -234,10 +271,11 @@ class Oracle:
         pops = np.ascontiguousarray(pops, np.float64).copy()
         iters, ch = C.c_int(), C.c_double()
         hist = np.zeros(max_iter)
-        st = lib().orc_iterate(self.ptr, _p(pops), tol, max_iter, ng_mode, ng_param,
-                               C.byref(iters), C.byref(ch), _p(hist))
+        ev = np.zeros(max_iter, np.int8)
+        st = lib().orc_iterate_ev(self.ptr, _p(pops), tol, max_iter, ng_mode, ng_param,
+                                  C.byref(iters), C.byref(ch), _p(hist), _p(ev))
         return dict(status=st, pops=pops, iters=iters.value, change=ch.value,
-                    history=hist[: iters.value].copy())
+                    history=hist[: iters.value].copy(), events=ev[: iters.value].copy())
 
     def render_pixels(self, pops, direction, npx, npy, f_min, f_max, nfreq, pixels):
         """Intensities [len(pixels)][nfreq] and walks of the given (ix, iy) pixels."""

@@ -30,7 +30,10 @@
  *                        Lambda-iteration rates (Rybicki & Hummer 1991)
  *   orc_ng               Ng prediction c = (R R^T)^-1 1 / 1^T (R R^T)^-1 1
  *                        (Section "Adaptive Ng-acceleration" and Appendix A)
- *   orc_iterate          Lambda-iteration with classical or adaptive Ng
+ *   orc_iterate_map      the classical and adaptive Ng schedules around any
+ *                        fixed-point map (Section "Adaptive Ng-acceleration",
+ *                        including its footnote's reading as an option)
+ *   orc_iterate          Lambda-iteration of a model on that schedule
  */
 #include "oracle.h"
 
@@ -688,97 +691,154 @@ int orc_ng(int nhist, int64_t n, const double *hist, double *out, double *coeffs
 }
 
 /* ------------------------------------------------------------------------
- * Lambda-iteration from the given populations.  Each iteration: line
- * coefficients -> formal solution at every origin -> statistical
- * equilibrium -> relative change against the previous iterate.  Stops when
- * the change is <= tol.
- *   ng_mode 1 (classical): after every ng_param plain iterates following the
- *     last restart, replace the iterate by the Ng prediction from the
- *     ng_param + 1 stored iterates; the history restarts from it.
+ * Fixed-point iteration x <- step(x) with Ng acceleration (Section
+ * "Adaptive Ng-acceleration").  The schedule is independent of what the map
+ * computes; orc_iterate drives it with one Lambda-iteration of the model.
+ * Stops when the relative change max |new - old| / max(new, floor) is <= tol.
+ *   ng_mode 1 (classical): once ng_param plain iterates have been stored
+ *     after the start of the history, replace the iterate by the Ng
+ *     prediction from the ng_param + 1 stored iterates.
  *   ng_mode 2 (adaptive): after each iterate with at least 3 stored, form the
  *     prediction P_N from all N stored iterates; use it if the relative
  *     change between the last two running predictions is below that between
  *     the last two iterates, or if N = N_max (= ng_param).
- * A rejected prediction (singular Gram matrix, negative component) keeps
- * the plain iterate; the history restarts from it.
+ *   A rejected prediction (singular Gram matrix, negative component) keeps
+ *   the plain iterate.  Whenever a prediction is used, or the store is full,
+ *   the history restarts:
+ *     default: from the current populations (the prediction, if one was
+ *       used, becomes y_1 of the new history);
+ *     ORC_NG_FRESH (or'ed into ng_mode): after a used prediction the history
+ *       is emptied and only the regular iterates computed after it are
+ *       stored (the footnote of the adaptive-Ng paragraph); a full store
+ *       without a used prediction restarts from the last regular iterate.
+ * events[it - 1] (may be NULL): 0 no prediction formed, 1 formed and not
+ * used, 2 used, 3 formed but invalid (singular or negative).
  * ---------------------------------------------------------------------- */
-int orc_iterate(const orc_model *m, double *pops, double tol, int max_iter, int ng_mode,
-                int ng_param, int *iters_out, double *change_out, double *change_hist)
+int orc_iterate_map(orc_map_fn step, void *ud, int64_t n, double pop_floor, double *x,
+                    double tol, int max_iter, int ng_mode, int ng_param, int *iters_out,
+                    double *change_out, double *change_hist, int8_t *events)
 {
-    const int N = m->npoints, nl = m->nlines, L = m->nlev;
-    const int64_t n = (int64_t)N * L;
-    double *chi = (double *)malloc(sizeof(double) * (size_t)N * nl);
-    double *S = (double *)malloc(sizeof(double) * (size_t)N * nl);
-    double *J = (double *)malloc(sizeof(double) * (size_t)N * nl);
-    double *Ls = (double *)malloc(sizeof(double) * (size_t)N * nl);
+    const int fresh = (ng_mode & ORC_NG_FRESH) != 0;
+    const int mode = ng_mode & 0xf;
     double *nw = (double *)malloc(sizeof(double) * (size_t)n);
-    const int hcap = (ng_mode == 0) ? 1 : (ng_mode == 1 ? ng_param + 1 : ng_param);
+    const int hcap = (mode == 0) ? 1 : (mode == 1 ? ng_param + 1 : ng_param);
     double *hist = (double *)malloc(sizeof(double) * (size_t)n * (hcap > 0 ? hcap : 1));
     double *pred = (double *)malloc(sizeof(double) * (size_t)n);
     double *prev_pred = (double *)malloc(sizeof(double) * (size_t)n);
+    orc_model fl;  /* only pop_floor is read by orc_rel_change */
+    memset(&fl, 0, sizeof(fl));
+    fl.pop_floor = pop_floor;
     int have_prev = 0;
     int nh = 1;
-    memcpy(hist, pops, sizeof(double) * n);
+    memcpy(hist, x, sizeof(double) * n);
     int status = -5, it = 0;
     double change = INFINITY;
     for (it = 1; it <= max_iter; it++) {
-        orc_line_coeffs(m, pops, chi, NULL, S);
-        orc_solve_origins(m, chi, S, N, NULL, J, Ls);
-        if (orc_stateq(m, J, Ls, S, nw) != 0) {
+        if (events) events[it - 1] = 0;
+        if (step(ud, x, nw) != 0) {
             status = -6;
             break;
         }
-        change = orc_rel_change(m, nw, pops, n);
+        change = orc_rel_change(&fl, nw, x, n);
         if (change_hist) change_hist[it - 1] = change;
-        memcpy(pops, nw, sizeof(double) * n);
+        memcpy(x, nw, sizeof(double) * n);
         if (change <= tol) {
             status = 0;
             break;
         }
-        if (ng_mode == 0) continue;
+        if (mode == 0) continue;
         memcpy(hist + (int64_t)nh * n, nw, sizeof(double) * n);
         nh++;
-        if (ng_mode == 1) {
+        int use = 0, full = 0;
+        if (mode == 1) {
             if (nh == ng_param + 1) {
-                if (orc_ng(nh, n, hist, pred, NULL) == 0) memcpy(pops, pred, sizeof(double) * n);
-                memcpy(hist, pops, sizeof(double) * n);
-                nh = 1;
+                full = 1;
+                if (orc_ng(nh, n, hist, pred, NULL) == 0) {
+                    use = 1;
+                    if (events) events[it - 1] = 2;
+                } else if (events) {
+                    events[it - 1] = 3;
+                }
             }
         } else {
-            int use = 0, ok = 0;
+            full = (nh >= ng_param);
             if (nh >= 3) {
-                ok = (orc_ng(nh, n, hist, pred, NULL) == 0);
+                const int ok = (orc_ng(nh, n, hist, pred, NULL) == 0);
                 if (ok) {
                     if (have_prev &&
-                        orc_rel_change(m, pred, prev_pred, n) <
-                            orc_rel_change(m, hist + (int64_t)(nh - 1) * n,
+                        orc_rel_change(&fl, pred, prev_pred, n) <
+                            orc_rel_change(&fl, hist + (int64_t)(nh - 1) * n,
                                            hist + (int64_t)(nh - 2) * n, n))
                         use = 1;
-                    if (nh >= ng_param) use = 1;
+                    if (full) use = 1;
                     memcpy(prev_pred, pred, sizeof(double) * n);
                     have_prev = 1;
                 }
+                if (events) events[it - 1] = ok ? (use ? 2 : 1) : 3;
             }
-            if (use) memcpy(pops, pred, sizeof(double) * n);
-            if (use || nh >= ng_param) {
-                memcpy(hist, pops, sizeof(double) * n);
+        }
+        if (use) memcpy(x, pred, sizeof(double) * n);
+        if (use || full) {
+            have_prev = 0;
+            if (use && fresh) {
+                nh = 0;
+            } else {
+                memcpy(hist, x, sizeof(double) * n);
                 nh = 1;
-                have_prev = 0;
             }
         }
     }
     if (it > max_iter) it = max_iter;
     *iters_out = it;
     *change_out = change;
-    free(chi);
-    free(S);
-    free(J);
-    free(Ls);
     free(nw);
     free(hist);
     free(pred);
     free(prev_pred);
     return status;
+}
+
+/* One Lambda-iteration of a model: line coefficients -> formal solution at
+ * every origin -> statistical equilibrium. */
+typedef struct {
+    const orc_model *m;
+    double *chi, *S, *J, *Ls;
+} lambda_ctx;
+
+static int lambda_step(void *ud, const double *pops, double *out)
+{
+    lambda_ctx *c = (lambda_ctx *)ud;
+    orc_line_coeffs(c->m, pops, c->chi, NULL, c->S);
+    orc_solve_origins(c->m, c->chi, c->S, c->m->npoints, NULL, c->J, c->Ls);
+    return orc_stateq(c->m, c->J, c->Ls, c->S, out);
+}
+
+int orc_iterate(const orc_model *m, double *pops, double tol, int max_iter, int ng_mode,
+                int ng_param, int *iters_out, double *change_out, double *change_hist)
+{
+    return orc_iterate_ev(m, pops, tol, max_iter, ng_mode, ng_param, iters_out, change_out,
+                          change_hist, NULL);
+}
+
+int orc_iterate_ev(const orc_model *m, double *pops, double tol, int max_iter, int ng_mode,
+                   int ng_param, int *iters_out, double *change_out, double *change_hist,
+                   int8_t *events)
+{
+    const size_t nl = (size_t)m->npoints * m->nlines;
+    lambda_ctx c;
+    c.m = m;
+    c.chi = (double *)malloc(sizeof(double) * nl);
+    c.S = (double *)malloc(sizeof(double) * nl);
+    c.J = (double *)malloc(sizeof(double) * nl);
+    c.Ls = (double *)malloc(sizeof(double) * nl);
+    const int st = orc_iterate_map(lambda_step, &c, (int64_t)m->npoints * m->nlev, m->pop_floor,
+                                   pops, tol, max_iter, ng_mode, ng_param, iters_out,
+                                   change_out, change_hist, events);
+    free(c.chi);
+    free(c.S);
+    free(c.J);
+    free(c.Ls);
+    return st;
 }
 
 /* ------------------------------------------------------------------------

@@ -85,10 +85,27 @@ double orc_rel_change(const orc_model *m, const double *a, const double *b, int6
 /* Ng extrapolation from nhist iterates (oldest first) of length n */
 int orc_ng(int nhist, int64_t n, const double *hist, double *out, double *coeffs);
 
-/* full Lambda-iteration; ng_mode 0 none, 1 classical order ng_param,
-   2 adaptive with N_max = ng_param; returns 0 on convergence */
+/* Ng schedule flag: after a used prediction the history holds only the
+   regular iterates computed after it */
+#define ORC_NG_FRESH 0x10
+
+/* one application of a fixed-point map: out = step(in); nonzero aborts */
+typedef int (*orc_map_fn)(void *ud, const double *in, double *out);
+
+/* fixed-point iteration of `step` on x[n] with ng_mode 0 none, 1 classical
+   order ng_param, 2 adaptive with N_max = ng_param (| ORC_NG_FRESH);
+   events[max_iter] (may be NULL) logs the Ng decision of each iteration;
+   returns 0 on convergence, -5 without, -6 if step failed */
+int orc_iterate_map(orc_map_fn step, void *ud, int64_t n, double pop_floor, double *x,
+                    double tol, int max_iter, int ng_mode, int ng_param, int *iters_out,
+                    double *change_out, double *change_hist, int8_t *events);
+
+/* full Lambda-iteration of a model on that schedule */
 int orc_iterate(const orc_model *m, double *pops, double tol, int max_iter, int ng_mode,
                 int ng_param, int *iters_out, double *change_out, double *change_hist);
+int orc_iterate_ev(const orc_model *m, double *pops, double tol, int max_iter, int ng_mode,
+                   int ng_param, int *iters_out, double *change_out, double *change_hist,
+                   int8_t *events);
 
 /* Synthetic image (channel maps) along direction dir: npx x npy pixels over
    the projected extent of the cloud, nfreq observer-frame frequencies
