@@ -1,10 +1,13 @@
 """Benchmark: formal-solution throughput of the line radiative transfer path on
 one MI355X.
 
-Workload (default): the 3D outflow, 50,000 points uniform in the shell
-r in [1, 20] with k = 16 neighbour lists, 10-level linear rotor (9 lines),
-48 HEALPix rays, 31 bins per line; formal solution in FP32 with FP64
-statistical equilibrium and classical Ng of order 4.
+Workload (default): the large-velocity-gradient clumpy cloud, 200,000
+points in a sphere with k = 16 neighbour lists, log-normal density,
+rotation plus turbulence with Doppler shifts up to 20 line widths between
+neighbours, 20-level linear rotor (19 lines), 48 HEALPix rays, 39 bins per
+line; formal solution in FP32 with FP64 statistical equilibrium and
+classical Ng of order 4.  The 3D outflow (50,000 points) and a short
+serving run are reported as extra keys.
 
 A step is one Lambda-iteration over the whole model: line coefficients ->
 formal solution (every origin x ray x line x bin) -> statistical
@@ -50,10 +53,18 @@ FLOP_PER_ELEMENT = 20.0
 FLOP_PER_SEMI = 38.0
 FLOP_PER_SEMI_ONE_WIDTH = 26.0
 FLOP_PER_ORIGIN_ROW = 8.0
-# Peak: 256 CUs x 4 SIMD x 16 lanes x 2 FLOP (FMA) x 2.4 GHz = 78.6 TFLOP/s for
-# FP32 without packed (dual) FP32 instructions, which this build does not use;
-# the packed figure is 157.3 TFLOP/s.  FP64 vector: 78.6 TFLOP/s.
-PEAK_FP32_TFLOPS = 78.6
+# A second, coarser count of the same work: one operation each for ~17
+# simple vector operations, the profile exponential and two reciprocals per
+# element (20), and one per erf/erfc evaluation, two per semi-analytic
+# segment.
+OPS_PER_ELEMENT_COARSE = 20.0
+OPS_PER_SEMI_COARSE = 2.0
+# Peaks: MI355X's published FP32 vector figure is 157.3 TFLOP/s (256 CUs x 4
+# SIMD x 16 lanes x 2 FLOP (FMA) x 2 (packed dual-issue FP32) x 2.4 GHz);
+# without packed FP32 instructions, which this build does not emit, the
+# issue-rate ceiling is half of it, 78.6.  FP64 vector: 78.6 TFLOP/s.
+PEAK_FP32_TFLOPS = 157.3
+PEAK_FP32_NONPACKED_TFLOPS = 78.6
 PEAK_FP64_TFLOPS = 78.6
 
 
@@ -63,7 +74,10 @@ def parse():
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
     p.add_argument("--workload", choices=["outflow", "clumpy", "shells", "batch", "serve"],
-                   default="outflow")
+                   default="clumpy")
+    p.add_argument("--no-extras", action="store_true",
+                   help="default workload only: skip the outflow and serving extra keys")
+    p.add_argument("--extra-serve-seconds", type=float, default=8.0)
     p.add_argument("--serve-seconds", type=float, default=20.0,
                    help="serve workload: length of the request stream")
     p.add_argument("--serve-models", type=int, default=8)
@@ -74,7 +88,7 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--max-iter", type=int, default=200)
-    p.add_argument("--converge-seconds", type=float, default=90.0,
+    p.add_argument("--converge-seconds", type=float, default=240.0,
                    help="stop a converged-model leg after this long (reported)")
     p.add_argument("--ng-study", action="store_true",
                    help="classical vs adaptive Ng iteration counts on the spherical shells")
@@ -108,7 +122,9 @@ def alu_roofline(ctx, m, ms_per_launch, precision):
     per_semi = FLOP_PER_SEMI_ONE_WIDTH if one_width else FLOP_PER_SEMI
     flop = (elements * FLOP_PER_ELEMENT + lanes * c["semi_segments"] * per_semi +
             lanes * m.npoints * npairs * FLOP_PER_ORIGIN_ROW)
-    achieved = flop / (ms_per_launch * 1e-3) / 1e12
+    ops_coarse = elements * OPS_PER_ELEMENT_COARSE + lanes * c["semi_segments"] * OPS_PER_SEMI_COARSE
+    sec = ms_per_launch * 1e-3
+    achieved = flop / sec / 1e12
     peak = PEAK_FP32_TFLOPS if precision == "fp32" else PEAK_FP64_TFLOPS
     # algorithmic HBM bytes of one launch: the packed trace once, the trace
     # offsets, the per-point line table (chi', S' in the solve precision)
@@ -118,15 +134,26 @@ def alu_roofline(ctx, m, ms_per_launch, precision):
     alg_bytes = (c["total_records"] * rec_bytes + (m.npoints * m.nrays + 1) * 8 +
                  m.npoints * m.nlines * 2 * tsz + m.npoints * 2 * tsz +
                  m.npoints * m.nlines * 2 * 8)
-    return {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
-            "frac": round(achieved / peak, 4), "traffic": None,
-            "kernel": "k_formal_solve<%s>" % ("float" if precision == "fp32" else "double"),
-            "flop_per_launch": flop, "elements_per_launch": elements,
-            "semi_segments": c["semi_segments"], "one_width": one_width,
-            "ms_per_launch": round(ms_per_launch, 4),
-            "algorithmic_bytes_per_launch": alg_bytes,
-            "hbm_GBps_algorithmic": round(alg_bytes / (ms_per_launch * 1e-3) / 1e9, 1),
-            "hbm_frac_algorithmic": round(alg_bytes / (ms_per_launch * 1e-3) / 8e12, 5)}
+    out = {"bound": "alu", "achieved": round(achieved, 3), "peak": peak, "unit": "TFLOP/s",
+           "frac": round(achieved / peak, 4), "traffic": None,
+           "kernel": "k_formal_solve<%s>" % ("float" if precision == "fp32" else "double"),
+           "flop_per_launch": flop, "elements_per_launch": elements,
+           "semi_segments": c["semi_segments"], "one_width": one_width,
+           "flop_count": "per element 20 FLOP, per semi-analytic segment and lane %d, per "
+                         "origin row 8 (FMA = 2)" % per_semi,
+           "coarse_count": {"ops_per_launch": ops_coarse,
+                            "rule": "20 per element, 2 (the two erf/erfc) per semi-analytic "
+                                    "segment and lane",
+                            "achieved": round(ops_coarse / sec / 1e12, 3),
+                            "frac": round(ops_coarse / sec / 1e12 / peak, 4)},
+           "ms_per_launch": round(ms_per_launch, 4),
+           "algorithmic_bytes_per_launch": alg_bytes,
+           "hbm_GBps_algorithmic": round(alg_bytes / sec / 1e9, 1),
+           "hbm_frac_algorithmic": round(alg_bytes / sec / 8e12, 5)}
+    if precision == "fp32":
+        out["peak_nonpacked"] = PEAK_FP32_NONPACKED_TFLOPS
+        out["frac_nonpacked"] = round(achieved / PEAK_FP32_NONPACKED_TFLOPS, 4)
+    return out
 
 
 def committed_traffic(workload):
@@ -155,18 +182,20 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def converge(mgx, torch, m, precision, tol, max_iter, time_limit):
-    """Converged-model time from LTE, trace included: the Lambda-iteration with
-    classical Ng of order 4, driven step by step through the C ABI (the same
-    sequence mgx_iterate runs) so progress is visible."""
+def converge(mgx, torch, m, precision, tol, max_iter, time_limit, ng_mode=None, ng_param=4):
+    """Converged-model time from LTE, trace included: the Lambda-iteration
+    with Ng (classical order 4 by default), driven step by step through the C
+    ABI (the same sequence mgx_iterate runs) so progress is visible."""
+    ng_mode = mgx.NG_CLASSICAL if ng_mode is None else ng_mode
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     cx = mgx.Context(device=0, precision=precision)
     cx.load_model(m)
     cx.trace_rays()
     cx.set_lte_populations()
-    cx.ng_reset(5)
-    it, ch, ok = 0, float("inf"), False
+    classical = (ng_mode & 0xF) == mgx.NG_CLASSICAL
+    cx.ng_reset(ng_param + 1 if classical else ng_param)
+    it, ch, ok, applied = 0, float("inf"), False, 0
     while it < max_iter:
         it += 1
         cx.formal_solve(copy=False)
@@ -174,18 +203,21 @@ def converge(mgx, torch, m, precision, tol, max_iter, time_limit):
         if ch <= tol:
             ok = True
             break
-        if it % 4 == 0:
-            cx.ng_accelerate(apply=True)
-        log(f"  converge {'fp32' if precision == mgx.FP32 else 'fp64'} iter {it} "
-            f"change {ch:.3e}")
+        applied += cx.ng_accelerate(ng_mode, ng_param)
+        log(f"  converge {'fp32' if precision == mgx.FP32 else 'fp64'} ng {ng_mode}/{ng_param} "
+            f"iter {it} change {ch:.3e}")
         if time.perf_counter() - t0 > time_limit:
             break
     pops = cx.get_populations()
+    masing = cx.counters()["masing"]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     del cx
     return {"seconds": dt, "iterations": it, "final_change": ch, "converged": ok, "tol": tol,
-            "seconds_per_iteration": dt / it, "pops": pops}
+            "seconds_per_iteration": dt / it, "ng": {"mode": int(ng_mode), "param": ng_param,
+                                                   "predictions_used": applied},
+            "masing_clamps_last_iteration": masing,
+            "cut_at_seconds": None if ok or it >= max_iter else time_limit, "pops": pops}
 
 
 def cpu_baseline(m, seconds, gpu_J=None, converged=None):
@@ -231,7 +263,7 @@ def cpu_baseline(m, seconds, gpu_J=None, converged=None):
         g = np.asarray(gpu_J)[origins]
         out["gpu_Jbar_max_rel_err"] = float(np.max(np.abs(g - J) / np.abs(J)))
     for name, (p, iters, done) in (converged or {}).items():
-        sub = synth.origin_sample(m.npoints, 16, seed=98)
+        sub = synth.origin_sample(m.npoints, 48, seed=98)
         Jc, Lc = orc.solve_origins(p, sub)
         _, _, Sc, _ = orc.line_coeffs(p)
         res = 0.0
@@ -239,6 +271,7 @@ def cpu_baseline(m, seconds, gpu_J=None, converged=None):
             _, new = orc.stateq_point(int(o), Jc[k], Lc[k], Sc[o])
             res = max(res, float(np.max(np.abs(new - p[o]) / np.maximum(p[o], 1e-12))))
         out[f"{name}_pops_oracle_step_max_rel"] = res
+        out[f"{name}_pops_oracle_step_points"] = int(sub.size)
         if name == "fp64":
             per_iter = m.npoints * m.nrays * lanes / rate
             if per_iter * iters < 0.5 * seconds:
@@ -376,14 +409,14 @@ def bench_batch(args, mgx, torch):
     print(json.dumps(out), flush=True)
 
 
-def bench_serve(args, mgx, torch):
+def bench_serve(args, mgx, torch, models=None, seconds=None, emit=True):
     """A Poisson stream of requests (mean 50/s) on resident models: 98 %
     renders (256 x 256 pixels x 63 bins around a line, random model and
     inclination), 2 % converges from LTE (random model, FP32 formal solution,
     tol 1e-6, Ng order 4).  Reports latency percentiles per kind and the
     formal-solution updates/s the server sustained."""
     from paper_2411_03040_amd import synth
-    spec = synth.serve_spec(args.serve_models)
+    spec = synth.serve_spec(args.serve_models if models is None else models)
     srv = mgx.Server(device=0, precision=mgx.FP32, render_slots=2)
     t0 = time.perf_counter()
     models = []
@@ -399,7 +432,7 @@ def bench_serve(args, mgx, torch):
     st0 = srv.stats()
     log(f"bench serve: started in {start_s:.1f} s, resident {st0['hbm_resident'] / 1e9:.1f} GB")
     rng = np.random.default_rng(11)
-    rate, T = 50.0, args.serve_seconds
+    rate, T = 50.0, args.serve_seconds if seconds is None else seconds
     arrivals = np.cumsum(rng.exponential(1.0 / rate, size=int(rate * T * 2)))
     arrivals = arrivals[arrivals < T]
     kinds = np.where(rng.random(arrivals.size) < 0.02, 0, 1)
@@ -461,7 +494,147 @@ def bench_serve(args, mgx, torch):
         "roofline": None, "cpu_baseline": None,
     }
     srv.close()
+    if not emit:
+        return {k: out[k] for k in ("value", "config", "requests", "request_rate_per_s", "wall_s",
+                                    "latency", "replays", "iterate_busy_s", "render_busy_s",
+                                    "hbm", "start_seconds")}
     print(json.dumps(out), flush=True)
+
+
+def bench_single(args, mgx, torch, workload, steps, warmup, converge_legs, cpu, render):
+    """One model: a step is one Lambda-iteration (line coefficients, formal
+    solution, statistical equilibrium, convergence measure, Ng decision)."""
+    m, desc = make_model(workload)
+    prec = mgx.FP32 if args.precision == "fp32" else mgx.FP64
+    ctx = mgx.Context(device=0, precision=prec)
+    ctx.load_model(m)
+    log(f"bench: model {m.name} loaded")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.trace_rays()
+    torch.cuda.synchronize()
+    trace_ms = (time.perf_counter() - t0) * 1e3
+    ctx.set_lte_populations()
+    ng_order = 4
+    ctx.ng_reset(ng_order + 1)
+
+    def step():
+        ctx.formal_solve(copy=False)
+        ctx.update_populations()
+        ctx.ng_accelerate(mgx.NG_CLASSICAL, ng_order)
+
+    for _ in range(warmup):
+        step()
+    log(f"bench: {workload} warmup done")
+    ctx.reset_timers()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_step = dt / steps * 1e3
+    c = ctx.counters()
+    fs_ms = c["fs_ms_total"] / max(c["fs_launches"], 1)
+    updates = m.npoints * m.nrays * m.nlines * m.nbins
+    value = updates / (ms_step * 1e-3)
+    log(f"bench: {workload} {ms_step:.2f} ms/step, formal solution {fs_ms:.2f} ms")
+    # the formal solution alone (line coefficients excluded, trace cached):
+    # median of per-launch event times over 10 more steps, outside the timing
+    fs_each = []
+    for _ in range(10):
+        step()
+        fs_each.append(ctx.counters()["fs_ms_last"])
+    fs_median = float(np.median(fs_each))
+    if args.profile_steps:
+        # calibration for hardware byte counters: a plain elementwise kernel
+        # that reads 256 MiB and writes 256 MiB (larger than every cache level
+        # up to the L2s; run right after a fill of a different buffer)
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        flush = torch.zeros(128 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.mul(src, 2.0, out=dst)
+        torch.cuda.synchronize()
+        del flush
+        return {"ms_per_step": ms_step, "fs_ms": fs_ms, "value": value,
+                "copy_calibration_bytes": src.numel() * 4}
+    rend = None
+    if render and m.dim == 3:
+        # synthetic image as the serving workload asks for it: 256 x 256
+        # pixels x 63 bins around the second line at a seeded inclination
+        rng = np.random.default_rng(7)
+        th = rng.uniform(0, np.pi)
+        view = [np.sin(th), 0.0, np.cos(th)]
+        nu_r = m.nu[min(1, m.nlines - 1)]
+        ctx.render_image(view, 256, 256, nu_r * (1 - 5e-5), nu_r * (1 + 5e-5), 63)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        nrep = 3
+        for _ in range(nrep):
+            ctx.render_image(view, 256, 256, nu_r * (1 - 5e-5), nu_r * (1 + 5e-5), 63)
+        torch.cuda.synchronize()
+        render_ms = (time.perf_counter() - t0) / nrep * 1e3
+        rend = {"pixels": 256 * 256, "bins": 63, "ms": render_ms,
+                "pixel_bins_per_s": 256 * 256 * 63 / (render_ms * 1e-3),
+                "includes": "line coefficients, pixel entry search, walks, integration, "
+                            "copy of the float image to the host"}
+    roof = alu_roofline(ctx, m, fs_ms, args.precision)
+    if args.precision == "fp32":
+        roof["traffic"] = committed_traffic(workload)
+        if roof["traffic"]:
+            roof["hbm_GBps_measured"] = round(roof["traffic"] / (fs_ms * 1e-3) / 1e9, 1)
+    out = {
+        "metric": METRIC, "value": value, "unit": "updates/s", "n_gpus": 1,
+        "steps": steps, "warmup": warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if prec == mgx.FP32 else "f64", "data": "synthetic",
+        "config": {"workload": desc, "npoints": m.npoints, "rays": m.nrays,
+                   "lines": m.nlines, "bins": m.nbins, "levels": m.nlev,
+                   "formal_solve": args.precision, "stateq": "f64", "ng": "classical order 4"},
+        "formal_solve_ms": fs_ms, "trace_ms": trace_ms,
+        "render": rend,
+        "ray_pair_solves_per_s": value / 2.0,
+        "formal_solve_only": {"ms_median": fs_median,
+                              "updates_per_s": updates / (fs_median * 1e-3),
+                              "ray_pair_solves_per_s": updates / (fs_median * 1e-3) / 2.0},
+        "roofline": roof,
+    }
+    del ctx
+    conv_pops = None
+    if converge_legs:
+        conv = {}
+        legs = [("fp32_bulk", mgx.FP32, mgx.NG_CLASSICAL, 4), ("fp64", mgx.FP64, mgx.NG_CLASSICAL, 4)]
+        if workload == "clumpy":
+            legs.insert(1, ("fp32_bulk_adaptive", mgx.FP32, mgx.NG_ADAPTIVE | mgx.NG_FRESH, 8))
+        for name, p, mode, param in legs:
+            tol = 1e-6 if p == mgx.FP32 else 1e-10
+            r = converge(mgx, torch, m, p, tol, max_iter=args.max_iter,
+                         time_limit=args.converge_seconds, ng_mode=mode, ng_param=param)
+            conv[name] = r
+        pops = {k: v.pop("pops") for k, v in conv.items()}
+        a, b = pops["fp32_bulk"], pops["fp64"]
+        conv_pops = {k: (pops[k], conv[k]["iterations"], conv[k]["converged"])
+                     for k in ("fp32_bulk", "fp64")}
+        conv["fp32_vs_fp64_pops_max_rel"] = float(np.max(np.abs(a - b) / np.maximum(b, 1e-12)))
+        conv["fp32_vs_fp64_compares"] = ("two converged states" if conv["fp64"]["converged"]
+                                         else "FP64 state cut before convergence")
+        conv["speedup_fp32_bulk_over_fp64_per_iteration"] = (
+            conv["fp64"]["seconds_per_iteration"] / conv["fp32_bulk"]["seconds_per_iteration"])
+        conv["speedup_fp32_bulk_over_fp64_converged"] = (
+            conv["fp64"]["seconds"] / conv["fp32_bulk"]["seconds"])
+        out["converged"] = conv
+    if cpu:
+        log(f"bench: {workload} CPU oracle baseline")
+        cx = mgx.Context(device=0, precision=prec)
+        cx.load_model(m)
+        cx.trace_rays()
+        cx.set_lte_populations()
+        gpu_J, _ = cx.formal_solve()
+        del cx
+        out["cpu_baseline"] = cpu_baseline(m, args.cpu_seconds, gpu_J=gpu_J, converged=conv_pops)
+    else:
+        out["cpu_baseline"] = None
+    return out
 
 
 def main():
@@ -484,131 +657,22 @@ def main():
     if args.workload == "serve":
         bench_serve(args, mgx, torch)
         return
-    m, desc = make_model(args.workload)
-    prec = mgx.FP32 if args.precision == "fp32" else mgx.FP64
-    ctx = mgx.Context(device=0, precision=prec)
-    ctx.load_model(m)
-    log(f"bench: model {m.name} loaded")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ctx.trace_rays()
-    torch.cuda.synchronize()
-    trace_ms = (time.perf_counter() - t0) * 1e3
-    ctx.set_lte_populations()
-    ng_order = 4
-    ctx.ng_reset(ng_order + 1)
-
-    def step(i):
-        ctx.formal_solve(copy=False)
-        ctx.update_populations()
-        if (i + 1) % ng_order == 0:
-            ctx.ng_accelerate(apply=True)
-
-    for i in range(args.warmup):
-        step(i)
-    log("bench: warmup done")
-    ctx.reset_timers()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step(args.warmup + i)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ms_step = dt / args.steps * 1e3
-    c = ctx.counters()
-    fs_ms = c["fs_ms_total"] / max(c["fs_launches"], 1)
-    updates = m.npoints * m.nrays * m.nlines * m.nbins
-    value = updates / (ms_step * 1e-3)
-    # the formal solution alone (line coefficients excluded, trace cached):
-    # median of per-launch event times over 10 more steps, outside the timing
-    fs_each = []
-    for i in range(10):
-        step(args.warmup + args.steps + i)
-        fs_each.append(ctx.counters()["fs_ms_last"])
-    fs_median = float(np.median(fs_each))
+    out = bench_single(args, mgx, torch, args.workload, args.steps, args.warmup,
+                       converge_legs=not args.no_converge, cpu=not args.no_cpu,
+                       render=True)
     if args.profile_steps:
-        # calibration for hardware byte counters: a plain elementwise kernel
-        # that reads 256 MiB and writes 256 MiB (larger than every cache level
-        # up to the L2s; run right after a fill of a different buffer)
-        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
-        flush = torch.zeros(128 * 1024 * 1024, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        torch.mul(src, 2.0, out=dst)
-        torch.cuda.synchronize()
-        del flush
-        print(json.dumps({"ms_per_step": ms_step, "fs_ms": fs_ms, "value": value,
-                          "copy_calibration_bytes": src.numel() * 4}))
+        print(json.dumps(out), flush=True)
         return
-    # synthetic image as the serving workload asks for it: 256 x 256 pixels x 63
-    # bins around the second line at a seeded inclination
-    rng = np.random.default_rng(7)
-    th = rng.uniform(0, np.pi)
-    view = [np.sin(th), 0.0, np.cos(th)]
-    nu_r = m.nu[min(1, m.nlines - 1)]
-    render = None
-    if m.dim == 3:  # images of point clouds only
-        ctx.render_image(view, 256, 256, nu_r * (1 - 5e-5), nu_r * (1 + 5e-5), 63)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        nrep = 3
-        for _ in range(nrep):
-            ctx.render_image(view, 256, 256, nu_r * (1 - 5e-5), nu_r * (1 + 5e-5), 63)
-        torch.cuda.synchronize()
-        render_ms = (time.perf_counter() - t0) / nrep * 1e3
-        render = {"pixels": 256 * 256, "bins": 63, "ms": render_ms,
-                  "pixel_bins_per_s": 256 * 256 * 63 / (render_ms * 1e-3),
-                  "includes": "line coefficients, pixel entry search, walks, integration, "
-                              "copy of the float image to the host"}
-    roof = alu_roofline(ctx, m, fs_ms, args.precision)
-    if args.precision == "fp32":
-        roof["traffic"] = committed_traffic(args.workload)
-        if roof["traffic"]:
-            roof["hbm_GBps_measured"] = round(roof["traffic"] / (fs_ms * 1e-3) / 1e9, 1)
-    out = {
-        "metric": METRIC, "value": value, "unit": "updates/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32" if prec == mgx.FP32 else "f64", "data": "synthetic",
-        "config": {"workload": desc, "npoints": m.npoints, "rays": m.nrays,
-                   "lines": m.nlines, "bins": m.nbins, "levels": m.nlev,
-                   "formal_solve": args.precision, "stateq": "f64", "ng": "classical order 4"},
-        "formal_solve_ms": fs_ms, "trace_ms": trace_ms,
-        "render": render,
-        "ray_pair_solves_per_s": value / 2.0,
-        "formal_solve_only": {"ms_median": fs_median,
-                              "updates_per_s": updates / (fs_median * 1e-3),
-                              "ray_pair_solves_per_s": updates / (fs_median * 1e-3) / 2.0},
-        "roofline": roof,
-    }
-    del ctx
-    if not args.no_converge:
-        conv = {}
-        for name, p in (("fp32_bulk", mgx.FP32), ("fp64", mgx.FP64)):
-            tol = 1e-6 if p == mgx.FP32 else 1e-10
-            r = converge(mgx, torch, m, p, tol, max_iter=args.max_iter,
-                         time_limit=args.converge_seconds)
-            conv[name] = r
-        a, b = conv["fp32_bulk"].pop("pops"), conv["fp64"].pop("pops")
-        conv_pops = {"fp32_bulk": (a, conv["fp32_bulk"]["iterations"],
-                                   conv["fp32_bulk"]["converged"]),
-                     "fp64": (b, conv["fp64"]["iterations"], conv["fp64"]["converged"])}
-        conv["fp32_vs_fp64_pops_max_rel"] = float(np.max(np.abs(a - b) / np.maximum(b, 1e-12)))
-        conv["speedup_fp32_bulk_over_fp64"] = (conv["fp64"]["seconds_per_iteration"] /
-                                               conv["fp32_bulk"]["seconds_per_iteration"])
-        out["converged"] = conv
-    log(f"bench: timed steps {ms_step:.2f} ms/step")
-    if not args.no_cpu:
-        log("bench: CPU oracle baseline")
-        cx = mgx.Context(device=0, precision=prec)
-        cx.load_model(m)
-        cx.trace_rays()
-        cx.set_lte_populations()
-        gpu_J, _ = cx.formal_solve()
-        del cx
-        out["cpu_baseline"] = cpu_baseline(m, args.cpu_seconds, gpu_J=gpu_J,
-                                           converged=None if args.no_converge else conv_pops)
-    else:
-        out["cpu_baseline"] = None
+    if args.workload == "clumpy" and not args.no_extras:
+        # the 3D outflow: timed steps and the kernel roofline only
+        o = bench_single(args, mgx, torch, "outflow", args.steps, args.warmup,
+                         converge_legs=False, cpu=False, render=False)
+        out["outflow"] = {k: o[k] for k in ("value", "ms_per_step", "formal_solve_ms",
+                                            "config", "roofline", "trace_ms",
+                                            "formal_solve_only")}
+        # a short serving run: p50/p99 latency of converge and render requests
+        out["serving"] = bench_serve(args, mgx, torch, models=3,
+                                     seconds=args.extra_serve_seconds, emit=False)
     print(json.dumps(out), flush=True)
 
 

@@ -58,6 +58,11 @@ typedef enum {
 
 enum { MGX_FP64 = 0, MGX_FP32 = 1 };
 enum { MGX_NG_NONE = 0, MGX_NG_CLASSICAL = 1, MGX_NG_ADAPTIVE = 2 };
+/* Mask of the schedule in an ng_mode value, and a flag or'ed into it: after
+   a used prediction the history is emptied and holds only the regular
+   iterates computed after it (the footnote of the adaptive-Ng paragraph);
+   without the flag the prediction itself is the first stored iterate. */
+enum { MGX_NG_MODE_MASK = 0x0f, MGX_NG_FRESH = 0x10 };
 
 typedef struct {
     /* Precision of the opacity gather, optical depths and Feautrier sweeps.
@@ -66,7 +71,8 @@ typedef struct {
     int precision;
     /* Trapezoidal optical depth while the Doppler shift across a segment is
        below this many line widths, else the semi-analytic form (Section
-       "Semi-analytical approximation for line optical depths"; 0.35). */
+       "Semi-analytical approximation for line optical depths"; 0.35).  At
+       least MGX_MIN_BRANCH_THRESHOLD. */
     double branch_threshold;
     double tau_floor;     /* lower bound on a segment optical depth (1e-15)  */
     double chi_min;       /* masing clamp on chi^ij [m^-1 Hz] (1e-30)         */
@@ -78,6 +84,12 @@ typedef struct {
        either way.  Default 4 GiB; 0: whenever it fits; < 0: never. */
     int64_t trace_slot_min_bytes;
 } mgx_options;
+
+/* Smallest accepted branch_threshold: the semi-analytic optical depth
+   divides by the shift across the segment and, for arguments of opposite
+   sign, forms 2 - erfc(|a|) - erfc(|b|), both of which lose precision as the
+   shift goes to zero. */
+#define MGX_MIN_BRANCH_THRESHOLD 0.1
 
 /* Fills the defaults listed above (precision MGX_FP32). */
 void mgx_default_options(mgx_options *opt);
@@ -142,8 +154,9 @@ typedef struct {
 mgx_status mgx_reset_timers(mgx_ctx *ctx);
 
 /* Create a context on HIP device `device`; `stream` is a hipStream_t (or
-   NULL for a private stream).  opt may be NULL (defaults).
-   Errors: MGX_EINVAL (bad device/options), MGX_EHIP. */
+   NULL for a private stream).  opt may be NULL (defaults).  Options are
+   checked before any HIP call.
+   Errors: MGX_EINVAL (bad options, then bad device), MGX_EHIP. */
 mgx_status mgx_create(mgx_ctx **out, int device, void *stream, const mgx_options *opt);
 
 /* Frees all device memory of the context.  NULL is ignored. */
@@ -162,13 +175,19 @@ const char *mgx_last_error(const mgx_ctx *ctx);
    MGX_ENONFINITE (non-finite inputs), MGX_ENOMEM. */
 mgx_status mgx_load_model(mgx_ctx *ctx, const mgx_model *m);
 
-/* Trace every (origin, ray) through the cloud (neighbour walk; spherical
-   shells for dim 1) and keep the records on the device (geometry is
-   static, so this runs once per model).  Each record holds the point
-   index, the projected distance Z from the origin, the projected velocity
-   difference dv = n.(v - v_origin) and whether the segment ending at the
-   record uses the semi-analytic optical depth (shift >= branch_threshold
-   widths).  total_records_out may be NULL.  Errors: MGX_ESTATE, MGX_ENOMEM. */
+/* Ray tracing (Section "Magritte design": the ray-tracing algorithm of the
+   geometric data structures, which the paper defers to its earlier papers;
+   the walk implemented is: from the current point step to the listed
+   neighbour that lies further along the ray and is closest to the ray line,
+   ties to the earlier list entry, until a boundary point is reached; for
+   dim 1 the shell crossings in path order).  Every (origin, ray) is traced
+   once and the records stay on the device (geometry is static).  Each
+   record holds the point index, the projected distance Z from the origin,
+   the projected velocity difference dv = n.(v - v_origin) and whether the
+   segment ending at the record uses the semi-analytic optical depth
+   (shift >= branch_threshold widths; Section "Semi-analytical approximation
+   for line optical depths").  total_records_out may be NULL.
+   Errors: MGX_ESTATE (no model), MGX_ENOMEM. */
 mgx_status mgx_trace_rays(mgx_ctx *ctx, int64_t *total_records_out);
 
 /* Host copy of the trace of one (origin, ray): up to cap records into idx /
@@ -190,10 +209,19 @@ mgx_status mgx_get_trace_records(mgx_ctx *ctx, int64_t first, int64_t count, int
 mgx_status mgx_set_populations(mgx_ctx *ctx, const double *pops);
 mgx_status mgx_get_populations(mgx_ctx *ctx, double *pops);
 
-/* LTE populations f_i ~ g_i exp(-E_i / k T) (the usual initial guess). */
+/* LTE populations f_i ~ g_i exp(-E_i / k T), normalised per point
+   (compute_LTE_level_populations of the radiative transfer listing in
+   Section "Application / programmer interface": the initial guess of the
+   non-LTE iteration).  Errors: MGX_ESTATE (no model). */
 mgx_status mgx_set_lte_populations(mgx_ctx *ctx);
 
-/* One formal solution from the current populations: line coefficients
+/* One formal solution from the current populations (the radiation-field
+   half of the non-LTE iteration that compute_level_populations_sparse
+   runs; opacity factorisation chi = chi^ij phi^ij(nu), Gaussian profile,
+   line width and Doppler shift equations, trapezoidal-rule and
+   semi-analytic optical depths of Section "Semi-analytical approximation
+   for line optical depths"; the second-order Feautrier solve is the
+   textbook one the paper refers to): line coefficients
    chi^ij = (h nu / 4 pi)(n_l B_lu - n_u B_ul), S = eta^ij / chi^ij, then for
    every origin, ray pair, line and bin the optical depths (trapezoidal or
    semi-analytic) and the Feautrier solve, reduced to
@@ -204,12 +232,22 @@ mgx_status mgx_set_lte_populations(mgx_ctx *ctx);
    Errors: MGX_ESTATE (no trace or populations), MGX_EHIP. */
 mgx_status mgx_formal_solve(mgx_ctx *ctx, double *Jbar, double *Lstar);
 
+/* Launch shape the formal solution uses for a model with `nlines` lines of
+   `nbins` bins in `precision`: lines per workgroup (line chunk), threads per
+   workgroup, and LDS bytes per workgroup at the smallest record chunk.  A
+   host-only query (no device needed).  Errors: MGX_EINVAL. */
+mgx_status mgx_formal_solve_shape(int precision, int nlines, int nbins, int *lines_per_chunk,
+                                  int *threads, int64_t *lds_bytes);
+
 /* Replace the device radiation field ([N][nlines] double each, host or
    device), e.g. to run statistical equilibrium on given inputs. */
 mgx_status mgx_set_radiation(mgx_ctx *ctx, const double *Jbar, const double *Lstar);
 
 /* Statistical equilibrium at every point from the current radiation field
-   with the accelerated Lambda-iteration rates (J_eff = Jbar - Lstar S_old,
+   (the state-of-the-medium half of the iteration that
+   compute_level_populations_sparse runs; the Lambda operator of the Ng
+   appendix comprises this solve and the formal solution) with the
+   accelerated Lambda-iteration rates (J_eff = Jbar - Lstar S_old,
    R_ul = A (1 - Lstar) + B_ul J_eff + C_ul, R_lu = B_lu J_eff + C_lu, row 0
    replaced by sum f = 1), in double.  Replaces the populations; the max over
    points and levels of |new - old| / max(new, pop_floor) goes to
@@ -221,28 +259,56 @@ mgx_status mgx_update_populations(mgx_ctx *ctx, double *max_rel_change_out);
 /* Ng acceleration (Section "Adaptive Ng-acceleration" and its appendix).
    mgx_ng_reset starts a history of at most `capacity` (2..32) iterates with
    the current populations as its first entry; each mgx_update_populations
-   then appends.  mgx_ng_accelerate forms the prediction from the N stored
-   iterates y_1..y_N: residuals r_k = y_{k+1} - y_k, G = R R^T,
-   c = G^-1 1 / 1^T G^-1 1, n* = sum c_k y_{k+1}.  If G is numerically
-   singular or n* has a negative entry the prediction is rejected.  When
-   `apply` is set and the prediction is accepted it replaces the
-   populations; with `apply` set the history then restarts from the
-   populations (accepted prediction or plain iterate).  *status_out: 1
-   accepted, 0 rejected.  *pred_change_out (may be NULL): relative change
-   between this prediction and the previous one formed since the last
-   restart (+inf if none), the adaptive criterion's input. */
+   then appends the new iterate, as does mgx_ng_push (for iterates set with
+   mgx_set_populations).  A full history drops its oldest iterate.
+   Errors: MGX_EINVAL (capacity), MGX_ESTATE (no populations / no history). */
 mgx_status mgx_ng_reset(mgx_ctx *ctx, int capacity);
-mgx_status mgx_ng_accelerate(mgx_ctx *ctx, int apply, int *status_out,
-                             double *pred_change_out);
+mgx_status mgx_ng_push(mgx_ctx *ctx);
 
-/* Lambda-iteration from the current populations until the max relative
-   change is <= tol (at most max_iter iterations): line coefficients ->
-   formal solution -> statistical equilibrium, with ng_mode MGX_NG_NONE,
-   MGX_NG_CLASSICAL (ng_param iterates combined, history of ng_param + 1) or
-   MGX_NG_ADAPTIVE (N_max = ng_param: the prediction from all stored iterates
-   is used once consecutive predictions change less than consecutive
-   iterates, or at N_max).  Errors: MGX_ENOCONV (populations hold the last
-   iterate), MGX_ESINGULAR, MGX_ENONFINITE. */
+/* One decision of the Ng schedule, made after each regular iterate (the
+   paper's non-LTE call takes only the Ng switch; the schedules are those of
+   Section "Adaptive Ng-acceleration"):
+     mode MGX_NG_CLASSICAL, order_or_nmax = N_steps: once N_steps iterates
+       follow the start of the history, the prediction from all N_steps + 1
+       stored iterates replaces the populations;
+     mode MGX_NG_ADAPTIVE, order_or_nmax = N_max: with N >= 3 stored, the
+       prediction P_N from all of them replaces the populations if
+       rel(P_N, P_{N-1}) < rel(y_N, y_{N-1}) (running predictions converge
+       faster than the iterates; rel is the last mgx_update_populations
+       change), or if N = N_max;
+   or'ed with MGX_NG_FRESH for the footnote's restart.  After a used
+   prediction, or when the history is full, the history restarts.  An
+   invalid prediction (see mgx_ng_predict) keeps the plain iterate.
+   *applied_out (may be NULL): 1 if a prediction replaced the populations.
+   Errors: MGX_ESTATE (no mgx_ng_reset), MGX_EINVAL (mode, or a parameter
+   needing more history than the capacity). */
+mgx_status mgx_ng_accelerate(mgx_ctx *ctx, int mode, int order_or_nmax, int *applied_out);
+
+/* The prediction itself (appendix "Derivation of Ng-acceleration") from the
+   N >= 2 stored iterates y_1..y_N: residuals r_k = y_{k+1} - y_k,
+   G = R R^T, c = G^-1 1 / 1^T G^-1 1, n* = sum c_k y_{k+1}.  Invalid if G is
+   numerically singular (a pivot below 1e-14 of its largest diagonal entry)
+   or n* has a negative entry.  With `apply`, a valid prediction replaces
+   the populations and the history restarts from the populations either
+   way.  *status_out: 1 valid, 0 invalid.  *pred_change_out: relative change
+   between this prediction and the previous valid one since the last
+   restart (+inf if none).  coef_out (host or device, N - 1 doubles, may be
+   NULL) receives c when valid.  Any output may be NULL.
+   Errors: MGX_ESTATE (fewer than two stored iterates). */
+mgx_status mgx_ng_predict(mgx_ctx *ctx, int apply, int *status_out, double *pred_change_out,
+                          double *coef_out);
+
+/* The non-LTE solver: compute_level_populations_sparse(Ng_acc, N_iter_max)
+   of the radiative transfer listing (Section "Application / programmer
+   interface"), with the Ng switch widened to a schedule.  Lambda-iteration
+   from the current populations until the max relative change is <= tol (at
+   most max_iter iterations): line coefficients -> formal solution ->
+   statistical equilibrium, then one mgx_ng_accelerate decision with
+   ng_mode MGX_NG_NONE, MGX_NG_CLASSICAL (ng_param = N_steps iterates
+   combined, history of ng_param + 1) or MGX_NG_ADAPTIVE (N_max = ng_param),
+   optionally or'ed with MGX_NG_FRESH.  Counters report the predictions used
+   and rejected.  Errors: MGX_EINVAL (mode or parameter), MGX_ENOCONV
+   (populations hold the last iterate), MGX_ESINGULAR, MGX_ENONFINITE. */
 mgx_status mgx_iterate(mgx_ctx *ctx, double tol, int max_iter, int ng_mode, int ng_param,
                        int *iters_out, double *final_change_out);
 

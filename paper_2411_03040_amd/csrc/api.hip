@@ -25,6 +25,16 @@ extern "C" void mgx_default_options(mgx_options *opt)
     opt->trace_slot_min_bytes = int64_t(4) << 30;
 }
 
+// The semi-analytic form needs segments with a shift of at least
+// MGX_MIN_BRANCH_THRESHOLD widths (its divided difference and the
+// opposite-sign erf difference lose precision as the shift goes to 0).
+bool mgxh::options_valid(const mgx_options &o)
+{
+    return (o.precision == MGX_FP32 || o.precision == MGX_FP64) &&
+           o.branch_threshold >= MGX_MIN_BRANCH_THRESHOLD && std::isfinite(o.branch_threshold) &&
+           o.tau_floor > 0 && o.chi_min > 0 && o.pop_floor > 0;
+}
+
 extern "C" mgx_status mgx_create(mgx_ctx **out, int device, void *stream,
                                  const mgx_options *opt)
 {
@@ -34,17 +44,16 @@ extern "C" mgx_status mgx_create(mgx_ctx **out, int device, void *stream,
         return MGX_EINVAL;
     }
     *out = nullptr;
-    int ndev = 0;
-    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
-        g_create_error = "no such HIP device";
-        return MGX_EINVAL;
-    }
     mgx_options o;
     mgx_default_options(&o);
     if (opt) o = *opt;
-    if ((o.precision != MGX_FP32 && o.precision != MGX_FP64) || !(o.branch_threshold >= 0) ||
-        !(o.tau_floor > 0) || !(o.chi_min > 0) || !(o.pop_floor > 0)) {
+    if (!options_valid(o)) {
         g_create_error = "invalid options";
+        return MGX_EINVAL;
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
+        g_create_error = "no such HIP device";
         return MGX_EINVAL;
     }
     mgx_ctx *c = new (std::nothrow) mgx_ctx();
@@ -598,8 +607,47 @@ void mgxh::run_line_coeffs(mgx_ctx *ctx)
                      ctx->counters.as<Counters>(), ctx->stream);
 }
 
-// Launch shape of one model's formal solution: lines per chunk (balanced)
-// and threads per workgroup (a multiple of 64 covering nlc * nbins).
+// Launch shape of a formal solution: lines per chunk (balanced) and threads
+// per workgroup (a multiple of 64 covering nlc * nbins).  The chunk is also
+// capped so that the LDS staging at the smallest record chunk the launch
+// uses (8 records per half) stays within 64 KiB: with one bin per line a
+// workgroup would otherwise stage up to 1024 lines per record.
+void mgxh::fs_shape(size_t tsize, int nlines, int nbins, int *nlc_out, int *nthreads_out,
+                    size_t *lds_out)
+{
+    const int max_threads = (tsize == 8 && nbins <= 512) ? 512 : kMaxBins;
+    auto threads = [nbins](int nlc) { return ((nlc * nbins + 63) / 64) * 64; };
+    auto lds = [tsize, &threads](int nlc) {
+        return tsize == 8 ? formal_solve_lds<double>(8, nlc, threads(nlc))
+                          : formal_solve_lds<float>(8, nlc, threads(nlc));
+    };
+    int nlc = std::max(1, max_threads / nbins);
+    if (nlc > nlines) nlc = nlines;
+    while (nlc > 1 && lds(nlc) > 64 * 1024) nlc--;
+    // balance the line chunks so the last one is not nearly empty
+    const int nchunks = (nlines + nlc - 1) / nlc;
+    nlc = (nlines + nchunks - 1) / nchunks;
+    *nlc_out = nlc;
+    *nthreads_out = threads(nlc);
+    *lds_out = lds(nlc);
+}
+
+extern "C" mgx_status mgx_formal_solve_shape(int precision, int nlines, int nbins,
+                                             int *lines_per_chunk, int *threads,
+                                             int64_t *lds_bytes)
+{
+    if ((precision != MGX_FP32 && precision != MGX_FP64) || nlines < 1 || nbins < 1 ||
+        nbins > kMaxBins)
+        return MGX_EINVAL;
+    int nlc, nth;
+    size_t lds;
+    fs_shape(precision == MGX_FP64 ? 8 : 4, nlines, nbins, &nlc, &nth, &lds);
+    if (lines_per_chunk) *lines_per_chunk = nlc;
+    if (threads) *threads = nth;
+    if (lds_bytes) *lds_bytes = (int64_t)lds;
+    return MGX_OK;
+}
+
 template <typename T>
 FSArgs<T> mgxh::fs_args(mgx_ctx *ctx)
 {
@@ -609,14 +657,8 @@ FSArgs<T> mgxh::fs_args(mgx_ctx *ctx)
     a.npairs = ctx->npairs;
     a.nlines = ctx->nlines;
     a.nbins = ctx->nbins;
-    const int max_threads = (sizeof(T) == 8 && ctx->nbins <= 512) ? 512 : kMaxBins;
-    int nlc = std::max(1, max_threads / ctx->nbins);
-    if (nlc > ctx->nlines) nlc = ctx->nlines;
-    // balance the line chunks so the last one is not nearly empty
-    const int nchunks = (ctx->nlines + nlc - 1) / nlc;
-    nlc = (ctx->nlines + nchunks - 1) / nchunks;
-    a.nlc = nlc;
-    a.nthreads = ((nlc * ctx->nbins + 63) / 64) * 64;
+    size_t lds;
+    fs_shape(sizeof(T), ctx->nlines, ctx->nbins, &a.nlc, &a.nthreads, &lds);
     a.off = ctx->offsets.as<int64_t>();
     a.rec = (const Rec<T> *)ctx->rec.p;
     a.pair_r = ctx->pair_r.as<int32_t>();
@@ -713,6 +755,12 @@ static DMem *ng_buffer(mgx_ctx *ctx)
 
 void mgxh::ng_append(mgx_ctx *ctx)
 {
+    if (ctx->ng_nh == 0) {  // emptied history: the iterate becomes y_1, no residual yet
+        HIPCHK(launch_copy(ctx->npop(), ctx->pops.as<double>(), ctx->ng_y[0]->as<double>(),
+                           ctx->stream));
+        ctx->ng_nh = 1;
+        return;
+    }
     if (ctx->ng_nh == ctx->ng_cap) {  // window full: drop the oldest iterate
         DMem *y0 = ctx->ng_y.front();
         ctx->ng_y.erase(ctx->ng_y.begin());
@@ -838,7 +886,8 @@ extern "C" mgx_status mgx_ng_reset(mgx_ctx *ctx, int capacity)
     API_END(ctx)
 }
 
-// Forms the prediction into ng_prev (when accepted).  Returns 1 accepted.
+// Forms the prediction from all stored iterates into ng_prev (when valid).
+// Returns 1 if valid (Gram matrix regular, no negative entry).
 int mgxh::ng_predict(mgx_ctx *ctx, double *pred_change)
 {
     const int K = ctx->ng_nh - 1;
@@ -872,7 +921,10 @@ int mgxh::ng_predict(mgx_ctx *ctx, double *pred_change)
     return ok ? 1 : 0;
 }
 
-void mgxh::ng_apply(mgx_ctx *ctx, bool accepted)
+// Use the last valid prediction (or keep the plain iterate) and restart the
+// history: from the populations, or, with `fresh` after a used prediction,
+// empty, so that only regular iterates computed after it are stored.
+void mgxh::ng_apply(mgx_ctx *ctx, bool accepted, bool fresh)
 {
     if (accepted) {
         HIPCHK(launch_copy(ctx->npop(), ctx->ng_prev.as<double>(), ctx->pops.as<double>(),
@@ -881,20 +933,94 @@ void mgxh::ng_apply(mgx_ctx *ctx, bool accepted)
     } else {
         ctx->host_cnt.ng_rejected++;
     }
-    ng_restart(ctx);
+    if (accepted && fresh) {
+        ctx->ng_nh = 0;
+        ctx->ng_have_prev = false;
+    } else {
+        ng_restart(ctx);
+    }
 }
 
-extern "C" mgx_status mgx_ng_accelerate(mgx_ctx *ctx, int apply, int *status_out,
-                                        double *pred_change_out)
+// One decision of the classical or adaptive schedule after a regular
+// iterate has been appended; `change` is the relative change between the
+// last two iterates.  Returns 1 if a prediction replaced the populations.
+int mgxh::ng_schedule_step(mgx_ctx *ctx, int mode, int param, double change)
+{
+    const bool fresh = (mode & MGX_NG_FRESH) != 0;
+    if ((mode & MGX_NG_MODE_MASK) == MGX_NG_CLASSICAL) {
+        if (ctx->ng_nh != param + 1) return 0;
+        double pc;
+        const bool ok = ng_predict(ctx, &pc) != 0;
+        ng_apply(ctx, ok, fresh);
+        return ok ? 1 : 0;
+    }
+    bool use = false;
+    if (ctx->ng_nh >= 3) {
+        double pc;
+        const int ok = ng_predict(ctx, &pc);
+        use = ok && (pc < change || ctx->ng_nh >= param);
+    }
+    if (use)
+        ng_apply(ctx, true, fresh);
+    else if (ctx->ng_nh >= param)
+        ng_apply(ctx, false, fresh);
+    return use ? 1 : 0;
+}
+
+static void check_ng_mode(int ng_mode, int ng_param, bool allow_none)
+{
+    REQUIRE((ng_mode & ~(MGX_NG_MODE_MASK | MGX_NG_FRESH)) == 0, MGX_EINVAL, "unknown ng_mode");
+    const int m = ng_mode & MGX_NG_MODE_MASK;
+    REQUIRE(m == MGX_NG_CLASSICAL || m == MGX_NG_ADAPTIVE || (allow_none && m == MGX_NG_NONE),
+            MGX_EINVAL, "unknown ng_mode");
+    if (m == MGX_NG_CLASSICAL)
+        REQUIRE(ng_param >= 1 && ng_param + 1 <= kNgMaxHist, MGX_EINVAL,
+                "classical Ng order must be 1..31");
+    if (m == MGX_NG_ADAPTIVE)
+        REQUIRE(ng_param >= 3 && ng_param <= kNgMaxHist, MGX_EINVAL,
+                "adaptive Ng N_max must be 3..32");
+}
+
+extern "C" mgx_status mgx_ng_push(mgx_ctx *ctx)
 {
     API_BEGIN(ctx)
-    REQUIRE(ctx->ng_active, MGX_ESTATE, "mgx_ng_accelerate without mgx_ng_reset");
+    REQUIRE(ctx->ng_active, MGX_ESTATE, "mgx_ng_push without mgx_ng_reset");
+    ng_append(ctx);
+    ctx->sync();
+    API_END(ctx)
+}
+
+extern "C" mgx_status mgx_ng_predict(mgx_ctx *ctx, int apply, int *status_out,
+                                     double *pred_change_out, double *coef_out)
+{
+    API_BEGIN(ctx)
+    REQUIRE(ctx->ng_active, MGX_ESTATE, "mgx_ng_predict without mgx_ng_reset");
+    REQUIRE(ctx->ng_nh >= 2, MGX_ESTATE, "mgx_ng_predict needs two stored iterates");
+    const int K = ctx->ng_nh - 1;
     double pc = INFINITY;
     const int ok = ng_predict(ctx, &pc);
-    if (apply) ng_apply(ctx, ok != 0);
+    if (ok && coef_out)
+        HIPCHK(hipMemcpyAsync(coef_out, ctx->ng_coef.p, sizeof(double) * K, hipMemcpyDefault,
+                              ctx->stream));
+    if (apply) ng_apply(ctx, ok != 0, false);
     ctx->sync();
     if (status_out) *status_out = ok;
     if (pred_change_out) *pred_change_out = pc;
+    API_END(ctx)
+}
+
+extern "C" mgx_status mgx_ng_accelerate(mgx_ctx *ctx, int mode, int order_or_nmax,
+                                        int *applied_out)
+{
+    API_BEGIN(ctx)
+    REQUIRE(ctx->ng_active, MGX_ESTATE, "mgx_ng_accelerate without mgx_ng_reset");
+    check_ng_mode(mode, order_or_nmax, false);
+    const int need = (mode & MGX_NG_MODE_MASK) == MGX_NG_CLASSICAL ? order_or_nmax + 1
+                                                                   : order_or_nmax;
+    REQUIRE(need <= ctx->ng_cap, MGX_EINVAL, "Ng history capacity below what the mode needs");
+    const int applied = ng_schedule_step(ctx, mode, order_or_nmax, ctx->host_cnt.last_change);
+    ctx->sync();
+    if (applied_out) *applied_out = applied;
     API_END(ctx)
 }
 
@@ -905,18 +1031,13 @@ extern "C" mgx_status mgx_iterate(mgx_ctx *ctx, double tol, int max_iter, int ng
     REQUIRE(ctx->traced, MGX_ESTATE, "mgx_iterate before mgx_trace_rays");
     REQUIRE(ctx->have_pops, MGX_ESTATE, "mgx_iterate without populations");
     REQUIRE(max_iter >= 1 && tol >= 0, MGX_EINVAL, "max_iter >= 1 and tol >= 0 required");
-    REQUIRE(ng_mode == MGX_NG_NONE || ng_mode == MGX_NG_CLASSICAL || ng_mode == MGX_NG_ADAPTIVE,
-            MGX_EINVAL, "unknown ng_mode");
+    check_ng_mode(ng_mode, ng_param, true);
+    const int mode = ng_mode & MGX_NG_MODE_MASK;
     ctx->ng_active = false;
-    if (ng_mode == MGX_NG_CLASSICAL) {
-        REQUIRE(ng_param >= 1 && ng_param + 1 <= kNgMaxHist, MGX_EINVAL,
-                "classical Ng order must be 1..31");
+    if (mode == MGX_NG_CLASSICAL)
         ng_reset(ctx, ng_param + 1);
-    } else if (ng_mode == MGX_NG_ADAPTIVE) {
-        REQUIRE(ng_param >= 3 && ng_param <= kNgMaxHist, MGX_EINVAL,
-                "adaptive Ng N_max must be 3..32");
+    else if (mode == MGX_NG_ADAPTIVE)
         ng_reset(ctx, ng_param);
-    }
     ctx->host_cnt.ng_applied = ctx->host_cnt.ng_rejected = 0;
     double change = INFINITY;
     int it = 0;
@@ -933,24 +1054,7 @@ extern "C" mgx_status mgx_iterate(mgx_ctx *ctx, double tol, int max_iter, int ng
             result = MGX_OK;
             break;
         }
-        if (ng_mode == MGX_NG_CLASSICAL) {
-            if (ctx->ng_nh == ng_param + 1) {
-                double pc;
-                ng_apply(ctx, ng_predict(ctx, &pc) != 0);
-            }
-        } else if (ng_mode == MGX_NG_ADAPTIVE) {
-            bool use = false;
-            if (ctx->ng_nh >= 3) {
-                double pc;
-                const int ok = ng_predict(ctx, &pc);
-                use = ok && (pc < change || ctx->ng_nh >= ng_param);
-            }
-            if (use) {
-                ng_apply(ctx, true);
-            } else if (ctx->ng_nh >= ng_param) {
-                ng_apply(ctx, false);
-            }
-        }
+        if (mode != MGX_NG_NONE) ng_schedule_step(ctx, ng_mode, ng_param, change);
     }
     if (it > max_iter) it = max_iter;
     ctx->ng_active = false;

@@ -23,14 +23,18 @@ extern "C" mgx_status mgx_batch_create(mgx_batch **out, int device, void *stream
     g_create_error.clear();
     if (!out) return MGX_EINVAL;
     *out = nullptr;
+    mgx_options o;
+    mgx_default_options(&o);
+    if (opt) o = *opt;
+    if (!options_valid(o)) {
+        g_create_error = "invalid options";
+        return MGX_EINVAL;
+    }
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) {
         g_create_error = "no such HIP device";
         return MGX_EINVAL;
     }
-    mgx_options o;
-    mgx_default_options(&o);
-    if (opt) o = *opt;
     mgx_batch *b = new (std::nothrow) mgx_batch();
     if (!b) return MGX_ENOMEM;
     b->device = device;

@@ -277,13 +277,17 @@ void run_line_coeffs(mgx_ctx *ctx);
 // (S_unit > 0: the solve-precision source function is S / S_unit, else S / Iref)
 void line_coeffs_into(mgx_ctx *ctx, const double *pops, void *chiT, void *ST, double *S64,
                       Counters *cnt, hipStream_t s, double S_unit = 0.0);
+bool options_valid(const mgx_options &o);
+void fs_shape(size_t tsize, int nlines, int nbins, int *nlc_out, int *nthreads_out,
+              size_t *lds_out);
 template <typename T>
 FSArgs<T> fs_args(mgx_ctx *ctx);
 StateqArgs stateq_args(mgx_ctx *ctx);
 void ng_reset(mgx_ctx *ctx, int capacity);
 void ng_append(mgx_ctx *ctx);
 int ng_predict(mgx_ctx *ctx, double *pred_change);
-void ng_apply(mgx_ctx *ctx, bool accepted);
+void ng_apply(mgx_ctx *ctx, bool accepted, bool fresh = false);
+int ng_schedule_step(mgx_ctx *ctx, int mode, int param, double change);
 // expected points per pixel walk (4 N^(1/3) + 16): the slot size of the
 // one-pass walk and the server's footprint estimate
 inline int64_t render_walk_cap(int N) { return (int64_t)(4.0 * cbrt((double)N) + 16.0); }

@@ -22,6 +22,9 @@ MGX_OK, MGX_EINVAL, MGX_ESTATE, MGX_ENOMEM, MGX_EHIP = 0, -1, -2, -3, -4
 MGX_ENOCONV, MGX_ESINGULAR, MGX_ENONFINITE, MGX_EPENDING = -5, -6, -7, -8
 FP64, FP32 = 0, 1
 NG_NONE, NG_CLASSICAL, NG_ADAPTIVE = 0, 1, 2
+# or'ed into an Ng mode: after a used prediction only later regular iterates
+# are stored
+NG_FRESH = 0x10
 
 _STATUS = {0: "MGX_OK", -1: "MGX_EINVAL", -2: "MGX_ESTATE", -3: "MGX_ENOMEM", -4: "MGX_EHIP",
            -5: "MGX_ENOCONV", -6: "MGX_ESINGULAR", -7: "MGX_ENONFINITE", -8: "MGX_EPENDING"}
@@ -122,9 +125,12 @@ def lib():
         "mgx_set_lte_populations": (I, [P]),
         "mgx_formal_solve": (I, [P, P, P]),
         "mgx_set_radiation": (I, [P, P, P]),
+        "mgx_formal_solve_shape": (I, [I, I, I, P, P, P]),
         "mgx_update_populations": (I, [P, P]),
         "mgx_ng_reset": (I, [P, I]),
-        "mgx_ng_accelerate": (I, [P, I, P, P]),
+        "mgx_ng_accelerate": (I, [P, I, I, P]),
+        "mgx_ng_predict": (I, [P, I, P, P, P]),
+        "mgx_ng_push": (I, [P]),
         "mgx_iterate": (I, [P, D, I, I, I, P, P]),
         "mgx_get_counters": (I, [P, P]),
         "mgx_reset_timers": (I, [P]),
@@ -346,10 +352,23 @@ class Context:
     def ng_reset(self, capacity: int) -> None:
         self._check(lib().mgx_ng_reset(self._h, capacity))
 
-    def ng_accelerate(self, apply: bool = True):
+    def ng_push(self) -> None:
+        self._check(lib().mgx_ng_push(self._h))
+
+    def ng_accelerate(self, mode: int, param: int) -> bool:
+        """One decision of the classical / adaptive Ng schedule; True if a
+        prediction replaced the populations."""
+        ap = C.c_int()
+        self._check(lib().mgx_ng_accelerate(self._h, int(mode), int(param), C.byref(ap)))
+        return bool(ap.value)
+
+    def ng_predict(self, apply: bool = False):
+        """(valid, change against the previous prediction, coefficients)."""
         st, pc = C.c_int(), C.c_double()
-        self._check(lib().mgx_ng_accelerate(self._h, int(apply), C.byref(st), C.byref(pc)))
-        return bool(st.value), pc.value
+        coef = np.zeros(32)
+        self._check(lib().mgx_ng_predict(self._h, int(apply), C.byref(st), C.byref(pc),
+                                         _ptr(coef)))
+        return bool(st.value), pc.value, coef
 
     def iterate(self, tol: float = 1e-10, max_iter: int = 500, ng_mode: int = NG_NONE,
                 ng_param: int = 4, raise_on_noconv: bool = True):
@@ -559,6 +578,17 @@ class Server:
         s = ServerStats()
         self._check(lib().mgx_server_get_stats(self._h, C.byref(s)))
         return {k: getattr(s, k) for k, _ in ServerStats._fields_}
+
+
+def formal_solve_shape(precision: int, nlines: int, nbins: int):
+    """(lines per chunk, threads per workgroup, LDS bytes) of the formal
+    solution's launch for such a model (host-only query)."""
+    nlc, nth, lds = C.c_int(), C.c_int(), C.c_int64()
+    st = lib().mgx_formal_solve_shape(precision, nlines, nbins, C.byref(nlc), C.byref(nth),
+                                      C.byref(lds))
+    if st != MGX_OK:
+        raise MgxError(st, "invalid formal-solution shape query")
+    return nlc.value, nth.value, lds.value
 
 
 def header_functions(header_path: Optional[str] = None):

@@ -52,3 +52,42 @@ def test_create_without_gpu_fails_cleanly():
     with pytest.raises(mgx.MgxError) as e:
         mgx.Context(device=0, use_torch_stream=False)
     assert e.value.status == mgx.MGX_EINVAL
+
+
+def test_options_checked_before_the_device():
+    """Invalid options fail with MGX_EINVAL before any HIP call, so this
+    runs without a GPU: a branch threshold of 0 (every segment would take the
+    semi-analytic form, including unshifted ones, dividing by a zero shift)
+    and one below the stated minimum."""
+    from paper_2411_03040_amd import mgx
+    L = mgx.lib()
+    for thr in (0.0, 0.05, float("nan")):
+        o = mgx.Options()
+        L.mgx_default_options(ctypes.byref(o))
+        o.branch_threshold = thr
+        h = ctypes.c_void_p()
+        st = L.mgx_create(ctypes.byref(h), 0, None, ctypes.byref(o))
+        assert st == mgx.MGX_EINVAL
+        assert L.mgx_last_error(None) == b"invalid options"
+        st = L.mgx_batch_create(ctypes.byref(h), 0, None, ctypes.byref(o))
+        assert st == mgx.MGX_EINVAL
+        assert L.mgx_batch_last_error(None) == b"invalid options"
+
+
+def test_formal_solve_shape_fits_lds():
+    """One bin per line and 2016 lines: the line chunk is capped so the LDS
+    staging fits (the workgroup would otherwise stage 1024 lines per
+    record); the usual workloads keep their shape (every line of the outflow
+    and the clumpy cloud in one workgroup)."""
+    from paper_2411_03040_amd import mgx
+    for prec in (mgx.FP32, mgx.FP64):
+        nlc, nth, lds = mgx.formal_solve_shape(prec, 2016, 1)
+        assert lds <= 64 * 1024 and nth % 64 == 0 and nth >= nlc and nlc >= 1
+        for nl, nb in ((9, 31), (19, 39), (1, 1024), (1, 1), (300, 7)):
+            nlc, nth, lds = mgx.formal_solve_shape(prec, nl, nb)
+            assert lds <= 64 * 1024 and nth <= 1024 and nth >= nlc * nb
+    assert mgx.formal_solve_shape(mgx.FP32, 9, 31)[0] == 9
+    assert mgx.formal_solve_shape(mgx.FP32, 19, 39)[0] == 19
+    assert mgx.formal_solve_shape(mgx.FP64, 9, 31)[0] == 9
+    with pytest.raises(mgx.MgxError):
+        mgx.formal_solve_shape(mgx.FP32, 1, 1025)

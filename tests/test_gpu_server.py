@@ -3,8 +3,10 @@ models, run through the C ABI.
 
 The bar is identity: a request's result (published populations, image) is
 bit for bit the result of the same work done alone -- by a lone context
-(itself checked against the oracle in the parity tests) and by a server that
-runs only that request -- whatever else is in flight.
+and by a server that runs only that request -- whatever else is in flight.
+The results of a request run inside a mixed stream are also compared with
+the oracle directly: converged populations (FP32-bulk bar, 1e-4), one oracle
+Lambda-iteration step from them, and sampled pixels of a render (2e-5).
 """
 import sys
 
@@ -140,6 +142,30 @@ def test_server_alone_vs_mixed(mgx):
     assert bits_equal(b.get_populations(0), pa)
     assert bits_equal(img_a, img_b)
     b.close()
+
+    # the mixed-stream results against the oracle: the converge request's
+    # populations against the oracle's own converged populations (FP32-bulk
+    # bar) and against one oracle Lambda-iteration step from them; the render
+    # against the oracle's pixels from the same populations
+    import oracle
+    m = ms[0]
+    orc = oracle.Oracle(m)
+    ref = orc.iterate(tol=1e-12, max_iter=500, ng_mode=1, ng_param=4)
+    assert ref["status"] == 0
+    e_conv = float(np.max(np.abs(pb - ref["pops"]) / np.maximum(ref["pops"], 1e-12)))
+    J, L = orc.solve_origins(pb)
+    _, _, S, _ = orc.line_coeffs(pb)
+    st, step = orc.stateq(J, L, S)
+    assert st == 0
+    e_step = float(np.max(np.abs(step - pb) / np.maximum(pb, 1e-12)))
+    rng2 = np.random.default_rng(9)
+    pix = [(int(x), int(y)) for x, y in zip(rng2.integers(0, 32, 16), rng2.integers(0, 24, 16))]
+    Io, _ = orc.render_pixels(pb, VIEW, 32, 24, *band(m), 21, pix)
+    got = np.array([img_b[y, x] for x, y in pix], np.float64)
+    e_img = float(np.max(np.abs(got - Io) / np.abs(Io)))
+    say(f"  mixed-stream converge vs oracle {e_conv:.2e}, oracle step {e_step:.2e}, "
+        f"render vs oracle {e_img:.2e}")
+    assert e_conv < 1e-4 and e_step < 1e-4 and e_img < 2e-5
 
 
 def test_server_admission_and_errors(mgx):
