@@ -298,6 +298,27 @@ mgx_status mgx_ng_accelerate(mgx_ctx *ctx, int mode, int order_or_nmax, int *app
 mgx_status mgx_ng_predict(mgx_ctx *ctx, int apply, int *status_out, double *pred_change_out,
                           double *coef_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid allocation): the
+   prediction of mgx_ng_predict from nhist (2..32) iterates the caller keeps
+   on device `device`, without a context and without allocating.
+   iterates: host array of nhist device pointers, oldest first, each to n
+   doubles.  prediction (n doubles), coef (nhist - 1 doubles) and status (one
+   int) are device memory the caller owns: coef and prediction are written
+   when the Gram matrix is regular, *status = 1 if the prediction is valid
+   (regular Gram matrix, no negative entry), else 0.  All work is enqueued on
+   `stream` (a hipStream_t; NULL: the default stream) and nothing is
+   synchronised: the results are ready when the stream reaches them.  The
+   Gram rows' partial sums, the Gram matrix and the flags live in a fixed
+   area of about 265 KiB compiled into the library, one per GPU, held until
+   the process ends; every call on a GPU shares it, so calls that overlap on
+   one GPU (other streams, other threads) race and must be serialised by the
+   caller.  Errors (message from mgx_last_error(NULL)): MGX_EINVAL (nhist
+   outside 2..32, n < 1, NULL pointers, no such device), MGX_EHIP. */
+mgx_status mgx_ng_predict_noalloc(int device, void *stream, const double *const *iterates,
+                                  int nhist, int64_t n, double *prediction, double *coef,
+                                  int *status);
+
 /* The non-LTE solver: compute_level_populations_sparse(Ng_acc, N_iter_max)
    of the radiative transfer listing (Section "Application / programmer
    interface"), with the Ng switch widened to a schedule.  Lambda-iteration

@@ -193,3 +193,164 @@ hipError_t launch_ng_predict(int64_t n, int K, const double *G, const PtrTable &
 }
 
 }  // namespace mgx
+
+// ---------------------------------------------------------------------------
+// The prediction without device allocation (mgx_ng_predict_noalloc): the
+// iterates stay where the caller keeps them, and everything else the
+// kernels need -- the Gram rows' block partial sums, the Gram matrix, the
+// solve's status and the negative-entry flag -- lives in one fixed area
+// compiled into the library.  Each GPU the library runs on holds its own
+// copy until the process ends; host code reaches it only through the
+// address hipGetSymbolAddress returns on that device.
+// ---------------------------------------------------------------------------
+namespace mgx {
+
+constexpr int kScratchPartial = 1024 * kNgKMax;     // block partials (max blocks x columns)
+constexpr int kScratchG = kNgKMax * kNgKMax;        // Gram matrix
+constexpr int kScratchDoubles = kScratchPartial + kScratchG + 32;  // + 256 bytes of flags
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+// Row j of the Gram matrix from the iterates themselves: r_j = y_{j+1} - y_j
+// against r_a = y_{a+1} - y_a (a <= j), block partials as k_ng_append forms
+// them (same residual arithmetic, same per-thread order, same tree), so the
+// matrix is the one the context's incremental path builds.
+__global__ __launch_bounds__(kNgThreads) void k_ng_gram_row(int64_t n, int j, const PtrTable y,
+                                                          double *partial)
+{
+    double acc[kNgKMax];
+#pragma unroll
+    for (int a = 0; a < kNgKMax; a++) acc[a] = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double rn = y.p[j + 1][i] - y.p[j][i];
+#pragma unroll
+        for (int a = 0; a < kNgKMax; a++) {
+            if (a < j) acc[a] += (y.p[a + 1][i] - y.p[a][i]) * rn;
+        }
+#pragma unroll
+        for (int a = 0; a < kNgKMax; a++)
+            if (a == j) acc[a] += rn * rn;
+    }
+    __shared__ double red[kNgThreads];
+    for (int a = 0; a <= j; a++) {
+        red[threadIdx.x] = acc[a];
+        __syncthreads();
+        for (int s = kNgThreads / 2; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) partial[(size_t)blockIdx.x * kNgKMax + a] = red[0];
+        __syncthreads();
+    }
+}
+
+// flags[0]: Gram solve status, flags[1]: negative entry seen
+__global__ void k_noalloc_clear(int *flags)
+{
+    if (threadIdx.x < 4) flags[threadIdx.x] = 0;
+}
+
+__global__ void k_noalloc_status(const int *flags, int *status_out)
+{
+    if (threadIdx.x == 0) *status_out = (flags[0] == 0 && flags[1] == 0) ? 1 : 0;
+}
+
+}  // namespace mgx
+
+#include <mutex>
+
+#include "../../include/mgx.h"
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch[kMaxDevices];  // per device: the address of `scratch` there
+}  // namespace
+
+// message of the last failed call without a context (mgx_last_error(NULL))
+namespace mgxh {
+extern thread_local std::string g_create_error;
+}
+
+extern "C" mgx_status mgx_ng_predict_noalloc(int device, void *stream,
+                                             const double *const *iterates, int nhist, int64_t n,
+                                             double *prediction, double *coef, int *status)
+{
+    using namespace mgx;
+    std::string &err = mgxh::g_create_error;
+    err.clear();
+    if (nhist < 2 || nhist > kNgMaxHist) {
+        err = "nhist must be 2.." + std::to_string(kNgMaxHist) + " (fixed scratch area)";
+        return MGX_EINVAL;
+    }
+    if (n < 1 || !iterates || !prediction || !coef || !status) {
+        err = "n >= 1 and non-NULL iterates, prediction, coef and status required";
+        return MGX_EINVAL;
+    }
+    for (int k = 0; k < nhist; k++)
+        if (!iterates[k]) {
+            err = "NULL iterate pointer";
+            return MGX_EINVAL;
+        }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev ||
+        device >= kMaxDevices) {
+        err = "no such HIP device";
+        return MGX_EINVAL;
+    }
+    int prev = -1;
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != device && hipSetDevice(device) != hipSuccess) {
+        err = "hipSetDevice failed";
+        return MGX_EHIP;
+    }
+    mgx_status rc = MGX_OK;
+    double *base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (!g_scratch[device]) {
+            void *p = nullptr;
+            const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e == hipSuccess && p)
+                g_scratch[device] = (double *)p;
+            else
+                err = std::string("hipGetSymbolAddress: ") + hipGetErrorString(e);
+        }
+        base = g_scratch[device];
+    }
+    if (!base) rc = MGX_EHIP;
+    if (rc == MGX_OK) {
+        hipStream_t s = (hipStream_t)stream;
+        double *partial = base;
+        double *G = base + kScratchPartial;
+        int *flags = (int *)(base + kScratchPartial + kScratchG);
+        PtrTable y{};
+        for (int k = 0; k < nhist; k++) y.p[k] = iterates[k];
+        PtrTable yt{};
+        for (int k = 0; k + 1 < nhist; k++) yt.p[k] = iterates[k + 1];
+        const int K = nhist - 1;
+        const int nb = ng_gram_blocks(n);
+        hipError_t e = hipSuccess;
+        k_noalloc_clear<<<1, 64, 0, s>>>(flags);
+        e = hipGetLastError();
+        for (int j = 0; j < K && e == hipSuccess; j++) {
+            k_ng_gram_row<<<nb, kNgThreads, 0, s>>>(n, j, y, partial);
+            e = hipGetLastError();
+            if (e == hipSuccess) {
+                k_ng_grow<<<j + 1, kNgThreads, 0, s>>>(j + 1, partial, nb, G);
+                e = hipGetLastError();
+            }
+        }
+        if (e == hipSuccess) e = launch_ng_predict(n, K, G, yt, coef, flags, prediction, flags + 1, s);
+        if (e == hipSuccess) {
+            k_noalloc_status<<<1, 64, 0, s>>>(flags, status);
+            e = hipGetLastError();
+        }
+        if (e != hipSuccess) {
+            err = std::string("HIP: ") + hipGetErrorString(e);
+            rc = MGX_EHIP;
+        }
+    }
+    if (prev >= 0 && prev != device) (void)hipSetDevice(prev);
+    return rc;
+}

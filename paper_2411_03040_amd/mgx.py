@@ -131,6 +131,7 @@ def lib():
         "mgx_ng_accelerate": (I, [P, I, I, P]),
         "mgx_ng_predict": (I, [P, I, P, P, P]),
         "mgx_ng_push": (I, [P]),
+        "mgx_ng_predict_noalloc": (I, [I, P, P, I, I64, P, P, P]),
         "mgx_iterate": (I, [P, D, I, I, I, P, P]),
         "mgx_get_counters": (I, [P, P]),
         "mgx_reset_timers": (I, [P]),
@@ -578,6 +579,22 @@ class Server:
         s = ServerStats()
         self._check(lib().mgx_server_get_stats(self._h, C.byref(s)))
         return {k: getattr(s, k) for k, _ in ServerStats._fields_}
+
+
+def ng_predict_noalloc(iterates, prediction, coef, status, device: int = 0,
+                       stream: Optional[int] = None) -> None:
+    """Ng prediction from device iterates without allocation (see the C
+    header): iterates is a sequence of contiguous device tensors of equal
+    length, prediction / coef / status device tensors (float64, float64,
+    int32).  Enqueued on torch's current stream unless stream is given."""
+    nh = len(iterates)
+    table = (C.c_void_p * max(nh, 1))(*[_ptr(t) for t in iterates])
+    n = int(iterates[0].numel()) if nh else 0
+    s = _torch_stream(device) if stream is None else stream
+    st = lib().mgx_ng_predict_noalloc(device, s, table, nh, n, _ptr(prediction), _ptr(coef),
+                                      _ptr(status))
+    if st != MGX_OK:
+        raise MgxError(st, lib().mgx_last_error(None).decode())
 
 
 def formal_solve_shape(precision: int, nlines: int, nbins: int):
