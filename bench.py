@@ -88,6 +88,8 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--max-iter", type=int, default=200)
+    p.add_argument("--tol", type=float, default=1e-6,
+                   help="converged-model legs: relative-change tolerance of every leg")
     p.add_argument("--converge-seconds", type=float, default=240.0,
                    help="stop a converged-model leg after this long (reported)")
     p.add_argument("--ng-study", action="store_true",
@@ -220,7 +222,7 @@ def converge(mgx, torch, m, precision, tol, max_iter, time_limit, ng_mode=None, 
             "cut_at_seconds": None if ok or it >= max_iter else time_limit, "pops": pops}
 
 
-def cpu_baseline(m, seconds, gpu_J=None, converged=None):
+def cpu_baseline(m, seconds, gpu_J=None, converged=None, tol=1e-10):
     """The oracle (all host cores) on a seeded sample of origins of the same
     model from LTE populations, as updates/s.  With the GPU's J-bar from the
     same LTE populations (gpu_J), also its largest relative error on the
@@ -278,7 +280,7 @@ def cpu_baseline(m, seconds, gpu_J=None, converged=None):
                 # small enough: the oracle converges the model itself (same
                 # tolerance and Ng schedule as the FP64 GPU form)
                 t0 = time.perf_counter()
-                r = orc.iterate(tol=1e-10, max_iter=2000, ng_mode=1, ng_param=4)
+                r = orc.iterate(tol=tol, max_iter=2000, ng_mode=1, ng_param=4)
                 out["oracle_converged_seconds"] = time.perf_counter() - t0
                 out["oracle_converged_iterations"] = r["iters"]
                 out["fp64_pops_max_rel_vs_oracle"] = float(
@@ -606,8 +608,10 @@ def bench_single(args, mgx, torch, workload, steps, warmup, converge_legs, cpu, 
         legs = [("fp32_bulk", mgx.FP32, mgx.NG_CLASSICAL, 4), ("fp64", mgx.FP64, mgx.NG_CLASSICAL, 4)]
         if workload == "clumpy":
             legs.insert(1, ("fp32_bulk_adaptive", mgx.FP32, mgx.NG_ADAPTIVE | mgx.NG_FRESH, 8))
+        # every leg to the same tolerance (the FP32-bulk form's), so the
+        # converged-model times compare like for like
         for name, p, mode, param in legs:
-            tol = 1e-6 if p == mgx.FP32 else 1e-10
+            tol = args.tol
             r = converge(mgx, torch, m, p, tol, max_iter=args.max_iter,
                          time_limit=args.converge_seconds, ng_mode=mode, ng_param=param)
             conv[name] = r
@@ -631,7 +635,8 @@ def bench_single(args, mgx, torch, workload, steps, warmup, converge_legs, cpu, 
         cx.set_lte_populations()
         gpu_J, _ = cx.formal_solve()
         del cx
-        out["cpu_baseline"] = cpu_baseline(m, args.cpu_seconds, gpu_J=gpu_J, converged=conv_pops)
+        out["cpu_baseline"] = cpu_baseline(m, args.cpu_seconds, gpu_J=gpu_J, converged=conv_pops,
+                                           tol=args.tol)
     else:
         out["cpu_baseline"] = None
     return out

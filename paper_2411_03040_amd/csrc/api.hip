@@ -827,7 +827,7 @@ StateqArgs mgxh::stateq_args(mgx_ctx *ctx)
 static mgx_status update_populations(mgx_ctx *ctx, double *change_out)
 {
     StateqArgs s = stateq_args(ctx);
-    HIPCHK(launch_reset_counters(ctx->counters.as<Counters>(), ctx->stream));
+    HIPCHK(launch_reset_counters(ctx->counters.as<Counters>(), ctx->stream, false));
     HIPCHK(launch_stateq(s, ctx->stream));
     std::swap(ctx->pops.p, ctx->pops_new.p);
     std::swap(ctx->pops.bytes, ctx->pops_new.bytes);
@@ -836,6 +836,7 @@ static mgx_status update_populations(mgx_ctx *ctx, double *change_out)
     double change;
     memcpy(&change, &c.change_bits, sizeof(double));
     ctx->host_cnt.singular = (int64_t)c.singular;
+    ctx->host_cnt.masing = (int64_t)c.masing;
     ctx->host_cnt.last_change = change;
     ctx->have_rad = false;
     if (change_out) *change_out = change;

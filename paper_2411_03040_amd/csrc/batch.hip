@@ -319,7 +319,7 @@ static void batch_capture(mgx_batch *b)
             StateqArgs s = stateq_args(c);
             s.active = b->active.as<int>();
             s.model = i;
-            HIPCHK(launch_reset_counters(c->counters.as<Counters>(), b->stream));
+            HIPCHK(launch_reset_counters(c->counters.as<Counters>(), b->stream, false));
             HIPCHK(launch_stateq(s, b->stream));
             HIPCHK(launch_copy_if_active(c->npop(), c->pops_new.as<double>(), c->pops.as<double>(),
                                          b->active.as<int>(), i, b->stream));

@@ -177,7 +177,9 @@ hipError_t launch_lte(int N, int nlev, const double *T, const double *E, const d
                       double *pops, hipStream_t s);
 int stateq_group(int nlev);  // lanes per point of the statistical-equilibrium kernel
 hipError_t launch_stateq(const StateqArgs &a, hipStream_t s);
-hipError_t launch_reset_counters(Counters *c, hipStream_t s);
+// with_masing false: keep the masing count of the last line-coefficient pass
+// (the statistical-equilibrium step resets only its own counters)
+hipError_t launch_reset_counters(Counters *c, hipStream_t s, bool with_masing = true);
 hipError_t launch_rel_change(int64_t n, const double *a, const double *b, double floor_,
                              unsigned long long *bits, hipStream_t s);
 hipError_t launch_bin_table(int nbins, double xmax, double *xf, double *W, hipStream_t s);

@@ -19,19 +19,19 @@
 
 namespace mgx {
 
-__global__ void k_reset_counters(Counters *c)
+__global__ void k_reset_counters(Counters *c, int with_masing)
 {
     if (threadIdx.x == 0) {
-        c->masing = 0;
+        if (with_masing) c->masing = 0;
         c->singular = 0;
         c->nonfinite = 0;
         c->change_bits = 0;
     }
 }
 
-hipError_t launch_reset_counters(Counters *c, hipStream_t s)
+hipError_t launch_reset_counters(Counters *c, hipStream_t s, bool with_masing)
 {
-    k_reset_counters<<<1, 64, 0, s>>>(c);
+    k_reset_counters<<<1, 64, 0, s>>>(c, with_masing ? 1 : 0);
     return hipGetLastError();
 }
 

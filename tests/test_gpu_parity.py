@@ -577,6 +577,30 @@ def test_iterate_small_outflow_fp32_and_fp64(mgx):
         assert ok and e < bar
 
 
+def test_masing_count_matches_oracle(mgx):
+    """Populations inverted on purpose at a third of the points: the line
+    coefficients clamp chi^ij there; the count equals the oracle's, and it
+    is still reported after the statistical-equilibrium step that follows
+    (and after a whole mgx_iterate)."""
+    m = synth.tiny_cloud(npoints=300, seed=71, k=10, nside=1, nlev=3, nbins=5)
+    orc = oracle.Oracle(m)
+    pops = orc.lte()
+    pops[::3, 0] *= 0.01            # J=0 depleted: n_1/g_1 > n_0/g_0 on the 1-0 line
+    pops /= pops.sum(1, keepdims=True)
+    _, _, _, n_orc = orc.line_coeffs(pops)
+    assert n_orc > 50
+    for prec in (mgx.FP64, mgx.FP32):
+        ctx = make_ctx(mgx, m, prec)
+        ctx.set_populations(pops)
+        ctx.formal_solve()
+        assert ctx.counters()["masing"] == n_orc
+        ctx.update_populations()
+        assert ctx.counters()["masing"] == n_orc
+        ctx.set_populations(pops)
+        ctx.iterate(tol=1e-6, max_iter=1, raise_on_noconv=False)
+        assert ctx.counters()["masing"] == n_orc
+
+
 def oracle_step_residual(model, pops, count=48, seed=98):
     """max relative change of the oracle's own Lambda-iteration step (formal
     solution + statistical equilibrium) from `pops`, at sampled points."""
@@ -620,9 +644,15 @@ def test_converged_clumpy_full_fp32_bulk_oracle_step(mgx, clumpy):
     ctx.set_lte_populations()
     it, ch, ok = ctx.iterate(tol=1e-6, max_iter=300, ng_mode=mgx.NG_CLASSICAL, ng_param=4)
     assert ok
-    r = oracle_step_residual(clumpy, ctx.get_populations())
-    say(f"  clumpy converged FP32-bulk: {it} iterations, oracle step {r:.3e}")
+    pops = ctx.get_populations()
+    r = oracle_step_residual(clumpy, pops)
+    # the J=1-0 line is inverted (clamped) at about half the points
+    n_mas = ctx.counters()["masing"]
+    inv = int(np.sum(pops[:, 1] / clumpy.g[1] > pops[:, 0] / clumpy.g[0]))
+    say(f"  clumpy converged FP32-bulk: {it} iterations, oracle step {r:.3e}, masing clamps "
+        f"{n_mas}, inverted J=1-0 at {inv} points")
     assert r < 1e-4
+    assert n_mas > 0.3 * clumpy.npoints and abs(n_mas - inv) < 0.01 * inv
 
 
 # ---------------------------------------------------------------------------
