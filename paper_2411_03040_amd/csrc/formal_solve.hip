@@ -63,6 +63,7 @@ struct FM<float> {
         return __builtin_amdgcn_exp2f(fmaf(-xs, xs, lchi));
     }
     static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+    static __device__ __forceinline__ float rcp_ge1(float x) { return __builtin_amdgcn_rcpf(x); }
     // erfc for x >= 0, branch-free, in the product form of Numerical Recipes
     // (Press et al., 2nd ed., Sec. 6.2),
     //   erfc(x) = t exp(-x^2 + P(t)),  t = 1 / (1 + p x),
@@ -79,6 +80,9 @@ struct FM<float> {
     // see erf_scale), P is fitted to log2(erfc(x) / t) + xs^2 directly and
     // p is divided by sqrt(log2 e).
     static constexpr float erf_scale = 1.2011224f;  // sqrt(log2 e)
+    // erfc_scaled(xs) is exactly 0 for xs >= this: the exponent -xs^2 + P(t)
+    // is then below -157, past the smallest float (2^-149)
+    static constexpr float erfc_zero = 12.5f;
     static __device__ __forceinline__ float erfc_scaled(float xs)
     {
         const float t = __builtin_amdgcn_rcpf(fmaf(xs, 0.51618386f, 1.0f));
@@ -115,8 +119,52 @@ struct FM<double> {
         return chi * exp(-(x * x));
     }
     static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+    // 1 / x for x >= 1 (finite or +inf): the hardware estimate refined by two
+    // Newton steps (within an ulp; the argument range rules out the
+    // operands IEEE division guards against)
+    static __device__ __forceinline__ double rcp_ge1(double x)
+    {
+        double r = __builtin_amdgcn_rcp(x);
+        r = fma(r, fma(-x, r, 1.0), r);
+        r = fma(r, fma(-x, r, 1.0), r);
+        return isinf(x) ? 0.0 : r;
+    }
     static constexpr double erf_scale = 1.0;
-    static __device__ __forceinline__ double erfc_scaled(double x) { return erfc(x); }
+    // erfc for x >= 0, branch-free: the product form erfc(x) = t exp(P(t) -
+    // x^2), t = 1 / (1 + x / 2), with a degree-20 P fitted at 50 digits for
+    // x in [0, 26.5] (fit_erfc.py --fp64 reproduces it); the double
+    // evaluation is within 8e-14 of erfc there, the rounding of x^2 dominating
+    // near the top of the range.  (The library erfc branches by argument
+    // range, which diverges across the bins of a wave.)
+    static __device__ __forceinline__ double erfc_scaled(double x)
+    {
+        const double t = rcp_ge1(fma(x, 0.5, 1.0));
+        double p = -0.016239501604125413;
+        p = fma(p, t, 0.39759805519212382);
+        p = fma(p, t, -3.2793542009084606);
+        p = fma(p, t, 14.598535839604947);
+        p = fma(p, t, -41.377983391993126);
+        p = fma(p, t, 80.68994480295521);
+        p = fma(p, t, -112.65882633664431);
+        p = fma(p, t, 115.01700588295229);
+        p = fma(p, t, -87.126719461560256);
+        p = fma(p, t, 50.058971529304863);
+        p = fma(p, t, -22.629240549741915);
+        p = fma(p, t, 8.0951282183331497);
+        p = fma(p, t, -2.0788523994433934);
+        p = fma(p, t, 0.51027472396717621);
+        p = fma(p, t, -0.17288954588737776);
+        p = fma(p, t, -0.13329972931773915);
+        p = fma(p, t, -0.086941180427807283);
+        p = fma(p, t, 0.083402493085032281);
+        p = fma(p, t, 0.37499678709769213);
+        p = fma(p, t, 1.0000000896502224);
+        p = fma(p, t, -1.2655121246141809);
+        return t * exp(fma(-x, x, p));
+    }
+    // erfc_scaled(x) is exactly 0 for x >= this: exp(-x^2 + P) < exp(-756),
+    // below the smallest double (4.9e-324)
+    static constexpr double erfc_zero = 27.5;
     static __device__ __forceinline__ double expm1_(double x) { return expm1(x); }
     static __device__ __forceinline__ double at_least(double x, double lo)
     {
@@ -125,16 +173,33 @@ struct FM<double> {
 };
 
 // erf(b) - erf(a) from ea = erfc(|a|) and eb = erfc(|b|) (arguments scaled
-// by erf_scale), without cancellation for arguments of equal sign (the
-// semi-analytic branch guarantees |b - a| is at least about the branch
-// threshold, so the opposite-sign form 2 - erfc - erfc never cancels either).
+// by erf_scale): with sa, sb = +-1 the signs of a and b (of their sign bits,
+// so -0 counts as negative), erf(x) = s (1 - erfc|x|) gives
+//   erf(b) - erf(a) = (sb - sa) + sa ea - sb eb,
+// i.e. +-(ea - eb) for equal signs -- no cancellation in the wings -- and
+// +-((2 - ea) - eb) for opposite signs (the semi-analytic branch guarantees
+// |b - a| is at least about the branch threshold, so that never cancels
+// either).  Two multiply-adds, the same for every lane: no divergent branch
+// (the sign-dependent forms measured 3 % slower on the clumpy cloud).
 template <typename T>
 __device__ __forceinline__ T erf_diff(T a, T b, T ea, T eb)
 {
-    if (a >= (T)0 && b >= (T)0) return ea - eb;
-    if (a <= (T)0 && b <= (T)0) return eb - ea;
-    const T t = (T)2 - ea - eb;
-    return (b > a) ? t : -t;
+    const T sa = copysign((T)1, a), sb = copysign((T)1, b);
+    return fma(-sb, eb, fma(sa, ea, sb - sa));
+}
+
+// True when, on every lane of the wave, both ends of a semi-analytic
+// segment lie in the same far wing, where erfc is exactly zero in T: the erf
+// difference is then exactly 0 and the optical depth the floor, so the two
+// erfc evaluations can be skipped without changing a bit.  (The bins of a
+// wave share their offset from the line in widths up to x_f, so far out
+// along a ray with a large velocity difference the whole wave is there.)
+template <typename T>
+__device__ __forceinline__ bool far_wing(T a, T b)
+{
+    const T lim = FM<T>::erfc_zero;
+    const bool far = (a >= lim && b >= lim) || (a <= -lim && b <= -lim);
+    return __all(far);
 }
 
 // Per staged record: meta A (dv, 1/b scaled for the profile, a quarter of
@@ -214,10 +279,11 @@ __device__ __forceinline__ Rec<double> load_stream(gptr<Rec<double>> p)
 
 template <typename T>
 struct HalfState {
-    T G, eps, hm;      // elimination state: 2g, eps, half the previous depth
-    T chi, S, u, cb;   // previous point: opacity, source, xb + dv k1, chi'*b
-    T qdx, sibb, rw;   // segment data stored with the previous record
-    T ec;              // erfc(|u sibb|) of the previous point, if ec_ok
+    T G, eps, hm;         // elimination state: 2g, eps, half the previous depth
+    T lchi, ib, S, u, cb; // previous point: chi' (chi_phi's form), profile scale,
+                          // source, xb + dv k1, chi'*b
+    T qdx, sibb, rw;      // segment data stored with the previous record
+    T ec;                 // erfc(|u sibb|) of the previous point, if ec_ok
     bool ec_ok;
 };
 
@@ -273,7 +339,8 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
     const T inv_k1 = (T)(1.0 / (1.0 + xbd / kC));
     const T acmb = (T)acmb_l[l];
     const int64_t ol = (int64_t)o * nl + l;
-    const T chi_o = chi[ol] * (T)exp(-xfd * xfd);
+    const T lchi_o = FM<T>::log_scale(chi[ol]);
+    const T ib_o = ibpt[o];
     const T S_o = S[ol];
     const T cb_o = chi[ol] * bpt[o];
     const T half_floor = (T)(0.5 * a.tau_floor);
@@ -289,7 +356,7 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
     auto row = [&](HalfState<T> &st, T h) {
         const T D = st.hm + h;
         const T q2 = D * (T)2 + st.G;
-        const T inv = FM<T>::rcp((T)1 + q2 * h);
+        const T inv = FM<T>::rcp_ge1((T)1 + q2 * h);
         st.G = q2 * inv;
         st.eps = (D * st.S + st.eps) * inv;
         st.hm = h;
@@ -307,22 +374,33 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
     // is kept (ec) and not evaluated twice.  (A template parameter, not a
     // run-time test: the bookkeeping measured 9 % slower where it never
     // applies.)
-    auto segment = [&](HalfState<T> &st, T chiQ, T uQ, T cbQ) -> T {
+    // The profile chi' exp(-x^2) at the two ends is formed only by a
+    // trapezoidal segment (the semi-analytic form does not use it).  In a
+    // model with more than one width, a semi-analytic segment whose ends lie
+    // in the same far wing for the whole wave skips its erfc pair
+    // (far_wing: exact).
+    auto segment = [&](HalfState<T> &st, T lchiQ, T ibQ, T uQ, T cbQ) -> T {
         T h;
         if (signbit(st.qdx)) {
             const T xP = st.u * st.sibb;
             const T xQ = uQ * st.sibb;
-            T eP;
-            if (ONE_WIDTH && st.ec_ok)
-                eP = st.ec;
-            else
-                eP = FM<T>::erfc_scaled(fabs(xP));
-            const T eQ = FM<T>::erfc_scaled(fabs(xQ));
-            h = (st.cb + cbQ) * erf_diff<T>(xP, xQ, eP, eQ) * (st.rw * inv_k1);
-            st.ec = eQ;
+            if (!ONE_WIDTH && far_wing(xP, xQ)) {
+                h = (T)0;
+            } else {
+                T eP;
+                if (ONE_WIDTH && st.ec_ok)
+                    eP = st.ec;
+                else
+                    eP = FM<T>::erfc_scaled(fabs(xP));
+                const T eQ = FM<T>::erfc_scaled(fabs(xQ));
+                h = (st.cb + cbQ) * erf_diff<T>(xP, xQ, eP, eQ) * (st.rw * inv_k1);
+                st.ec = eQ;
+            }
             st.ec_ok = ONE_WIDTH;
         } else {
-            h = st.qdx * (st.chi + chiQ);
+            const T chiP = FM<T>::chi_phi(st.lchi, st.u * st.ib);
+            const T chiQ = FM<T>::chi_phi(lchiQ, uQ * ibQ);
+            h = st.qdx * (chiP + chiQ);
             st.ec_ok = false;
         }
         return FM<T>::at_least(h, half_floor);
@@ -345,28 +423,25 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
         A.G = B.G = (T)2;
         A.hm = B.hm = (T)0;
         A.eps = B.eps = bdy_I((T)0);  // replaced at the far end of a non-empty half
-        A.chi = A.S = A.u = A.cb = A.qdx = A.sibb = A.rw = A.ec = (T)0;
-        B.chi = B.S = B.u = B.cb = B.qdx = B.sibb = B.rw = B.ec = (T)0;
+        A.lchi = A.ib = A.S = A.u = A.cb = A.qdx = A.sibb = A.rw = A.ec = (T)0;
+        B.lchi = B.ib = B.S = B.u = B.cb = B.qdx = B.sibb = B.rw = B.ec = (T)0;
         A.ec_ok = B.ec_ok = false;
 
-        // point Q (staged record e) of a half: its profile, then either the
-        // far-end boundary intensity or one elimination row
+        // point Q (staged record e) of a half: either the far-end boundary
+        // intensity or one elimination row
         auto visit = [&](HalfState<T> &s, const MetaA<T> *pa, const LineRec<T> *pl,
                          bool far_end) {
             const MetaA<T> ma = *pa;
             const LineRec<T> lr = *pl;
             const T dvQ = ma.dv;
             const T uQ = xb + dvQ * k1;
-            // (the profile is evaluated even where both segments at Q are
-            // semi-analytic and never read it: a branch around it measured
-            // 12 % slower)
-            const T chiQ = FM<T>::chi_phi(lr.lchi, uQ * ma.ib);
             if (far_end) {
                 s.eps = bdy_I(dvQ);
                 s.ec_ok = false;
             } else
-                row(s, segment(s, chiQ, uQ, lr.cb));
-            s.chi = chiQ;
+                row(s, segment(s, lr.lchi, ma.ib, uQ, lr.cb));
+            s.lchi = lr.lchi;
+            s.ib = ma.ib;
             s.S = lr.S;
             s.u = uQ;
             s.cb = lr.cb;
@@ -452,8 +527,8 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
             }
         }
         // last segment of each non-empty half ends at the origin
-        if (nA > 0) row(A, segment(A, chi_o, xb, cb_o));
-        if (nB > 0) row(B, segment(B, chi_o, xb, cb_o));
+        if (nA > 0) row(A, segment(A, lchi_o, ib_o, xb, cb_o));
+        if (nB > 0) row(B, segment(B, lchi_o, ib_o, xb, cb_o));
         // combine in the order minus, plus
         const HalfState<T> &Hm = a_minus ? A : B, &Hp = a_minus ? B : A;
         const T Do = Hm.hm + Hp.hm;
