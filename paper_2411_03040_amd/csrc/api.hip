@@ -608,19 +608,20 @@ void mgxh::run_line_coeffs(mgx_ctx *ctx)
 }
 
 // Launch shape of a formal solution: lines per chunk (balanced) and threads
-// per workgroup (a multiple of 64 covering nlc * nbins).  The chunk is also
-// capped so that the LDS staging at the smallest record chunk the launch
-// uses (8 records per half) stays within 64 KiB: with one bin per line a
-// workgroup would otherwise stage up to 1024 lines per record.
+// per workgroup (a multiple of 64 covering nlc * nbins).  The line chunk is
+// also capped so that the LDS staging of one record per half stays within
+// 64 KiB: with one bin per line a workgroup would otherwise stage up to 1024
+// lines per record.  *lds_out: the LDS of the record chunk the launch picks.
 void mgxh::fs_shape(size_t tsize, int nlines, int nbins, int *nlc_out, int *nthreads_out,
                     size_t *lds_out)
 {
     const int max_threads = (tsize == 8 && nbins <= 512) ? 512 : kMaxBins;
     auto threads = [nbins](int nlc) { return ((nlc * nbins + 63) / 64) * 64; };
-    auto lds = [tsize, &threads](int nlc) {
-        return tsize == 8 ? formal_solve_lds<double>(8, nlc, threads(nlc))
-                          : formal_solve_lds<float>(8, nlc, threads(nlc));
+    auto lds_at = [tsize, nbins, &threads](int ch, int nlc) {
+        return tsize == 8 ? formal_solve_lds<double>(ch, nlc, nbins, threads(nlc))
+                          : formal_solve_lds<float>(ch, nlc, nbins, threads(nlc));
     };
+    auto lds = [&lds_at](int nlc) { return lds_at(1, nlc); };
     int nlc = std::max(1, max_threads / nbins);
     if (nlc > nlines) nlc = nlines;
     while (nlc > 1 && lds(nlc) > 64 * 1024) nlc--;
@@ -629,7 +630,9 @@ void mgxh::fs_shape(size_t tsize, int nlines, int nbins, int *nlc_out, int *nthr
     nlc = (nlines + nchunks - 1) / nchunks;
     *nlc_out = nlc;
     *nthreads_out = threads(nlc);
-    *lds_out = lds(nlc);
+    const int ch = tsize == 8 ? formal_solve_chunk<double>(nlc, nbins, threads(nlc))
+                              : formal_solve_chunk<float>(nlc, nbins, threads(nlc));
+    *lds_out = lds_at(ch, nlc);
 }
 
 extern "C" mgx_status mgx_formal_solve_shape(int precision, int nlines, int nbins,

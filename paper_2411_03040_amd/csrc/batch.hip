@@ -102,6 +102,7 @@ static void batch_build_tables(mgx_batch *b)
     for (int k = 0; k < MGX_BATCH_CLASSES; k++) {
         b->class_threads[k] = 64 * (k + 1);
         b->class_nlc_max[k] = 0;
+        b->class_nb_max[k] = 0;
         b->class_ch[k] = 64;
     }
     for (int i = 0; i < M; i++) {
@@ -110,6 +111,7 @@ static void batch_build_tables(mgx_batch *b)
         // a model's workgroup size is a multiple of 64 up to 1024
         const int k = d[i].nthreads / 64 - 1;
         b->class_nlc_max[k] = std::max(b->class_nlc_max[k], d[i].nlc);
+        b->class_nb_max[k] = std::max(b->class_nb_max[k], d[i].nbins);
         cost.ensure(sizeof(int64_t) * c->N);
         HIPCHK(launch_origin_cost(c->N, c->R, c->offsets.as<int64_t>(), cost.as<int64_t>(),
                                   b->stream));
@@ -242,7 +244,8 @@ template <typename T>
 static void batch_launch_class(mgx_batch *b, int k, const int4 *items, const int *count,
                                int blocks, const int *active, int ch)
 {
-    const size_t lds = formal_solve_lds<T>(ch, b->class_nlc_max[k], b->class_threads[k]);
+    const size_t lds = formal_solve_lds<T>(ch, b->class_nlc_max[k], b->class_nb_max[k],
+                                           b->class_threads[k]);
     HIPCHK(launch_formal_solve_batch<T>((const FSArgs<T> *)b->descs.p, items, count, blocks,
                                         active, ch, b->class_threads[k], lds, b->stream));
 }
@@ -257,18 +260,18 @@ static void batch_tune(mgx_batch *b)
         const int n = b->class_nitems[k];
         if (n == 0) continue;
         const int nlc = b->class_nlc_max[k], nth = b->class_threads[k];
-        // the largest chunk that fits 60 KB (at least 8, as the single-model
-        // launch does) and every smaller candidate
-        int chmax = 64;
-        while (formal_solve_lds<T>(chmax, nlc, nth) > 60 * 1024 && chmax > 8) chmax /= 2;
-        REQUIRE(formal_solve_lds<T>(chmax, nlc, nth) <= 160 * 1024, MGX_EINVAL,
+        const int nbm = b->class_nb_max[k];
+        // the largest chunk that fits 60 KB (as the single-model launch
+        // picks it) and the two below it
+        const int chmax = formal_solve_chunk<T>(nlc, nbm, nth);
+        REQUIRE(formal_solve_lds<T>(chmax, nlc, nbm, nth) <= 160 * 1024, MGX_EINVAL,
                 "line chunk does not fit the LDS");
         const int ns = b->class_nsample[k];
         HIPCHK(hipMemcpyAsync(b->tune_count.p, &ns, sizeof(int), hipMemcpyHostToDevice,
                               b->stream));
         float best = INFINITY;
-        for (int ch : {8, 16, 32, 64}) {
-            if (ch > chmax || (ch == 8 && chmax > 8)) continue;
+        for (int ch : {1, 2, 4, 8, 16, 32, 64}) {
+            if (ch > chmax || ch * 4 < chmax) continue;
             HIPCHK(hipEventRecord(b->ev0, b->stream));
             batch_launch_class<T>(b, k, b->sample[k].as<int4>(), b->tune_count.as<int>(), ns,
                                   b->all_active.as<int>(), ch);

@@ -56,11 +56,13 @@ struct FM;
 template <>
 struct FM<float> {
     // chi' exp(-x^2) as exp2(log2 chi' - xs^2), xs = x sqrt(log2 e): the
-    // staged line record carries log2 chi'
+    // staged line record carries log2 chi', the staged (point, bin) record
+    // the profile's exponent -xs^2
     static __device__ __forceinline__ float log_scale(float chi) { return __builtin_amdgcn_logf(chi); }
-    static __device__ __forceinline__ float chi_phi(float lchi, float xs)
+    static __device__ __forceinline__ float ns_of(float xs) { return -(xs * xs); }
+    static __device__ __forceinline__ float chi_ns(float lchi, float ns)
     {
-        return __builtin_amdgcn_exp2f(fmaf(-xs, xs, lchi));
+        return __builtin_amdgcn_exp2f(lchi + ns);
     }
     static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
     static __device__ __forceinline__ float rcp_ge1(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -80,9 +82,6 @@ struct FM<float> {
     // see erf_scale), P is fitted to log2(erfc(x) / t) + xs^2 directly and
     // p is divided by sqrt(log2 e).
     static constexpr float erf_scale = 1.2011224f;  // sqrt(log2 e)
-    // erfc_scaled(xs) is exactly 0 for xs >= this: the exponent -xs^2 + P(t)
-    // is then below -157, past the smallest float (2^-149)
-    static constexpr float erfc_zero = 12.5f;
     static __device__ __forceinline__ float erfc_scaled(float xs)
     {
         const float t = __builtin_amdgcn_rcpf(fmaf(xs, 0.51618386f, 1.0f));
@@ -114,10 +113,8 @@ struct FM<float> {
 template <>
 struct FM<double> {
     static __device__ __forceinline__ double log_scale(double chi) { return chi; }
-    static __device__ __forceinline__ double chi_phi(double chi, double x)
-    {
-        return chi * exp(-(x * x));
-    }
+    static __device__ __forceinline__ double ns_of(double x) { return -(x * x); }
+    static __device__ __forceinline__ double chi_ns(double chi, double ns) { return chi * exp(ns); }
     static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
     // 1 / x for x >= 1 (finite or +inf): the hardware estimate refined by two
     // Newton steps (within an ulp; the argument range rules out the
@@ -162,9 +159,7 @@ struct FM<double> {
         p = fma(p, t, -1.2655121246141809);
         return t * exp(fma(-x, x, p));
     }
-    // erfc_scaled(x) is exactly 0 for x >= this: exp(-x^2 + P) < exp(-756),
-    // below the smallest double (4.9e-324)
-    static constexpr double erfc_zero = 27.5;
+
     static __device__ __forceinline__ double expm1_(double x) { return expm1(x); }
     static __device__ __forceinline__ double at_least(double x, double lo)
     {
@@ -188,62 +183,76 @@ __device__ __forceinline__ T erf_diff(T a, T b, T ea, T eb)
     return fma(-sb, eb, fma(sa, ea, sb - sa));
 }
 
-// True when, on every lane of the wave, both ends of a semi-analytic
-// segment lie in the same far wing, where erfc is exactly zero in T: the erf
-// difference is then exactly 0 and the optical depth the floor, so the two
-// erfc evaluations can be skipped without changing a bit.  (The bins of a
-// wave share their offset from the line in widths up to x_f, so far out
-// along a ray with a large velocity difference the whole wave is there.)
+// LDS records.  The offset of a (point, bin) from the line centre is formed
+// in velocity units, x = (x_f b_o + dv + x_f b_o dv / c) / b, so it does not
+// depend on the line: the profile's exponent at a point and the
+// semi-analytic optical depth's erf difference are the same for every line
+// of the chunk.  The staging pass therefore computes them once per (record,
+// bin) and every line's lanes read them; only the per-point line data
+// (chi', S, chi' b) is staged per (record, line).
+//  * MetaA (per record, read by the sweep as a broadcast): dv (for the
+//    far-end boundary intensity) and a quarter of the length of the segment
+//    from this record towards the origin, or -1 when that segment takes the
+//    semi-analytic form.  (Quarters and halves: the sweep works with half
+//    optical depths.)
+//  * StageRec (per record, staging only): dv here and at the next record
+//    towards the origin (0 at the origin), 1/b (scaled for the profile),
+//    1/b-bar of the segment (times erf_scale), half the lane-independent
+//    factor dx sqrt(pi)/4 / (dv_Q - dv_P) of a semi-analytic segment (the
+//    trace computed it in FP64 and stored it in place of the length), b and
+//    the point index.
+//  * LineRec (per record and line): chi' in the form chi_ns takes (log2 chi'
+//    in FP32), S', chi' b (the semi-analytic segment's weight).
+//  * BinRec (per record and bin): the profile exponent -x^2 at the point (in
+//    the FP32 form, base 2) and, for a semi-analytic segment, its optical
+//    depth without the weight: (erf x_Q - erf x_P) times the factor above
+//    times 1/k1, so that dt/2 = (chi'b_P + chi'b_Q) * D.
+//  * BinConst (per bin, this origin): x_f b_o, k1 = 1 + x_f b_o / c, 1/k1.
 template <typename T>
-__device__ __forceinline__ bool far_wing(T a, T b)
-{
-    const T lim = FM<T>::erfc_zero;
-    const bool far = (a >= lim && b >= lim) || (a <= -lim && b <= -lim);
-    return __all(far);
-}
-
-// Per staged record: meta A (dv, 1/b scaled for the profile, a quarter of
-// the length of the segment ending here -- -1 when that segment takes the
-// semi-analytic form -- and its 1/b-bar times erf_scale), read by the solve
-// as one broadcast; meta B (b, point index, the semi-analytic factor below)
-// only feeds the line gather.  Per record and line of the chunk: chi' (in
-// the form chi_phi takes), S', chi' b (the semi-analytic segment's weight)
-// and, for a semi-analytic segment, half the lane-independent factor of its
-// optical depth, dx sqrt(pi)/4 / (dv_Q - dv_P), which the trace computed in
-// FP64 and stored in place of the segment length.  (Halves and quarters:
-// the solve works with half optical depths.)
-template <typename T>
-struct alignas(4 * sizeof(T)) MetaA {
-    T dv, ib, qdx, ibb;
+struct alignas(2 * sizeof(T)) MetaA {
+    T dv, qdx;
 };
 template <typename T>
-struct alignas(2 * sizeof(T)) MetaB {
-    T b;
-    int32_t p;
-    T rw;
+struct StageRec {
+    T dv, dvm, ib, sibb, rw, b;
+    int32_t p, semi;
 };
 template <typename T>
 struct alignas(4 * sizeof(T)) LineRec {
-    T lchi, S, cb, rw;  // lchi: chi' in the form FM::chi_phi takes (log2 chi' in FP32)
+    T lchi, S, cb, pad;
+};
+template <typename T>
+struct alignas(2 * sizeof(T)) BinRec {
+    T ns, D;
+};
+template <typename T>
+struct alignas(4 * sizeof(T)) BinConst {
+    T xb, k1, ik1, pad;
 };
 
 struct LDSLayout {
     int ch;
-    size_t a, b, line, total;
+    size_t bc, st, a, line, bin, total;
 };
 
+// Every section's size is a multiple of 16 bytes, so each starts aligned.
 template <typename T>
-__host__ __device__ inline LDSLayout lds_layout(int ch, int nlc, int nthreads)
+__host__ __device__ inline LDSLayout lds_layout(int ch, int nlc, int nb, int nthreads)
 {
     LDSLayout L;
     L.ch = ch;
     size_t o = 0;
+    L.bc = o;
+    o += sizeof(BinConst<T>) * nb;
+    L.st = o;
+    o += sizeof(StageRec<T>) * 2 * ch;
+    o = (o + 15) & ~(size_t)15;
     L.a = o;
     o += sizeof(MetaA<T>) * 2 * ch;
-    L.b = o;
-    o += sizeof(MetaB<T>) * 2 * ch;
     L.line = o;
     o += sizeof(LineRec<T>) * 2 * ch * nlc;
+    L.bin = o;
+    o += sizeof(BinRec<T>) * 2 * ch * nb;
     const size_t red = sizeof(double) * 2 * nthreads;
     L.total = o > red ? o : red;
     return L;
@@ -279,23 +288,24 @@ __device__ __forceinline__ Rec<double> load_stream(gptr<Rec<double>> p)
 
 template <typename T>
 struct HalfState {
-    T G, eps, hm;         // elimination state: 2g, eps, half the previous depth
-    T lchi, ib, S, u, cb; // previous point: chi' (chi_phi's form), profile scale,
-                          // source, xb + dv k1, chi'*b
-    T qdx, sibb, rw;      // segment data stored with the previous record
-    T ec;                 // erfc(|u sibb|) of the previous point, if ec_ok
-    bool ec_ok;
+    T G, eps, hm;       // elimination state: 2g, eps, half the previous depth
+    T lchi, ns, S, cb;  // previous point: chi' (chi_ns's form), profile exponent,
+                        // source, chi'*b
+    T qdx, D;           // segment from the previous point towards the origin:
+                        // quarter length (-1: semi-analytic) and its BinRec D
 };
 
 // Unrolling and occupancy, as measured: both sweep loops are unrolled twice
 // (no register copies between iterations), the longer half alone four times
-// in FP64.  Launches other than one-width models are held to 64 VGPRs in FP32
-// (eight waves per SIMD) and 128 in FP64 (four waves): a few bytes spill
-// outside the sweeps, and the extra waves hide more of the transcendental
-// and LDS latency than the spills cost.  One-width models keep their
-// registers (seven waves in FP32), which measured faster there than a cap.
+// in FP64.  FP32 launches other than one-width models are held to 64 VGPRs
+// (eight waves per SIMD): a few bytes spill outside the sweeps, and the
+// extra waves hide more latency than the spills cost (outflow 13.0 ms
+// against 14.5 uncapped); one-width models keep their 70 registers (seven
+// waves; capped: 149 ms against 134 on the clumpy cloud).  Every FP64 launch
+// is held to 128 VGPRs (four waves; the one-width kernel needs 146, three
+// waves: 865 ms against 601 capped on the clumpy cloud).
 template <typename T, bool ONE_WIDTH>
-constexpr int kWavesPerEu = ONE_WIDTH ? 1 : (sizeof(T) == 4 ? 8 : 4);
+constexpr int kWavesPerEu = sizeof(T) == 4 ? (ONE_WIDTH ? 1 : 8) : 4;
 
 // One origin x line chunk, executed by the whole workgroup (blockDim.x
 // threads, at least nlc * nbins).  Shared by the single-model launch and the
@@ -324,23 +334,35 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
     const gptr<T> chi = glob(a.chi), S = glob(a.S), bpt = glob(a.bpt), ibpt = glob(a.ibpt);
     const gptr_mut<double> Jout = glob_mut(a.J), Lout = glob_mut(a.L);
 
-    const LDSLayout LY = lds_layout<T>(ch, nlc, nth);
+    const LDSLayout LY = lds_layout<T>(ch, nlc, nb, nth);
+    BinConst<T> *s_bc = (BinConst<T> *)(smem + LY.bc);
+    StageRec<T> *s_st = (StageRec<T> *)(smem + LY.st);
     MetaA<T> *s_a = (MetaA<T> *)(smem + LY.a);
-    MetaB<T> *s_b = (MetaB<T> *)(smem + LY.b);
     LineRec<T> *s_line = (LineRec<T> *)(smem + LY.line);
+    BinRec<T> *s_bin = (BinRec<T> *)(smem + LY.bin);
+
+    // per-bin constants of this origin, for the staging pass
+    const double bo = b64[o];
+    for (int t = tid; t < nb; t += nth) {
+        const double xbt = xf[t] * bo;
+        BinConst<T> c;
+        c.xb = (T)xbt;
+        c.k1 = (T)(1.0 + xbt / kC);
+        c.ik1 = (T)(1.0 / (1.0 + xbt / kC));
+        c.pad = (T)0;
+        s_bc[t] = c;
+    }
 
     // per-lane constants
-    const double bo = b64[o];
     const double xfd = xf[f];
     const double xbd = xfd * bo;
     const T xb = (T)xbd;
     const T k1 = (T)(1.0 + xbd / kC);
     const T inv_c = (T)(1.0 / kC);
-    const T inv_k1 = (T)(1.0 / (1.0 + xbd / kC));
     const T acmb = (T)acmb_l[l];
     const int64_t ol = (int64_t)o * nl + l;
     const T lchi_o = FM<T>::log_scale(chi[ol]);
-    const T ib_o = ibpt[o];
+    const T ns_o = FM<T>::ns_of(xb * ibpt[o]);
     const T S_o = S[ol];
     const T cb_o = chi[ol] * bpt[o];
     const T half_floor = (T)(0.5 * a.tau_floor);
@@ -363,46 +385,20 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
     };
 
     // half the optical depth of the segment from the previous point of st
-    // (farther out) to Q, whose unscaled offset is uQ = xb + dvQ k1; qdx
-    // carries a quarter of the segment length.  Semi-analytic:
+    // (farther out) to Q.  Trapezoidal: a quarter of the length times the
+    // two ends' chi' exp(-x^2) (formed only here: a semi-analytic segment
+    // does not use the profile).  Semi-analytic:
     //   dt = dx sqrt(pi)/4 (cb_P + cb_Q) (erf x_Q - erf x_P) / (b-bar (x_Q - x_P))
     // with x = u / b-bar and x_Q - x_P = (dvQ - dvP) k1 / b-bar, so b-bar
-    // cancels outside the erf arguments; half of dx sqrt(pi)/4 / (dvQ - dvP)
-    // comes with the record (rw).  Floored at tau_floor / 2.  With one
-    // Doppler width everywhere every b-bar is the same number, so erfc at Q
-    // is also erfc at the near end of a following semi-analytic segment: it
-    // is kept (ec) and not evaluated twice.  (A template parameter, not a
-    // run-time test: the bookkeeping measured 9 % slower where it never
-    // applies.)
-    // The profile chi' exp(-x^2) at the two ends is formed only by a
-    // trapezoidal segment (the semi-analytic form does not use it).  In a
-    // model with more than one width, a semi-analytic segment whose ends lie
-    // in the same far wing for the whole wave skips its erfc pair
-    // (far_wing: exact).
-    auto segment = [&](HalfState<T> &st, T lchiQ, T ibQ, T uQ, T cbQ) -> T {
+    // cancels outside the erf arguments and everything but the weight
+    // cb_P + cb_Q is the staged BinRec D of the segment.  Floored at
+    // tau_floor / 2.
+    auto segment = [&](HalfState<T> &st, T lchiQ, T nsQ, T cbQ) -> T {
         T h;
-        if (signbit(st.qdx)) {
-            const T xP = st.u * st.sibb;
-            const T xQ = uQ * st.sibb;
-            if (!ONE_WIDTH && far_wing(xP, xQ)) {
-                h = (T)0;
-            } else {
-                T eP;
-                if (ONE_WIDTH && st.ec_ok)
-                    eP = st.ec;
-                else
-                    eP = FM<T>::erfc_scaled(fabs(xP));
-                const T eQ = FM<T>::erfc_scaled(fabs(xQ));
-                h = (st.cb + cbQ) * erf_diff<T>(xP, xQ, eP, eQ) * (st.rw * inv_k1);
-                st.ec = eQ;
-            }
-            st.ec_ok = ONE_WIDTH;
-        } else {
-            const T chiP = FM<T>::chi_phi(st.lchi, st.u * st.ib);
-            const T chiQ = FM<T>::chi_phi(lchiQ, uQ * ibQ);
-            h = st.qdx * (chiP + chiQ);
-            st.ec_ok = false;
-        }
+        if (signbit(st.qdx))
+            h = (st.cb + cbQ) * st.D;
+        else
+            h = st.qdx * (FM<T>::chi_ns(st.lchi, st.ns) + FM<T>::chi_ns(lchiQ, nsQ));
         return FM<T>::at_least(h, half_floor);
     };
 
@@ -423,31 +419,26 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
         A.G = B.G = (T)2;
         A.hm = B.hm = (T)0;
         A.eps = B.eps = bdy_I((T)0);  // replaced at the far end of a non-empty half
-        A.lchi = A.ib = A.S = A.u = A.cb = A.qdx = A.sibb = A.rw = A.ec = (T)0;
-        B.lchi = B.ib = B.S = B.u = B.cb = B.qdx = B.sibb = B.rw = B.ec = (T)0;
-        A.ec_ok = B.ec_ok = false;
+        A.lchi = A.ns = A.S = A.cb = A.qdx = A.D = (T)0;
+        B.lchi = B.ns = B.S = B.cb = B.qdx = B.D = (T)0;
 
         // point Q (staged record e) of a half: either the far-end boundary
         // intensity or one elimination row
         auto visit = [&](HalfState<T> &s, const MetaA<T> *pa, const LineRec<T> *pl,
-                         bool far_end) {
+                         const BinRec<T> *pn, bool far_end) {
             const MetaA<T> ma = *pa;
             const LineRec<T> lr = *pl;
-            const T dvQ = ma.dv;
-            const T uQ = xb + dvQ * k1;
-            if (far_end) {
-                s.eps = bdy_I(dvQ);
-                s.ec_ok = false;
-            } else
-                row(s, segment(s, lr.lchi, ma.ib, uQ, lr.cb));
+            const BinRec<T> br = *pn;
+            if (far_end)
+                s.eps = bdy_I(ma.dv);
+            else
+                row(s, segment(s, lr.lchi, br.ns, lr.cb));
             s.lchi = lr.lchi;
-            s.ib = ma.ib;
+            s.ns = br.ns;
             s.S = lr.S;
-            s.u = uQ;
             s.cb = lr.cb;
             s.qdx = ma.qdx;
-            s.sibb = ma.ibb;
-            s.rw = lr.rw;
+            s.D = br.D;
         };
 
         for (int hi = nA; hi > 0; hi -= ch) {
@@ -464,34 +455,59 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
                 const int64_t base = plus ? offp : offm;
                 const Rec<T> rc = load_stream(rec + base + k);
                 const int p = rc.ps & 0x7fffffff;
+                const bool semi = rc.ps < 0;
+                StageRec<T> sr;
+                sr.dv = rc.dv;
+                sr.dvm = k > 0 ? rec[base + k - 1].dv : (T)0;  // the origin's is 0
+                sr.ib = ibpt[p];
+                sr.sibb = rc.ibb * (T)FM<T>::erf_scale;
+                sr.rw = semi ? rc.dx * half : (T)0;
+                sr.b = bpt[p];
+                sr.p = p;
+                sr.semi = semi ? 1 : 0;
+                s_st[t] = sr;
                 MetaA<T> ma;
                 ma.dv = rc.dv;
-                ma.ib = ibpt[p];
                 // a quarter of the trapezoid's length, or -1 marking a
-                // semi-analytic segment (whose record carries its
-                // optical-depth factor)
-                ma.qdx = rc.ps < 0 ? (T)-1 : rc.dx * (T)0.25;
-                ma.ibb = rc.ibb * (T)FM<T>::erf_scale;
+                // semi-analytic segment
+                ma.qdx = semi ? (T)-1 : rc.dx * (T)0.25;
                 s_a[t] = ma;
-                MetaB<T> mb;
-                mb.b = bpt[p];
-                mb.p = p;
-                mb.rw = rc.ps < 0 ? rc.dx * half : (T)0;
-                s_b[t] = mb;
             }
             __syncthreads();
             for (int t = tid; t < cnt * nl_here; t += nth) {
                 const int e = t / nl_here;
                 const int li = t - e * nl_here;
-                const MetaB<T> mb = s_b[e];
-                const int64_t idx = (int64_t)mb.p * nl + l0 + li;
+                const StageRec<T> &sr = s_st[e];
+                const int64_t idx = (int64_t)sr.p * nl + l0 + li;
                 LineRec<T> lr;
                 const T chi_l = chi[idx];
                 lr.lchi = FM<T>::log_scale(chi_l);
                 lr.S = S[idx];
-                lr.cb = chi_l * mb.b;
-                lr.rw = mb.rw;
+                lr.cb = chi_l * sr.b;
+                lr.pad = (T)0;
                 s_line[e * nlc + li] = lr;
+            }
+            // per (record, bin): the profile exponent at the point and the
+            // semi-analytic segment's erf difference times its factor and 1/k1
+            // (x_P at this record, x_Q at the next one towards the origin)
+            for (int t = tid; t < cnt * nb; t += nth) {
+                const int e = t / nb;
+                const int fb = t - e * nb;
+                const StageRec<T> &sr = s_st[e];
+                const BinConst<T> bc = s_bc[fb];
+                const T uP = bc.xb + sr.dv * bc.k1;
+                BinRec<T> br;
+                br.ns = FM<T>::ns_of(uP * sr.ib);
+                br.D = (T)0;
+                if (sr.semi) {
+                    const T uQ = bc.xb + sr.dvm * bc.k1;
+                    const T xP = uP * sr.sibb;
+                    const T xQ = uQ * sr.sibb;
+                    const T eP = FM<T>::erfc_scaled(fabs(xP));
+                    const T eQ = FM<T>::erfc_scaled(fabs(xQ));
+                    br.D = erf_diff<T>(xP, xQ, eP, eQ) * (sr.rw * bc.ik1);
+                }
+                s_bin[e * nb + fb] = br;
             }
             __syncthreads();
             // record k of half A is staged at eA + k, of half B at eB + k
@@ -501,34 +517,39 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
             // LDS read takes its address as it is
             const MetaA<T> *pa = s_a + (eA + k);
             const LineRec<T> *la = s_line + (eA + k) * nlc + ll;
+            const BinRec<T> *na = s_bin + (eA + k) * nb + f;
             // records beyond the end of B: A alone (its far end first)
             if (k >= nB && k == nA - 1) {
-                visit(A, pa--, la, true);
+                visit(A, pa--, la, na, true);
                 la -= nlc;
+                na -= nb;
                 k--;
             }
             const int kAB = max(lo, nB);
-#pragma unroll (sizeof(T) == 8 ? 4 : 2)
-            for (; k >= kAB; k--, la -= nlc) visit(A, pa--, la, false);
+#pragma unroll(sizeof(T) == 8 ? 4 : 2)
+            for (; k >= kAB; k--, la -= nlc, na -= nb) visit(A, pa--, la, na, false);
             const MetaA<T> *pb = s_a + (eB + k);
             const LineRec<T> *lb = s_line + (eB + k) * nlc + ll;
+            const BinRec<T> *nbp = s_bin + (eB + k) * nb + f;
             // B's far end (A's too when the halves are equally long)
             if (k >= lo && k == nB - 1) {
-                visit(A, pa--, la, k == nA - 1);
-                visit(B, pb--, lb, true);
+                visit(A, pa--, la, na, k == nA - 1);
+                visit(B, pb--, lb, nbp, true);
                 la -= nlc;
                 lb -= nlc;
+                na -= nb;
+                nbp -= nb;
                 k--;
             }
 #pragma unroll 2
-            for (; k >= lo; k--, la -= nlc, lb -= nlc) {
-                visit(A, pa--, la, false);
-                visit(B, pb--, lb, false);
+            for (; k >= lo; k--, la -= nlc, lb -= nlc, na -= nb, nbp -= nb) {
+                visit(A, pa--, la, na, false);
+                visit(B, pb--, lb, nbp, false);
             }
         }
         // last segment of each non-empty half ends at the origin
-        if (nA > 0) row(A, segment(A, lchi_o, ib_o, xb, cb_o));
-        if (nB > 0) row(B, segment(B, lchi_o, ib_o, xb, cb_o));
+        if (nA > 0) row(A, segment(A, lchi_o, ns_o, cb_o));
+        if (nB > 0) row(B, segment(B, lchi_o, ns_o, cb_o));
         // combine in the order minus, plus
         const HalfState<T> &Hm = a_minus ? A : B, &Hp = a_minus ? B : A;
         const T Do = Hm.hm + Hp.hm;
@@ -604,12 +625,36 @@ void k_formal_solve_batch(const FSArgs<T> *__restrict__ descs, const int4 *__res
 }
 
 template <typename T>
-size_t formal_solve_lds(int ch, int nlc, int nthreads)
+size_t formal_solve_lds(int ch, int nlc, int nb, int nthreads)
 {
-    return lds_layout<T>(ch, nlc, nthreads).total;
+    return lds_layout<T>(ch, nlc, nb, nthreads).total;
 }
-template size_t formal_solve_lds<float>(int, int, int);
-template size_t formal_solve_lds<double>(int, int, int);
+template size_t formal_solve_lds<float>(int, int, int, int);
+template size_t formal_solve_lds<double>(int, int, int, int);
+
+// The LDS a workgroup may take so that enough workgroups fit on a CU (160
+// KiB of LDS) to fill the waves its registers allow (about 32 per CU in
+// FP32, 16 in FP64): small workgroups (5 waves for the outflow's 9 lines x 31
+// bins) then stage fewer records at a time instead of being held to two per
+// CU by their LDS; large ones keep 60 KiB.
+static size_t lds_budget(int nthreads, int target_waves)
+{
+    const int waves = (nthreads + 63) / 64;
+    const int wgs = (target_waves + waves - 1) / waves;
+    const size_t b = (size_t)160 * 1024 / wgs - 1024;
+    return b < (size_t)60 * 1024 ? b : (size_t)60 * 1024;
+}
+
+template <typename T>
+int formal_solve_chunk(int nlc, int nb, int nthreads)
+{
+    const size_t budget = lds_budget(nthreads, sizeof(T) == 4 ? 32 : 16);
+    int ch = 64;
+    while (lds_layout<T>(ch, nlc, nb, nthreads).total > budget && ch > 1) ch /= 2;
+    return ch;
+}
+template int formal_solve_chunk<float>(int, int, int);
+template int formal_solve_chunk<double>(int, int, int);
 
 template <typename T>
 hipError_t launch_formal_solve_batch(const FSArgs<T> *descs, const int4 *items, const int *count,
@@ -650,12 +695,8 @@ static void launch_fs_variant(const FSArgs<T> &a, dim3 grid, size_t lds, int ch,
 template <typename T>
 hipError_t launch_formal_solve(const FSArgs<T> &a, hipStream_t s)
 {
-    int ch = 64;
-    LDSLayout L = lds_layout<T>(ch, a.nlc, a.nthreads);
-    while (L.total > 60 * 1024 && ch > 8) {
-        ch /= 2;
-        L = lds_layout<T>(ch, a.nlc, a.nthreads);
-    }
+    const int ch = formal_solve_chunk<T>(a.nlc, a.nbins, a.nthreads);
+    const LDSLayout L = lds_layout<T>(ch, a.nlc, a.nbins, a.nthreads);
     const int nchunks = (a.nlines + a.nlc - 1) / a.nlc;
     dim3 grid(a.N, nchunks);
     // double keeps more state live per lane: a 512-thread bound leaves it 256

@@ -333,6 +333,7 @@ struct mgx_batch {
     int class_threads[MGX_BATCH_CLASSES] = {};
     int class_nitems[MGX_BATCH_CLASSES] = {};
     int class_nlc_max[MGX_BATCH_CLASSES] = {};
+    int class_nb_max[MGX_BATCH_CLASSES] = {};
     int class_ch[MGX_BATCH_CLASSES] = {};
     int64_t work_items = 0;
     std::vector<int> host_active;

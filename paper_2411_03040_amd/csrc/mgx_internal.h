@@ -160,7 +160,12 @@ template <typename T>
 hipError_t launch_formal_solve(const FSArgs<T> &a, hipStream_t s);
 // batched: one workgroup per (model, origin, line chunk) item of a lane class
 template <typename T>
-size_t formal_solve_lds(int ch, int nlc, int nthreads);
+size_t formal_solve_lds(int ch, int nlc, int nb, int nthreads);
+// records per half staged at once: the largest power of two <= 64 whose LDS
+// fits the workgroup's share of a CU (at most 60 KiB; down to 1 for very
+// wide bin sets)
+template <typename T>
+int formal_solve_chunk(int nlc, int nb, int nthreads);
 template <typename T>
 hipError_t launch_formal_solve_batch(const FSArgs<T> *descs, const int4 *items, const int *count,
                                      int blocks, const int *active, int ch, int nthreads,
