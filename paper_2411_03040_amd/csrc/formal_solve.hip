@@ -55,14 +55,11 @@ struct FM;
 
 template <>
 struct FM<float> {
-    // chi' exp(-x^2) as exp2(log2 chi' - xs^2), xs = x sqrt(log2 e): the
-    // staged line record carries log2 chi', the staged (point, bin) record
-    // the profile's exponent -xs^2
-    static __device__ __forceinline__ float log_scale(float chi) { return __builtin_amdgcn_logf(chi); }
-    static __device__ __forceinline__ float ns_of(float xs) { return -(xs * xs); }
-    static __device__ __forceinline__ float chi_ns(float lchi, float ns)
+    // the profile exp(-x^2) of a (point, bin) as exp2(-xs^2), xs = x sqrt(log2
+    // e) (the factor is folded into 1/b)
+    static __device__ __forceinline__ float phi_of(float xs)
     {
-        return __builtin_amdgcn_exp2f(lchi + ns);
+        return __builtin_amdgcn_exp2f(-(xs * xs));
     }
     static __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
     static __device__ __forceinline__ float rcp_ge1(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -112,9 +109,7 @@ struct FM<float> {
 
 template <>
 struct FM<double> {
-    static __device__ __forceinline__ double log_scale(double chi) { return chi; }
-    static __device__ __forceinline__ double ns_of(double x) { return -(x * x); }
-    static __device__ __forceinline__ double chi_ns(double chi, double ns) { return chi * exp(ns); }
+    static __device__ __forceinline__ double phi_of(double x) { return exp(-(x * x)); }
     static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
     // 1 / x for x >= 1 (finite or +inf): the hardware estimate refined by two
     // Newton steps (within an ulp; the argument range rules out the
@@ -190,27 +185,32 @@ __device__ __forceinline__ T erf_diff(T a, T b, T ea, T eb)
 // of the chunk.  The staging pass therefore computes them once per (record,
 // bin) and every line's lanes read them; only the per-point line data
 // (chi', S, chi' b) is staged per (record, line).
-//  * MetaA (per record, read by the sweep as a broadcast): dv (for the
-//    far-end boundary intensity) and a quarter of the length of the segment
-//    from this record towards the origin, or -1 when that segment takes the
-//    semi-analytic form.  (Quarters and halves: the sweep works with half
-//    optical depths.)
+//  * MetaA (per record): dv, read by the sweep only at a ray's far end (the
+//    boundary intensity's comoving frequency).
 //  * StageRec (per record, staging only): dv here and at the next record
 //    towards the origin (0 at the origin), 1/b (scaled for the profile),
 //    1/b-bar of the segment (times erf_scale), half the lane-independent
 //    factor dx sqrt(pi)/4 / (dv_Q - dv_P) of a semi-analytic segment (the
 //    trace computed it in FP64 and stored it in place of the length), b and
 //    the point index.
-//  * LineRec (per record and line): chi' in the form chi_ns takes (log2 chi'
-//    in FP32), S', chi' b (the semi-analytic segment's weight).
-//  * BinRec (per record and bin): the profile exponent -x^2 at the point (in
-//    the FP32 form, base 2) and, for a semi-analytic segment, its optical
-//    depth without the weight: (erf x_Q - erf x_P) times the factor above
-//    times 1/k1, so that dt/2 = (chi'b_P + chi'b_Q) * D.
+//  * LineRec (per record and line): chi', S', chi' b (the semi-analytic
+//    segment's weight).
+//  * BinRec (per record and bin): the profile exp(-x^2) at the point, and W
+//    for the segment from this record towards the origin: for a
+//    semi-analytic segment its optical depth without the weight, W = (erf x_Q
+//    - erf x_P) times the factor above times 1/k1 >= 0, so that dt/2 =
+//    (chi'b_P + chi'b_Q) W; for a trapezoidal one W = -(a quarter of its
+//    length) < 0, so that dt/2 = -W (chi'phi_P + chi'phi_Q).  The sign of W
+//    is the branch bit, the same on every lane of the record.  (A
+//    semi-analytic W of -0, from an erf difference that underflowed to zero,
+//    reads as a trapezoid of length 0: the same floored depth.)  In FP32 the
+//    profile underflows past ~10 widths, where chi' times it is far below
+//    the optical-depth floor.
+//  (Quarters and halves: the sweep works with half optical depths.)
 //  * BinConst (per bin, this origin): x_f b_o, k1 = 1 + x_f b_o / c, 1/k1.
 template <typename T>
-struct alignas(2 * sizeof(T)) MetaA {
-    T dv, qdx;
+struct MetaA {
+    T dv;
 };
 template <typename T>
 struct StageRec {
@@ -219,11 +219,11 @@ struct StageRec {
 };
 template <typename T>
 struct alignas(4 * sizeof(T)) LineRec {
-    T lchi, S, cb, pad;
+    T chi, S, cb, pad;
 };
 template <typename T>
 struct alignas(2 * sizeof(T)) BinRec {
-    T ns, D;
+    T phi, W;
 };
 template <typename T>
 struct alignas(4 * sizeof(T)) BinConst {
@@ -289,10 +289,9 @@ __device__ __forceinline__ Rec<double> load_stream(gptr<Rec<double>> p)
 template <typename T>
 struct HalfState {
     T G, eps, hm;       // elimination state: 2g, eps, half the previous depth
-    T lchi, ns, S, cb;  // previous point: chi' (chi_ns's form), profile exponent,
-                        // source, chi'*b
-    T qdx, D;           // segment from the previous point towards the origin:
-                        // quarter length (-1: semi-analytic) and its BinRec D
+    T chi, phi, S, cb;  // previous point: chi', profile, source, chi'*b
+    T W;                // segment from the previous point towards the origin:
+                        // its BinRec W
 };
 
 // Unrolling and occupancy, as measured: both sweep loops are unrolled twice
@@ -361,8 +360,8 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
     const T inv_c = (T)(1.0 / kC);
     const T acmb = (T)acmb_l[l];
     const int64_t ol = (int64_t)o * nl + l;
-    const T lchi_o = FM<T>::log_scale(chi[ol]);
-    const T ns_o = FM<T>::ns_of(xb * ibpt[o]);
+    const T chi_o = chi[ol];
+    const T phi_o = FM<T>::phi_of(xb * ibpt[o]);
     const T S_o = S[ol];
     const T cb_o = chi[ol] * bpt[o];
     const T half_floor = (T)(0.5 * a.tau_floor);
@@ -386,19 +385,18 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
 
     // half the optical depth of the segment from the previous point of st
     // (farther out) to Q.  Trapezoidal: a quarter of the length times the
-    // two ends' chi' exp(-x^2) (formed only here: a semi-analytic segment
-    // does not use the profile).  Semi-analytic:
+    // two ends' chi' exp(-x^2).  Semi-analytic:
     //   dt = dx sqrt(pi)/4 (cb_P + cb_Q) (erf x_Q - erf x_P) / (b-bar (x_Q - x_P))
     // with x = u / b-bar and x_Q - x_P = (dvQ - dvP) k1 / b-bar, so b-bar
     // cancels outside the erf arguments and everything but the weight
-    // cb_P + cb_Q is the staged BinRec D of the segment.  Floored at
+    // cb_P + cb_Q is the staged BinRec W of the segment.  Floored at
     // tau_floor / 2.
-    auto segment = [&](HalfState<T> &st, T lchiQ, T nsQ, T cbQ) -> T {
+    auto segment = [&](HalfState<T> &st, T chiQ, T phiQ, T cbQ) -> T {
         T h;
-        if (signbit(st.qdx))
-            h = (st.cb + cbQ) * st.D;
+        if (signbit(st.W))
+            h = st.W * -(st.chi * st.phi + chiQ * phiQ);
         else
-            h = st.qdx * (FM<T>::chi_ns(st.lchi, st.ns) + FM<T>::chi_ns(lchiQ, nsQ));
+            h = (st.cb + cbQ) * st.W;
         return FM<T>::at_least(h, half_floor);
     };
 
@@ -419,26 +417,24 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
         A.G = B.G = (T)2;
         A.hm = B.hm = (T)0;
         A.eps = B.eps = bdy_I((T)0);  // replaced at the far end of a non-empty half
-        A.lchi = A.ns = A.S = A.cb = A.qdx = A.D = (T)0;
-        B.lchi = B.ns = B.S = B.cb = B.qdx = B.D = (T)0;
+        A.chi = A.phi = A.S = A.cb = A.W = (T)0;
+        B.chi = B.phi = B.S = B.cb = B.W = (T)0;
 
         // point Q (staged record e) of a half: either the far-end boundary
         // intensity or one elimination row
         auto visit = [&](HalfState<T> &s, const MetaA<T> *pa, const LineRec<T> *pl,
                          const BinRec<T> *pn, bool far_end) {
-            const MetaA<T> ma = *pa;
             const LineRec<T> lr = *pl;
             const BinRec<T> br = *pn;
             if (far_end)
-                s.eps = bdy_I(ma.dv);
+                s.eps = bdy_I(pa->dv);
             else
-                row(s, segment(s, lr.lchi, br.ns, lr.cb));
-            s.lchi = lr.lchi;
-            s.ns = br.ns;
+                row(s, segment(s, lr.chi, br.phi, lr.cb));
+            s.chi = lr.chi;
+            s.phi = br.phi;
             s.S = lr.S;
             s.cb = lr.cb;
-            s.qdx = ma.qdx;
-            s.D = br.D;
+            s.W = br.W;
         };
 
         for (int hi = nA; hi > 0; hi -= ch) {
@@ -461,16 +457,15 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
                 sr.dvm = k > 0 ? rec[base + k - 1].dv : (T)0;  // the origin's is 0
                 sr.ib = ibpt[p];
                 sr.sibb = rc.ibb * (T)FM<T>::erf_scale;
-                sr.rw = semi ? rc.dx * half : (T)0;
+                // semi-analytic: half its lane-independent factor; trapezoidal:
+                // minus a quarter of its length
+                sr.rw = semi ? rc.dx * half : rc.dx * (T)-0.25;
                 sr.b = bpt[p];
                 sr.p = p;
                 sr.semi = semi ? 1 : 0;
                 s_st[t] = sr;
                 MetaA<T> ma;
                 ma.dv = rc.dv;
-                // a quarter of the trapezoid's length, or -1 marking a
-                // semi-analytic segment
-                ma.qdx = semi ? (T)-1 : rc.dx * (T)0.25;
                 s_a[t] = ma;
             }
             __syncthreads();
@@ -481,15 +476,15 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
                 const int64_t idx = (int64_t)sr.p * nl + l0 + li;
                 LineRec<T> lr;
                 const T chi_l = chi[idx];
-                lr.lchi = FM<T>::log_scale(chi_l);
+                lr.chi = chi_l;
                 lr.S = S[idx];
                 lr.cb = chi_l * sr.b;
                 lr.pad = (T)0;
                 s_line[e * nlc + li] = lr;
             }
-            // per (record, bin): the profile exponent at the point and the
-            // semi-analytic segment's erf difference times its factor and 1/k1
-            // (x_P at this record, x_Q at the next one towards the origin)
+            // per (record, bin): the profile at the point and W of the segment
+            // towards the origin (semi-analytic: the erf difference, x_P at
+            // this record and x_Q at the next one, times its factor and 1/k1)
             for (int t = tid; t < cnt * nb; t += nth) {
                 const int e = t / nb;
                 const int fb = t - e * nb;
@@ -497,15 +492,15 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
                 const BinConst<T> bc = s_bc[fb];
                 const T uP = bc.xb + sr.dv * bc.k1;
                 BinRec<T> br;
-                br.ns = FM<T>::ns_of(uP * sr.ib);
-                br.D = (T)0;
+                br.phi = FM<T>::phi_of(uP * sr.ib);
+                br.W = sr.rw;
                 if (sr.semi) {
                     const T uQ = bc.xb + sr.dvm * bc.k1;
                     const T xP = uP * sr.sibb;
                     const T xQ = uQ * sr.sibb;
                     const T eP = FM<T>::erfc_scaled(fabs(xP));
                     const T eQ = FM<T>::erfc_scaled(fabs(xQ));
-                    br.D = erf_diff<T>(xP, xQ, eP, eQ) * (sr.rw * bc.ik1);
+                    br.W = erf_diff<T>(xP, xQ, eP, eQ) * (sr.rw * bc.ik1);
                 }
                 s_bin[e * nb + fb] = br;
             }
@@ -548,8 +543,8 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
             }
         }
         // last segment of each non-empty half ends at the origin
-        if (nA > 0) row(A, segment(A, lchi_o, ns_o, cb_o));
-        if (nB > 0) row(B, segment(B, lchi_o, ns_o, cb_o));
+        if (nA > 0) row(A, segment(A, chi_o, phi_o, cb_o));
+        if (nB > 0) row(B, segment(B, chi_o, phi_o, cb_o));
         // combine in the order minus, plus
         const HalfState<T> &Hm = a_minus ? A : B, &Hp = a_minus ? B : A;
         const T Do = Hm.hm + Hp.hm;
