@@ -261,8 +261,8 @@ static void batch_tune(mgx_batch *b)
         if (n == 0) continue;
         const int nlc = b->class_nlc_max[k], nth = b->class_threads[k];
         const int nbm = b->class_nb_max[k];
-        // the largest chunk that fits 60 KB (as the single-model launch
-        // picks it) and the two below it
+        // the largest chunk the LDS budget allows (as the single-model
+        // launch picks it), half and a quarter of it
         const int chmax = formal_solve_chunk<T>(nlc, nbm, nth);
         REQUIRE(formal_solve_lds<T>(chmax, nlc, nbm, nth) <= 160 * 1024, MGX_EINVAL,
                 "line chunk does not fit the LDS");
@@ -270,8 +270,11 @@ static void batch_tune(mgx_batch *b)
         HIPCHK(hipMemcpyAsync(b->tune_count.p, &ns, sizeof(int), hipMemcpyHostToDevice,
                               b->stream));
         float best = INFINITY;
-        for (int ch : {1, 2, 4, 8, 16, 32, 64}) {
-            if (ch > chmax || ch * 4 < chmax) continue;
+        b->class_ch[k] = chmax;
+        int tried = 0;
+        for (int ch : {chmax, (chmax + 1) / 2, (chmax + 3) / 4}) {
+            if (ch == tried) continue;
+            tried = ch;
             HIPCHK(hipEventRecord(b->ev0, b->stream));
             batch_launch_class<T>(b, k, b->sample[k].as<int4>(), b->tune_count.as<int>(), ns,
                                   b->all_active.as<int>(), ch);

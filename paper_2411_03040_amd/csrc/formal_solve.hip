@@ -180,79 +180,97 @@ __device__ __forceinline__ T erf_diff(T a, T b, T ea, T eb)
 
 // LDS records.  The offset of a (point, bin) from the line centre is formed
 // in velocity units, x = (x_f b_o + dv + x_f b_o dv / c) / b, so it does not
-// depend on the line: the profile's exponent at a point and the
-// semi-analytic optical depth's erf difference are the same for every line
-// of the chunk.  The staging pass therefore computes them once per (record,
-// bin) and every line's lanes read them; only the per-point line data
-// (chi', S, chi' b) is staged per (record, line).
+// depend on the line: the profile at a point and the semi-analytic optical
+// depth's erf difference are the same for every line of the chunk.  The
+// staging pass therefore computes them once per (record, bin) and every
+// line's lanes read them; the per-point line data is staged per (record,
+// line).  Both forms of a segment's half depth are a sum over its two ends of
+// a line factor times a bin factor,
+//   trapezoidal:    h = chi'_P (q phi_P) + chi'_Q (q phi_Q),  q = dx / 4,
+//   semi-analytic:  h = (chi'b)_P W + (chi'b)_Q W,
+// with W the segment's erf difference times its factor (below), so staging
+// picks each end's factors by the segment's form and the sweep evaluates one
+// multiply-add, the same for every segment.  Segment k runs from record k to
+// record k - 1 (the next one towards the origin, or the origin itself):
 //  * MetaA (per record): dv, read by the sweep only at a ray's far end (the
 //    boundary intensity's comoving frequency).
 //  * StageRec (per record, staging only): dv here and at the next record
-//    towards the origin (0 at the origin), 1/b (scaled for the profile),
-//    1/b-bar of the segment (times erf_scale), half the lane-independent
-//    factor dx sqrt(pi)/4 / (dv_Q - dv_P) of a semi-analytic segment (the
-//    trace computed it in FP64 and stored it in place of the length), b and
-//    the point index.
-//  * LineRec (per record and line): chi', S', chi' b (the semi-analytic
-//    segment's weight).
-//  * BinRec (per record and bin): the profile exp(-x^2) at the point, and W
-//    for the segment from this record towards the origin: for a
-//    semi-analytic segment its optical depth without the weight, W = (erf x_Q
-//    - erf x_P) times the factor above times 1/k1 >= 0, so that dt/2 =
-//    (chi'b_P + chi'b_Q) W; for a trapezoidal one W = -(a quarter of its
-//    length) < 0, so that dt/2 = -W (chi'phi_P + chi'phi_Q).  The sign of W
-//    is the branch bit, the same on every lane of the record.  (A
-//    semi-analytic W of -0, from an erf difference that underflowed to zero,
-//    reads as a trapezoid of length 0: the same floored depth.)  In FP32 the
-//    profile underflows past ~10 widths, where chi' times it is far below
-//    the optical-depth floor.
+//    towards the origin (0 at the origin), 1/b here and there (scaled for
+//    the profile), 1/b-bar of the segment (times erf_scale), the segment's
+//    lane-independent factor (trapezoidal: a quarter of its length;
+//    semi-analytic: half of dx sqrt(pi)/4 / (dv_Q - dv_P), which the trace
+//    computed in FP64 and stored in place of the length), b, the point
+//    indices here and at the record beyond (-1 past the far end), and the
+//    forms of the segment that starts here and of the one that ends here
+//    (from the record beyond).
+//  * LineRec (per record and line): the line factor of this point as the far
+//    end of its own segment (uf) and as the near end of the segment from the
+//    record beyond (un): chi' b for a semi-analytic segment, chi' for a
+//    trapezoidal one; S' at the record beyond (the elimination row of this
+//    visit crosses that point) and S' here (read at the origin's row only).
+//  * BinRec (per record and bin): the bin factors of the segment that starts
+//    here, at its far end (vf, this point) and its near end (vn, the next
+//    point): q phi_P and q phi_Q for a trapezoidal segment, both W =
+//    (erf x_Q - erf x_P) times the factor above times 1/k1 for a
+//    semi-analytic one (x_Q - x_P = (dv_Q - dv_P) k1 / b-bar: b-bar cancels
+//    outside the erf arguments).  In FP32 the profile underflows past ~10
+//    widths, where chi' times it is far below the optical-depth floor.
 //  (Quarters and halves: the sweep works with half optical depths.)
-//  * BinConst (per bin, this origin): x_f b_o, k1 = 1 + x_f b_o / c, 1/k1.
+// Row order, as measured.  FP32 keeps a record's LineRecs (BinRecs)
+// adjacent: the sweep steps its pointers by nlc (nb) per record.  FP64 keeps
+// a line's (bin's) records adjacent, in rows of an odd number of records so
+// the lines and bins one wave reads fall in different banks: the two records
+// of an unrolled step share one address with immediate offsets (FP64: 436
+// against 473 ms per clumpy-cloud solve; the same order costs FP32 6 %).
+template <typename T>
+constexpr bool kRowsByRecord = sizeof(T) == 8;
 template <typename T>
 struct MetaA {
     T dv;
 };
 template <typename T>
 struct StageRec {
-    T dv, dvm, ib, sibb, rw, b;
-    int32_t p, semi;
+    T dv, dvm, ib, ibm, sibb, rw, b;
+    int32_t p, pn, form;  // form bit 0: this record's segment is
+                          // semi-analytic; bit 1: the one ending here is
 };
 template <typename T>
 struct alignas(4 * sizeof(T)) LineRec {
-    T chi, S, cb, pad;
+    T uf, un, Sn, S;
 };
 template <typename T>
 struct alignas(2 * sizeof(T)) BinRec {
-    T phi, W;
+    T vf, vn;
 };
-template <typename T>
-struct alignas(4 * sizeof(T)) BinConst {
-    T xb, k1, ik1, pad;
-};
-
 struct LDSLayout {
-    int ch;
-    size_t bc, st, a, line, bin, total;
+    int ch;                  // records per half
+    int ls, le, bs, be;      // LineRec (BinRec) index = line (bin) * ls (bs)
+                             // + staged record * le (be)
+    size_t st, a, line, bin, total;
 };
 
-// Every section's size is a multiple of 16 bytes, so each starts aligned.
+// Every section starts 16-byte aligned.
 template <typename T>
 __host__ __device__ inline LDSLayout lds_layout(int ch, int nlc, int nb, int nthreads)
 {
     LDSLayout L;
     L.ch = ch;
+    const int rows = kRowsByRecord<T> ? 2 * ch + 1 : 2 * ch;
+    L.ls = kRowsByRecord<T> ? rows : 1;
+    L.le = kRowsByRecord<T> ? 1 : nlc;
+    L.bs = kRowsByRecord<T> ? rows : 1;
+    L.be = kRowsByRecord<T> ? 1 : nb;
     size_t o = 0;
-    L.bc = o;
-    o += sizeof(BinConst<T>) * nb;
     L.st = o;
     o += sizeof(StageRec<T>) * 2 * ch;
     o = (o + 15) & ~(size_t)15;
     L.a = o;
     o += sizeof(MetaA<T>) * 2 * ch;
+    o = (o + 15) & ~(size_t)15;
     L.line = o;
-    o += sizeof(LineRec<T>) * 2 * ch * nlc;
+    o += sizeof(LineRec<T>) * (size_t)rows * nlc;
     L.bin = o;
-    o += sizeof(BinRec<T>) * 2 * ch * nb;
+    o += sizeof(BinRec<T>) * (size_t)rows * nb;
     const size_t red = sizeof(double) * 2 * nthreads;
     L.total = o > red ? o : red;
     return L;
@@ -286,25 +304,37 @@ __device__ __forceinline__ Rec<double> load_stream(gptr<Rec<double>> p)
     return r;
 }
 
+// LDS pointers as 32-bit addresses.  opaque() hides how an address was
+// formed: the optimiser would otherwise split a stepped sweep pointer into
+// its lane-dependent and uniform parts and add the two at every access
+// (ds instructions take no scalar offset), one vector add per read instead
+// of one per step.
+template <typename X>
+using lptr = const __attribute__((address_space(3))) X *;
+template <typename X>
+__device__ __forceinline__ lptr<X> opaque(const X *p)
+{
+    uint32_t v = (uint32_t)(uintptr_t)(lptr<X>)p;
+    asm volatile("" : "+v"(v));
+    return (lptr<X>)(uintptr_t)v;
+}
+
 template <typename T>
 struct HalfState {
-    T G, eps, hm;       // elimination state: 2g, eps, half the previous depth
-    T chi, phi, S, cb;  // previous point: chi', profile, source, chi'*b
-    T W;                // segment from the previous point towards the origin:
-                        // its BinRec W
+    T G, eps, hm;  // elimination state: 2g, eps, half the previous depth
+    T a, vn;       // previous point P: its end's term of the segment from P
+                   // towards the origin (uf vf) and that segment's near-end
+                   // bin factor
 };
 
-// Unrolling and occupancy, as measured: both sweep loops are unrolled twice
-// (no register copies between iterations), the longer half alone four times
-// in FP64.  FP32 launches other than one-width models are held to 64 VGPRs
-// (eight waves per SIMD): a few bytes spill outside the sweeps, and the
-// extra waves hide more latency than the spills cost (outflow 13.0 ms
-// against 14.5 uncapped); one-width models keep their 70 registers (seven
-// waves; capped: 149 ms against 134 on the clumpy cloud).  Every FP64 launch
-// is held to 128 VGPRs (four waves; the one-width kernel needs 146, three
-// waves: 865 ms against 601 capped on the clumpy cloud).
+// Unrolling and occupancy, as measured: the sweep loops take two records
+// per step (no register copies between steps).  FP32 launches other than
+// one-width models are held to 64 VGPRs (eight waves per SIMD; a few bytes
+// spill outside the sweeps); one-width models keep their 67 (seven waves,
+// which for their 12-wave workgroups is the same two workgroups per CU as
+// eight).  Every FP64 launch is held to 128 VGPRs (four waves).
 template <typename T, bool ONE_WIDTH>
-constexpr int kWavesPerEu = sizeof(T) == 4 ? (ONE_WIDTH ? 1 : 8) : 4;
+constexpr int kWavesPerEu = sizeof(T) == 4 ? (ONE_WIDTH ? 7 : 8) : 4;
 
 // One origin x line chunk, executed by the whole workgroup (blockDim.x
 // threads, at least nlc * nbins).  Shared by the single-model launch and the
@@ -334,34 +364,22 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
     const gptr_mut<double> Jout = glob_mut(a.J), Lout = glob_mut(a.L);
 
     const LDSLayout LY = lds_layout<T>(ch, nlc, nb, nth);
-    BinConst<T> *s_bc = (BinConst<T> *)(smem + LY.bc);
     StageRec<T> *s_st = (StageRec<T> *)(smem + LY.st);
     MetaA<T> *s_a = (MetaA<T> *)(smem + LY.a);
     LineRec<T> *s_line = (LineRec<T> *)(smem + LY.line);
     BinRec<T> *s_bin = (BinRec<T> *)(smem + LY.bin);
 
-    // per-bin constants of this origin, for the staging pass
+    // per-lane constants (bin f: x_f b_o, k1 = 1 + x_f b_o / c, 1/k1)
     const double bo = b64[o];
-    for (int t = tid; t < nb; t += nth) {
-        const double xbt = xf[t] * bo;
-        BinConst<T> c;
-        c.xb = (T)xbt;
-        c.k1 = (T)(1.0 + xbt / kC);
-        c.ik1 = (T)(1.0 / (1.0 + xbt / kC));
-        c.pad = (T)0;
-        s_bc[t] = c;
-    }
-
-    // per-lane constants
     const double xfd = xf[f];
     const double xbd = xfd * bo;
     const T xb = (T)xbd;
     const T k1 = (T)(1.0 + xbd / kC);
+    const T ik1 = (T)(1.0 / (1.0 + xbd / kC));
     const T inv_c = (T)(1.0 / kC);
     const T acmb = (T)acmb_l[l];
     const int64_t ol = (int64_t)o * nl + l;
     const T chi_o = chi[ol];
-    const T phi_o = FM<T>::phi_of(xb * ibpt[o]);
     const T S_o = S[ol];
     const T cb_o = chi[ol] * bpt[o];
     const T half_floor = (T)(0.5 * a.tau_floor);
@@ -371,33 +389,37 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
         const T r = k1 * ((T)1 + dv * inv_c);
         return r * r * r * FM<T>::rcp(FM<T>::expm1_(acmb * r));
     };
+    // the boundary intensity at the origin (an empty half's)
+    const T I_o = bdy_I((T)0);
 
-    // one elimination step across the previous point, h = half the depth of
-    // the segment that follows it (q2 = 2q, and q2 h = q dt exactly)
-    auto row = [&](HalfState<T> &st, T h) {
+    // staging columns, fixed per thread so the loops need no division:
+    // line li of records le0, le0 + lrows, ...; bin f (the lane's own) of
+    // records be0, be0 + brows, ... (threads past the last full row idle)
+    const int lrows = nth / nl_here, brows = nth / nb;
+    const int li_s = tid % nl_here, le0 = tid / nl_here < lrows ? tid / nl_here : INT_MAX;
+    const int be0 = tid / nb < brows ? tid / nb : INT_MAX;
+
+    // one elimination step across the previous point (source SP), h = half
+    // the depth of the segment that follows it (q2 = 2q, and q2 h = q dt
+    // exactly)
+    auto row = [&](HalfState<T> &st, T h, T SP) {
         const T D = st.hm + h;
         const T q2 = D * (T)2 + st.G;
         const T inv = FM<T>::rcp_ge1((T)1 + q2 * h);
         st.G = q2 * inv;
-        st.eps = (D * st.S + st.eps) * inv;
+        st.eps = (D * SP + st.eps) * inv;
         st.hm = h;
     };
 
     // half the optical depth of the segment from the previous point of st
-    // (farther out) to Q.  Trapezoidal: a quarter of the length times the
-    // two ends' chi' exp(-x^2).  Semi-analytic:
-    //   dt = dx sqrt(pi)/4 (cb_P + cb_Q) (erf x_Q - erf x_P) / (b-bar (x_Q - x_P))
-    // with x = u / b-bar and x_Q - x_P = (dvQ - dvP) k1 / b-bar, so b-bar
-    // cancels outside the erf arguments and everything but the weight
-    // cb_P + cb_Q is the staged BinRec W of the segment.  Floored at
-    // tau_floor / 2.
-    auto segment = [&](HalfState<T> &st, T chiQ, T phiQ, T cbQ) -> T {
-        T h;
-        if (signbit(st.W))
-            h = st.W * -(st.chi * st.phi + chiQ * phiQ);
-        else
-            h = (st.cb + cbQ) * st.W;
-        return FM<T>::at_least(h, half_floor);
+    // (farther out) to Q, whose line factor as the segment's near end is
+    // unQ: trapezoidal dt/2 = dx/4 (chi'_P phi_P + chi'_Q phi_Q),
+    // semi-analytic
+    //   dt/2 = dx sqrt(pi)/8 (cb_P + cb_Q) (erf x_Q - erf x_P) / (b-bar (x_Q - x_P)),
+    // both as the far end's term plus unQ times the near-end bin factor.
+    // Floored at tau_floor / 2.
+    auto segment = [&](const HalfState<T> &st, T unQ) -> T {
+        return FM<T>::at_least(unQ * st.vn + st.a, half_floor);
     };
 
     double accJ = 0.0, accL = 0.0;
@@ -408,6 +430,10 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
         const int np = (int)(off[(int64_t)o * R + rp + 1] - offp);
         const int64_t offm = off[(int64_t)o * R + rm];
         const int nm = (int)(off[(int64_t)o * R + rm + 1] - offm);
+        // the origin's line factor as the near end of each half's last
+        // segment, by that segment's form
+        const T un_om = (nm > 0 && rec[offm].ps < 0) ? cb_o : chi_o;
+        const T un_op = (np > 0 && rec[offp].ps < 0) ? cb_o : chi_o;
 
         // Halves by length: A the longer (all of a chunk's records lie
         // inside it), B the shorter.  The minus half is staged first.
@@ -416,27 +442,24 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
         HalfState<T> A, B;
         A.G = B.G = (T)2;
         A.hm = B.hm = (T)0;
-        A.eps = B.eps = bdy_I((T)0);  // replaced at the far end of a non-empty half
-        A.chi = A.phi = A.S = A.cb = A.W = (T)0;
-        B.chi = B.phi = B.S = B.cb = B.W = (T)0;
+        A.eps = B.eps = I_o;  // replaced at the far end of a non-empty half
+        A.a = A.vn = (T)0;
+        B.a = B.vn = (T)0;
 
         // point Q (staged record e) of a half: either the far-end boundary
         // intensity or one elimination row
-        auto visit = [&](HalfState<T> &s, const MetaA<T> *pa, const LineRec<T> *pl,
-                         const BinRec<T> *pn, bool far_end) {
-            const LineRec<T> lr = *pl;
-            const BinRec<T> br = *pn;
+        auto visit = [&](HalfState<T> &s, T dv, auto pl, auto pn, bool far_end) {
+            const T uf = pl->uf, un = pl->un, Sn = pl->Sn;
+            const T vf = pn->vf, vn = pn->vn;
             if (far_end)
-                s.eps = bdy_I(pa->dv);
+                s.eps = bdy_I(dv);
             else
-                row(s, segment(s, lr.chi, br.phi, lr.cb));
-            s.chi = lr.chi;
-            s.phi = br.phi;
-            s.S = lr.S;
-            s.cb = lr.cb;
-            s.W = br.W;
+                row(s, segment(s, un), Sn);
+            s.a = uf * vf;
+            s.vn = vn;
         };
 
+        int eA0 = 0, eB0 = 0;  // staged index of record 0 of each half
         for (int hi = nA; hi > 0; hi -= ch) {
             const int lo = hi - ch > 0 ? hi - ch : 0;
             // valid records of each half in [lo, hi), packed densely: the
@@ -449,102 +472,157 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
                 const bool plus = t >= cm;
                 const int k = lo + (plus ? t - cm : t);
                 const int64_t base = plus ? offp : offm;
+                const int n = plus ? np : nm;
                 const Rec<T> rc = load_stream(rec + base + k);
                 const int p = rc.ps & 0x7fffffff;
                 const bool semi = rc.ps < 0;
                 StageRec<T> sr;
                 sr.dv = rc.dv;
-                sr.dvm = k > 0 ? rec[base + k - 1].dv : (T)0;  // the origin's is 0
+                if (k > 0) {
+                    sr.dvm = rec[base + k - 1].dv;
+                    sr.ibm = ibpt[rec[base + k - 1].ps & 0x7fffffff];
+                } else {  // the origin, dv = 0
+                    sr.dvm = (T)0;
+                    sr.ibm = ibpt[o];
+                }
                 sr.ib = ibpt[p];
                 sr.sibb = rc.ibb * (T)FM<T>::erf_scale;
                 // semi-analytic: half its lane-independent factor; trapezoidal:
-                // minus a quarter of its length
-                sr.rw = semi ? rc.dx * half : rc.dx * (T)-0.25;
+                // a quarter of its length
+                sr.rw = semi ? rc.dx * half : rc.dx * (T)0.25;
                 sr.b = bpt[p];
                 sr.p = p;
-                sr.semi = semi ? 1 : 0;
+                const int psn = k + 1 < n ? rec[base + k + 1].ps : 0;
+                sr.pn = k + 1 < n ? psn & 0x7fffffff : -1;
+                sr.form = (semi ? 1 : 0) | (psn < 0 ? 2 : 0);
                 s_st[t] = sr;
                 MetaA<T> ma;
                 ma.dv = rc.dv;
                 s_a[t] = ma;
             }
             __syncthreads();
-            for (int t = tid; t < cnt * nl_here; t += nth) {
-                const int e = t / nl_here;
-                const int li = t - e * nl_here;
+            for (int e = le0; e < cnt; e += lrows) {
+                const int li = li_s;
                 const StageRec<T> &sr = s_st[e];
                 const int64_t idx = (int64_t)sr.p * nl + l0 + li;
                 LineRec<T> lr;
                 const T chi_l = chi[idx];
-                lr.chi = chi_l;
+                const T cb = chi_l * sr.b;
+                lr.uf = (sr.form & 1) ? cb : chi_l;
+                lr.un = (sr.form & 2) ? cb : chi_l;
+                lr.Sn = sr.pn >= 0 ? S[(int64_t)sr.pn * nl + l0 + li] : (T)0;
                 lr.S = S[idx];
-                lr.cb = chi_l * sr.b;
-                lr.pad = (T)0;
-                s_line[e * nlc + li] = lr;
+                s_line[li * LY.ls + e * LY.le] = lr;
             }
-            // per (record, bin): the profile at the point and W of the segment
-            // towards the origin (semi-analytic: the erf difference, x_P at
-            // this record and x_Q at the next one, times its factor and 1/k1)
-            for (int t = tid; t < cnt * nb; t += nth) {
-                const int e = t / nb;
-                const int fb = t - e * nb;
+            // per (record, bin): the bin factors of the segment towards the
+            // origin (P this record, Q the next one)
+            for (int e = be0; e < cnt; e += brows) {
                 const StageRec<T> &sr = s_st[e];
-                const BinConst<T> bc = s_bc[fb];
-                const T uP = bc.xb + sr.dv * bc.k1;
+                const T uP = xb + sr.dv * k1;
+                const T uQ = xb + sr.dvm * k1;
                 BinRec<T> br;
-                br.phi = FM<T>::phi_of(uP * sr.ib);
-                br.W = sr.rw;
-                if (sr.semi) {
-                    const T uQ = bc.xb + sr.dvm * bc.k1;
+                if (sr.form & 1) {
                     const T xP = uP * sr.sibb;
                     const T xQ = uQ * sr.sibb;
                     const T eP = FM<T>::erfc_scaled(fabs(xP));
                     const T eQ = FM<T>::erfc_scaled(fabs(xQ));
-                    br.W = erf_diff<T>(xP, xQ, eP, eQ) * (sr.rw * bc.ik1);
+                    br.vf = br.vn = erf_diff<T>(xP, xQ, eP, eQ) * (sr.rw * ik1);
+                } else {
+                    br.vf = sr.rw * FM<T>::phi_of(uP * sr.ib);
+                    br.vn = sr.rw * FM<T>::phi_of(uQ * sr.ibm);
                 }
-                s_bin[e * nb + fb] = br;
+                s_bin[f * LY.bs + e * LY.be] = br;
             }
             __syncthreads();
-            // record k of half A is staged at eA + k, of half B at eB + k
+            // record k of half A is staged at eA + k, of half B at eB + k; a
+            // lane's line and bin rows of each half, indexed by record
             const int eA = (a_minus ? 0 : cm) - lo, eB = (a_minus ? cm : 0) - lo;
-            int k = hi - 1;
-            // the sweeps step pointers to the staged records down, so each
-            // LDS read takes its address as it is
-            const MetaA<T> *pa = s_a + (eA + k);
-            const LineRec<T> *la = s_line + (eA + k) * nlc + ll;
-            const BinRec<T> *na = s_bin + (eA + k) * nb + f;
-            // records beyond the end of B: A alone (its far end first)
-            if (k >= nB && k == nA - 1) {
-                visit(A, pa--, la, na, true);
-                la -= nlc;
-                na -= nb;
-                k--;
-            }
-            const int kAB = max(lo, nB);
-#pragma unroll(sizeof(T) == 8 ? 4 : 2)
-            for (; k >= kAB; k--, la -= nlc, na -= nb) visit(A, pa--, la, na, false);
-            const MetaA<T> *pb = s_a + (eB + k);
-            const LineRec<T> *lb = s_line + (eB + k) * nlc + ll;
-            const BinRec<T> *nbp = s_bin + (eB + k) * nb + f;
-            // B's far end (A's too when the halves are equally long)
-            if (k >= lo && k == nB - 1) {
-                visit(A, pa--, la, na, k == nA - 1);
-                visit(B, pb--, lb, nbp, true);
-                la -= nlc;
-                lb -= nlc;
-                na -= nb;
-                nbp -= nb;
-                k--;
-            }
-#pragma unroll 2
-            for (; k >= lo; k--, la -= nlc, lb -= nlc, na -= nb, nbp -= nb) {
-                visit(A, pa--, la, na, false);
-                visit(B, pb--, lb, nbp, false);
+            eA0 = eA;  // the last chunk has lo = 0
+            eB0 = eB;
+            if constexpr (kRowsByRecord<T>) {
+                const LineRec<T> *la = s_line + ll * LY.ls + eA, *lb = s_line + ll * LY.ls + eB;
+                const BinRec<T> *na = s_bin + f * LY.bs + eA, *nbr = s_bin + f * LY.bs + eB;
+                int k = hi - 1;
+                // records beyond the end of B: A alone (its far end first), two
+                // records per step
+                if (k >= nB && k == nA - 1) {
+                    visit(A, s_a[eA + k].dv, la + k, na + k, true);
+                    k--;
+                }
+                const int kAB = max(lo, nB);
+                {
+                    // pointers at the lower record of each step: the upper one is
+                    // an immediate offset
+                    lptr<LineRec<T>> pl = opaque(la + k - 1);
+                    lptr<BinRec<T>> pn = opaque(na + k - 1);
+                    for (; k > kAB; k -= 2, pl -= 2, pn -= 2) {
+                        visit(A, (T)0, pl + 1, pn + 1, false);
+                        visit(A, (T)0, pl, pn, false);
+                    }
+                }
+                if (k == kAB) {
+                    visit(A, (T)0, la + k, na + k, false);
+                    k--;
+                }
+                // B's far end (A's too when the halves are equally long)
+                if (k >= lo && k == nB - 1) {
+                    const bool a_far = k == nA - 1;
+                    visit(A, a_far ? s_a[eA + k].dv : (T)0, la + k, na + k, a_far);
+                    visit(B, s_a[eB + k].dv, lb + k, nbr + k, true);
+                    k--;
+                }
+                {
+                    lptr<LineRec<T>> pla = opaque(la + k - 1), plb = opaque(lb + k - 1);
+                    lptr<BinRec<T>> pna = opaque(na + k - 1), pnb = opaque(nbr + k - 1);
+                    for (; k > lo; k -= 2, pla -= 2, plb -= 2, pna -= 2, pnb -= 2) {
+                        visit(A, (T)0, pla + 1, pna + 1, false);
+                        visit(B, (T)0, plb + 1, pnb + 1, false);
+                        visit(A, (T)0, pla, pna, false);
+                        visit(B, (T)0, plb, pnb, false);
+                    }
+                }
+                if (k == lo) {
+                    visit(A, (T)0, la + k, na + k, false);
+                    visit(B, (T)0, lb + k, nbr + k, false);
+                }
+            } else {
+                int k = hi - 1;
+                const LineRec<T> *la = s_line + (eA + k) * nlc + ll;
+                const BinRec<T> *na = s_bin + (eA + k) * nb + f;
+                // records beyond the end of B: A alone (its far end first)
+                if (k >= nB && k == nA - 1) {
+                    visit(A, s_a[eA + k].dv, la, na, true);
+                    la -= nlc;
+                    na -= nb;
+                    k--;
+                }
+                const int kAB = max(lo, nB);
+    #pragma unroll 2
+                for (; k >= kAB; k--, la -= nlc, na -= nb) visit(A, (T)0, la, na, false);
+                const LineRec<T> *lb = s_line + (eB + k) * nlc + ll;
+                const BinRec<T> *nbp = s_bin + (eB + k) * nb + f;
+                // B's far end (A's too when the halves are equally long)
+                if (k >= lo && k == nB - 1) {
+                    const bool a_far = k == nA - 1;
+                    visit(A, a_far ? s_a[eA + k].dv : (T)0, la, na, a_far);
+                    visit(B, s_a[eB + k].dv, lb, nbp, true);
+                    la -= nlc;
+                    lb -= nlc;
+                    na -= nb;
+                    nbp -= nb;
+                    k--;
+                }
+    #pragma unroll 2
+                for (; k >= lo; k--, la -= nlc, lb -= nlc, na -= nb, nbp -= nb) {
+                    visit(A, (T)0, la, na, false);
+                    visit(B, (T)0, lb, nbp, false);
+                }
             }
         }
         // last segment of each non-empty half ends at the origin
-        if (nA > 0) row(A, segment(A, chi_o, phi_o, cb_o));
-        if (nB > 0) row(B, segment(B, chi_o, phi_o, cb_o));
+        // (S' at records 0, still staged from the last chunk)
+        if (nA > 0) row(A, segment(A, a_minus ? un_om : un_op), s_line[ll * LY.ls + eA0 * LY.le].S);
+        if (nB > 0) row(B, segment(B, a_minus ? un_op : un_om), s_line[ll * LY.ls + eB0 * LY.le].S);
         // combine in the order minus, plus
         const HalfState<T> &Hm = a_minus ? A : B, &Hp = a_minus ? B : A;
         const T Do = Hm.hm + Hp.hm;
@@ -627,25 +705,30 @@ size_t formal_solve_lds(int ch, int nlc, int nb, int nthreads)
 template size_t formal_solve_lds<float>(int, int, int, int);
 template size_t formal_solve_lds<double>(int, int, int, int);
 
-// The LDS a workgroup may take so that enough workgroups fit on a CU (160
-// KiB of LDS) to fill the waves its registers allow (about 32 per CU in
-// FP32, 16 in FP64): small workgroups (5 waves for the outflow's 9 lines x 31
-// bins) then stage fewer records at a time instead of being held to two per
-// CU by their LDS; large ones keep 60 KiB.
+// The LDS a workgroup may take: 160 KiB shared by the workgroups the
+// registers let a CU hold (about 28 waves in FP32, 16 in FP64; whole
+// workgroups only), at most 80 KiB.  The chunk is then the largest that
+// fits, in steps of 8 records: a record chunk ends in a barrier and a wait on
+// the next chunk's gathers that only the CU's other workgroups can cover, so
+// fewer, larger chunks matter more than one more resident workgroup
+// (clumpy cloud, two 12-wave workgroups per CU: 56 records per half, 109
+// against 116 ms with 32; outflow, five 5-wave workgroups: 32 against 16,
+// 9.1 against 10.5 ms).
 static size_t lds_budget(int nthreads, int target_waves)
 {
     const int waves = (nthreads + 63) / 64;
-    const int wgs = (target_waves + waves - 1) / waves;
+    int wgs = target_waves / waves;
+    if (wgs < 1) wgs = 1;
     const size_t b = (size_t)160 * 1024 / wgs - 1024;
-    return b < (size_t)60 * 1024 ? b : (size_t)60 * 1024;
+    return b < (size_t)80 * 1024 ? b : (size_t)80 * 1024;
 }
 
 template <typename T>
 int formal_solve_chunk(int nlc, int nb, int nthreads)
 {
-    const size_t budget = lds_budget(nthreads, sizeof(T) == 4 ? 32 : 16);
+    const size_t budget = lds_budget(nthreads, sizeof(T) == 4 ? 28 : 16);
     int ch = 64;
-    while (lds_layout<T>(ch, nlc, nb, nthreads).total > budget && ch > 1) ch /= 2;
+    while (lds_layout<T>(ch, nlc, nb, nthreads).total > budget && ch > 1) ch -= ch > 8 ? 8 : 1;
     return ch;
 }
 template int formal_solve_chunk<float>(int, int, int);
