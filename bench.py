@@ -296,28 +296,42 @@ def cpu_baseline(m, seconds, gpu_J=None, converged=None, tol=1e-10):
 
 
 def ng_study(mgx, torch):
-    """Iterations to converge (1e-10, FP64) with no Ng, classical Ng of N_steps
-    and adaptive Ng with N_max, on the two spherical variants (moderate and
-    high optical depth): the comparison of the paper's Ng section."""
+    """Iterations to converge with no Ng, classical Ng of N_steps and adaptive
+    Ng with N_max, each also with the restart reading in which a prediction
+    starts the history afresh (NG_FRESH): on the two spherical variants
+    (moderate and high optical depth; FP64 to 1e-10) and on the clumpy cloud
+    (FP32-bulk to 1e-6; its plain iteration does not converge): the
+    comparison of the paper's Ng section."""
     from paper_2411_03040_amd import synth
     res = {}
-    for variant in ("a", "b"):
-        m = synth.spherical_shells(variant)
+    modes = ([("none", mgx.NG_NONE, 0)] +
+             [(f"classical_{n}", mgx.NG_CLASSICAL, n) for n in (2, 3, 4, 8)] +
+             [(f"adaptive_{n}", mgx.NG_ADAPTIVE, n) for n in (4, 8, 16, 32)] +
+             [("classical_4_fresh", mgx.NG_CLASSICAL | mgx.NG_FRESH, 4)] +
+             [(f"adaptive_{n}_fresh", mgx.NG_ADAPTIVE | mgx.NG_FRESH, n) for n in (8, 32)])
+    cases = [(f"shells_{v}", synth.spherical_shells(v), mgx.FP64, 1e-10, 2000, modes) for v in ("a", "b")]
+    cases.append(("clumpy_fp32_bulk", synth.config(2), mgx.FP32, 1e-6, 300,
+                  [m for m in modes if m[0] in ("classical_4", "adaptive_8", "adaptive_32",
+                                                 "classical_4_fresh", "adaptive_8_fresh",
+                                                 "adaptive_32_fresh")]))
+    for name, m, prec, tol, max_iter, case_modes in cases:
         row = {}
-        for label, mode, param in ([("none", mgx.NG_NONE, 0)] +
-                                   [(f"classical_{n}", mgx.NG_CLASSICAL, n) for n in (2, 3, 4, 8)] +
-                                   [(f"adaptive_{n}", mgx.NG_ADAPTIVE, n) for n in (4, 8, 16, 32)]):
-            cx = mgx.Context(device=0, precision=mgx.FP64)
+        for label, mode, param in case_modes:
+            cx = mgx.Context(device=0, precision=prec)
             cx.load_model(m)
             cx.trace_rays()
             cx.set_lte_populations()
-            it, ch, ok = cx.iterate(tol=1e-10, max_iter=2000, ng_mode=mode, ng_param=param if mode else 4,
-                                    raise_on_noconv=False)
+            t0 = time.perf_counter()
+            it, ch, ok = cx.iterate(tol=tol, max_iter=max_iter, ng_mode=mode,
+                                    ng_param=param if mode else 4, raise_on_noconv=False)
+            dt = time.perf_counter() - t0
             c = cx.counters()
-            row[label] = {"iterations": it, "converged": ok, "ng_applied": c["ng_applied"]}
-            log(f"  ng-study {variant} {label}: {it} iterations")
+            row[label] = {"iterations": it, "converged": ok, "ng_applied": c["ng_applied"],
+                          "seconds": dt}
+            log(f"  ng-study {name} {label}: {it} iterations, {dt:.2f} s")
             del cx
-        res[f"shells_{variant}"] = row
+        res[name] = {"tol": tol, "precision": "fp64" if prec == mgx.FP64 else "fp32 bulk",
+                     "modes": row}
     return res
 
 
