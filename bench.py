@@ -405,7 +405,9 @@ def bench_batch(args, mgx, torch):
                      "tune_seconds": st["tune_seconds"],
                      "classes": [{"threads": st["class_threads"][k],
                                   "items": st["class_items"][k],
-                                  "chunk": st["class_chunk"][k]}
+                                  "chunk": st["class_chunk"][k],
+                                  "order": ("by model and Morton origin" if st["class_order"][k]
+                                            else "longest first")}
                                  for k in range(16) if st["class_items"][k]]},
         "generate_seconds": gen_s, "prepare_seconds": prep_s,
         "converged": {"seconds": conv_s, "models_converged": nconv, "tol": tol,

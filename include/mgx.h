@@ -374,6 +374,8 @@ typedef struct {
     int class_items[MGX_BATCH_CLASSES];    /* work items per lane class (0: unused) */
     int class_threads[MGX_BATCH_CLASSES];  /* workgroup size of each used class     */
     int class_chunk[MGX_BATCH_CLASSES];    /* tuned LDS records per half            */
+    int class_order[MGX_BATCH_CLASSES];    /* tuned item order: 0 longest first,
+                                              1 by model, Morton origin, chunk      */
     double tune_seconds;      /* time spent tuning the schedule                  */
     double iterate_seconds;   /* wall time of the last mgx_batch_iterate        */
     double last_converged_seconds;  /* ... until its last converged model stopped */

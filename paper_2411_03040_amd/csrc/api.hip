@@ -224,35 +224,13 @@ extern "C" mgx_status mgx_load_model(mgx_ctx *ctx, const mgx_model *m)
                        (hi3[2] - lo3[2]) * (hi3[2] - lo3[2]));
     ctx->L_unit = diag > 0 ? diag / cbrt((double)N) : 1.0;
 
-    // Origins in Morton (Z-curve) order of their positions, 10 bits per axis
-    // over the bounding box, ties by index -- kept only where the formal
-    // solution uses it: when the line table (chi' and S' in the solve
+    // Origins in Morton order of their positions -- kept only where the
+    // formal solution uses it: when the line table (chi' and S' in the solve
     // precision) outgrows one XCD's 4 MB L2.
     ctx->order.release();
     const size_t table = (size_t)N * m->nlines * 2 * (ctx->fp32() ? sizeof(float) : sizeof(double));
     if (table > ((size_t)4 << 20)) {
-        auto spread = [](uint32_t v) {
-            uint64_t x = v & 0x3ff;
-            x = (x | (x << 16)) & 0x030000ffull;
-            x = (x | (x << 8)) & 0x0300f00full;
-            x = (x | (x << 4)) & 0x030c30c3ull;
-            x = (x | (x << 2)) & 0x09249249ull;
-            return x;
-        };
-        std::vector<std::pair<uint64_t, int32_t>> key((size_t)N);
-        for (int i = 0; i < N; i++) {
-            uint64_t code = 0;
-            for (int k = 0; k < 3; k++) {
-                const double w = hi3[k] - lo3[k];
-                const double f = w > 0 ? (m->pos[(size_t)k * N + i] - lo3[k]) / w : 0.0;
-                const uint32_t c = (uint32_t)std::min(1023.0, std::max(0.0, f * 1024.0));
-                code |= spread(c) << k;
-            }
-            key[i] = {code, i};
-        }
-        std::sort(key.begin(), key.end());
-        std::vector<int32_t> ord((size_t)N);
-        for (int i = 0; i < N; i++) ord[i] = key[i].second;
+        const std::vector<int32_t> ord = morton_order(m->pos, N);
         upload(ctx, ctx->order, ord.data(), ord.size());
         ctx->sync();
     }
@@ -599,6 +577,42 @@ void mgxh::line_coeffs_into(mgx_ctx *ctx, const double *pops, void *chiT, void *
     la.cnt = cnt;
     HIPCHK(launch_reset_counters(cnt, s));
     HIPCHK(launch_line_coeffs(la, s));
+}
+
+std::vector<int32_t> mgxh::morton_order(const double *pos, int N)
+{
+    double lo3[3], hi3[3];
+    for (int k = 0; k < 3; k++) {
+        lo3[k] = INFINITY;
+        hi3[k] = -INFINITY;
+        for (int i = 0; i < N; i++) {
+            lo3[k] = std::min(lo3[k], pos[(size_t)k * N + i]);
+            hi3[k] = std::max(hi3[k], pos[(size_t)k * N + i]);
+        }
+    }
+    auto spread = [](uint32_t v) {
+        uint64_t x = v & 0x3ff;
+        x = (x | (x << 16)) & 0x030000ffull;
+        x = (x | (x << 8)) & 0x0300f00full;
+        x = (x | (x << 4)) & 0x030c30c3ull;
+        x = (x | (x << 2)) & 0x09249249ull;
+        return x;
+    };
+    std::vector<std::pair<uint64_t, int32_t>> key((size_t)N);
+    for (int i = 0; i < N; i++) {
+        uint64_t code = 0;
+        for (int k = 0; k < 3; k++) {
+            const double w = hi3[k] - lo3[k];
+            const double f = w > 0 ? (pos[(size_t)k * N + i] - lo3[k]) / w : 0.0;
+            const uint32_t c = (uint32_t)std::min(1023.0, std::max(0.0, f * 1024.0));
+            code |= spread(c) << k;
+        }
+        key[i] = {code, i};
+    }
+    std::sort(key.begin(), key.end());
+    std::vector<int32_t> ord((size_t)N);
+    for (int i = 0; i < N; i++) ord[i] = key[i].second;
+    return ord;
 }
 
 void mgxh::run_line_coeffs(mgx_ctx *ctx)

@@ -98,6 +98,7 @@ static void batch_build_tables(mgx_batch *b)
     const int M = (int)b->m.size();
     std::vector<FSArgs<T>> d(M);
     std::vector<std::vector<std::pair<int64_t, int4>>> cls(MGX_BATCH_CLASSES);
+    std::vector<std::vector<int32_t>> rank(M);  // origin -> its Morton rank
     DMem cost;
     for (int k = 0; k < MGX_BATCH_CLASSES; k++) {
         b->class_threads[k] = 64 * (k + 1);
@@ -118,7 +119,13 @@ static void batch_build_tables(mgx_batch *b)
         std::vector<int64_t> hc(c->N);
         HIPCHK(hipMemcpyAsync(hc.data(), cost.p, sizeof(int64_t) * c->N, hipMemcpyDeviceToHost,
                               b->stream));
+        std::vector<double> pos(3 * (size_t)c->N);
+        HIPCHK(hipMemcpyAsync(pos.data(), c->pos.p, sizeof(double) * pos.size(),
+                              hipMemcpyDeviceToHost, b->stream));
         b->sync();
+        const std::vector<int32_t> ord = morton_order(pos.data(), c->N);
+        rank[i].resize(c->N);
+        for (int j = 0; j < c->N; j++) rank[i][ord[j]] = j;
         const int nchunks = (c->nlines + d[i].nlc - 1) / d[i].nlc;
         const int64_t lanes = (int64_t)d[i].nlc * c->nbins;
         for (int o = 0; o < c->N; o++)
@@ -149,6 +156,18 @@ static void batch_build_tables(mgx_batch *b)
         b->work_items += (int64_t)it.size();
         if (!it.empty()) b->nclass++;
         upload(b->m[0], b->items_all[k], it.data(), it.size());
+        // the alternative order: by model, origin in Morton order, line chunk
+        // (workgroups dealt to one XCD then gather neighbouring points)
+        std::vector<int4> loc = it;
+        std::stable_sort(loc.begin(), loc.end(), [&rank](const int4 &x, const int4 &y) {
+            if (x.x != y.x) return x.x < y.x;
+            const int rx = rank[x.x][x.y], ry = rank[y.x][y.y];
+            if (rx != ry) return rx < ry;
+            return x.z < y.z;
+        });
+        b->items_alt[k].release();
+        if (!loc.empty()) upload(b->m[0], b->items_alt[k], loc.data(), loc.size());
+        b->class_order[k] = 0;
         b->items[k].ensure(sizeof(int4) * std::max<size_t>(1, it.size()));
         const size_t stride = it.size() >= 32768 ? 8 : 1;
         std::vector<int4> smp;
@@ -225,7 +244,7 @@ extern "C" mgx_status mgx_batch_get_populations(mgx_batch *b, int id, double *po
 }
 
 // Upload the host mask and keep only the work items of active models (same
-// longest-first order; *counts[k] of them per class).
+// order; *counts[k] of them per class).
 void mgxh::batch_push_mask(mgx_batch *b)
 {
     const int M = (int)b->m.size();
@@ -250,9 +269,9 @@ static void batch_launch_class(mgx_batch *b, int k, const int4 *items, const int
                                         active, ch, b->class_threads[k], lds, b->stream));
 }
 
-// Schedule tuning: per lane class, time each LDS chunk size (records staged
-// per half-ray) on a strided sample of the class's items and keep the
-// fastest.
+// Schedule tuning, per lane class: the LDS chunk (records staged per
+// half-ray), timed on a strided sample of the class's items, then the item
+// order, timed on full launches at that chunk; the fastest of each is kept.
 template <typename T>
 static void batch_tune(mgx_batch *b)
 {
@@ -287,6 +306,25 @@ static void batch_tune(mgx_batch *b)
                 b->class_ch[k] = ch;
             }
         }
+        // item order: one full launch of the class in each order at the
+        // chosen chunk; keep the faster
+        HIPCHK(hipMemcpyAsync(b->tune_count.p, &n, sizeof(int), hipMemcpyHostToDevice,
+                              b->stream));
+        float t[2] = {INFINITY, INFINITY};
+        for (int ord = 0; ord < 2; ord++) {
+            const int4 *items = (ord ? b->items_alt[k] : b->items_all[k]).as<int4>();
+            HIPCHK(hipEventRecord(b->ev0, b->stream));
+            batch_launch_class<T>(b, k, items, b->tune_count.as<int>(), n,
+                                  b->all_active.as<int>(), b->class_ch[k]);
+            HIPCHK(hipEventRecord(b->ev1, b->stream));
+            b->sync();
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, b->ev0, b->ev1));
+            t[ord] = ms;
+        }
+        b->class_order[k] = t[1] < t[0] ? 1 : 0;
+        if (b->class_order[k]) b->items_all[k].swap(b->items_alt[k]);
+        b->items_alt[k].release();
     }
 }
 
@@ -497,6 +535,7 @@ extern "C" mgx_status mgx_batch_get_stats(mgx_batch *b, mgx_batch_stats *out)
         b->st.class_items[k] = b->class_nitems[k];
         b->st.class_threads[k] = b->class_nitems[k] ? b->class_threads[k] : 0;
         b->st.class_chunk[k] = b->class_nitems[k] ? b->class_ch[k] : 0;
+        b->st.class_order[k] = b->class_nitems[k] ? b->class_order[k] : 0;
     }
     *out = b->st;
     API_END(b)

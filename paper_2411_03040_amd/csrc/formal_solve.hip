@@ -678,8 +678,10 @@ void k_formal_solve(FSArgs<T> a, int ch)
 }
 
 // Batched launch: one workgroup per work item (model, origin, line chunk) of
-// one lane class, items ordered longest first so the dispatcher hands out the
-// heavy ones early; workgroups past the live item count or of converged
+// one lane class, items in the order the tuner picked for the class (longest
+// first, so the dispatcher hands out the heavy ones early, or by model and
+// Morton origin, so workgroups that share an XCD's L2 gather neighbouring
+// points); workgroups past the live item count or of converged
 // (inactive) models return at once.  The descriptor of the item's model
 // replaces the kernel-argument descriptor of the single-model launch.  (Lane
 // classes mix models, so the one-width reuse is not used here; it changes

@@ -8,6 +8,7 @@
 
 #include <functional>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/mgx.h"
@@ -65,6 +66,11 @@ struct DMem {
     T *as() const
     {
         return (T *)p;
+    }
+    void swap(DMem &o)
+    {
+        std::swap(p, o.p);
+        std::swap(bytes, o.bytes);
     }
 };
 
@@ -300,6 +306,9 @@ void render_image(mgx_ctx *ctx, RenderBufs &rb, const double *pops, hipStream_t 
                   float *img);
 // device bytes held by a context
 size_t ctx_bytes(const mgx_ctx *ctx);
+// points 0..N-1 in Morton (Z-curve) order of their positions ([3][N]), 10
+// bits per axis over the bounding box, ties by index
+std::vector<int32_t> morton_order(const double *pos, int N);
 
 }  // namespace mgxh
 
@@ -321,9 +330,13 @@ struct mgx_batch {
     bool prepared = false, tuned = false;
     // device tables
     DMem descs, active, all_active, changes, cnt_ptrs, counts, tune_count;
-    // work items per class: every item in longest-first order, and the items
-    // of the models still iterating (same order; *counts[k] of them)
+    // work items per class: every item in the tuned order (longest first, or
+    // by model and Morton origin), and the items of the models still
+    // iterating (same order; *counts[k] of them)
     DMem items_all[MGX_BATCH_CLASSES], items[MGX_BATCH_CLASSES];
+    // the same items by model, origin in Morton order and line chunk (the
+    // tuner keeps the faster order in items_all; freed after tuning)
+    DMem items_alt[MGX_BATCH_CLASSES];
     DMem sample[MGX_BATCH_CLASSES];  // strided sample of the items, for tuning
     int class_nsample[MGX_BATCH_CLASSES] = {};
     void *select_tmp = nullptr;
@@ -335,6 +348,7 @@ struct mgx_batch {
     int class_nlc_max[MGX_BATCH_CLASSES] = {};
     int class_nb_max[MGX_BATCH_CLASSES] = {};
     int class_ch[MGX_BATCH_CLASSES] = {};
+    int class_order[MGX_BATCH_CLASSES] = {};  // 0 longest first, 1 by model and origin
     int64_t work_items = 0;
     std::vector<int> host_active;
     std::vector<BatchRun> runs;

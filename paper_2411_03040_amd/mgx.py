@@ -61,7 +61,7 @@ class BatchStats(C.Structure):
     _fields_ = [("models", C.c_int), ("active", C.c_int), ("iterations", C.c_int),
                 ("lane_classes", C.c_int), ("work_items", C.c_int64),
                 ("class_items", C.c_int * 16), ("class_threads", C.c_int * 16),
-                ("class_chunk", C.c_int * 16),
+                ("class_chunk", C.c_int * 16), ("class_order", C.c_int * 16),
                 ("tune_seconds", C.c_double),
                 ("iterate_seconds", C.c_double), ("last_converged_seconds", C.c_double),
                 ("updates_per_iteration", C.c_int64),
