@@ -779,8 +779,8 @@ hipError_t launch_formal_solve(const FSArgs<T> &a, hipStream_t s)
     const LDSLayout L = lds_layout<T>(ch, a.nlc, a.nbins, a.nthreads);
     const int nchunks = (a.nlines + a.nlc - 1) / a.nlc;
     dim3 grid(a.N, nchunks);
-    // double keeps more state live per lane: a 512-thread bound leaves it 256
-    // VGPRs (no spills); 1024 only when one line has more than 512 bins
+    // FP64 workgroups of at most 512 threads take the 512-thread bound (the
+    // same 128 VGPRs as the 1024 bound under the four-wave cap)
     if constexpr (sizeof(T) == 8) {
         if (a.nthreads <= 512) {
             launch_fs_variant<T, 512>(a, grid, L.total, ch, s);

@@ -85,7 +85,7 @@ def test_batch_equals_single_context(mgx, prec, tol):
     assert nconv == len(models)
     assert st["lane_classes"] == len(used) >= 5
     assert sum(st["class_items"]) == st["work_items"] == sum(
-        m.npoints * -(-m.nlines // max(1, min(m.nlines, (512 if prec == 0 else 1024) // m.nbins)))
+        m.npoints * -(-m.nlines // max(1, min(m.nlines, 1024 // m.nbins)))
         for m in models)
     assert st["iterations"] == int(its.max())
     for i, m in enumerate(models):
