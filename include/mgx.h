@@ -235,9 +235,9 @@ mgx_status mgx_formal_solve(mgx_ctx *ctx, double *Jbar, double *Lstar);
 /* Launch shape the formal solution uses for a model with `nlines` lines of
    `nbins` bins in `precision`: lines per workgroup (line chunk), threads per
    workgroup, and LDS bytes per workgroup at the record chunk the launch
-   picks (at most 80 KiB: the largest chunk that lets the workgroups the
-   registers allow share a CU's 160 KiB).  A host-only query (no device
-   needed).  Errors: MGX_EINVAL. */
+   picks (the largest chunk that lets the workgroups the registers allow
+   share a CU's 160 KiB).  A host-only query (no device needed).
+   Errors: MGX_EINVAL. */
 mgx_status mgx_formal_solve_shape(int precision, int nlines, int nbins, int *lines_per_chunk,
                                   int *threads, int64_t *lds_bytes);
 

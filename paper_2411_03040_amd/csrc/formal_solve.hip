@@ -709,20 +709,20 @@ template size_t formal_solve_lds<double>(int, int, int, int);
 
 // The LDS a workgroup may take: 160 KiB shared by the workgroups the
 // registers let a CU hold (about 28 waves in FP32, 16 in FP64; whole
-// workgroups only), at most 80 KiB.  The chunk is then the largest that
-// fits, in steps of 8 records: a record chunk ends in a barrier and a wait on
-// the next chunk's gathers that only the CU's other workgroups can cover, so
-// fewer, larger chunks matter more than one more resident workgroup
-// (clumpy cloud, two 12-wave workgroups per CU: 56 records per half, 109
-// against 116 ms with 32; outflow, five 5-wave workgroups: 32 against 16,
-// 9.1 against 10.5 ms).
+// workgroups only).  The chunk is then the largest that fits, in steps of 8
+// records: a record chunk ends in a barrier and a wait on the next chunk's
+// gathers that only the CU's other workgroups can cover, so fewer, larger
+// chunks matter more than one more resident workgroup (clumpy cloud, two
+// 12-wave workgroups per CU: 56 records per half, 109 against 116 ms with
+// 32; outflow, five 5-wave workgroups: 32 against 16, 9.1 against 10.5 ms;
+// FP64 clumpy cloud, one workgroup per CU with 148 KiB: 56 against 24, 326
+// against 359 ms).
 static size_t lds_budget(int nthreads, int target_waves)
 {
     const int waves = (nthreads + 63) / 64;
     int wgs = target_waves / waves;
     if (wgs < 1) wgs = 1;
-    const size_t b = (size_t)160 * 1024 / wgs - 1024;
-    return b < (size_t)80 * 1024 ? b : (size_t)80 * 1024;
+    return (size_t)160 * 1024 / wgs - 1024;
 }
 
 template <typename T>
