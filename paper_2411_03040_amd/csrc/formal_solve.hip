@@ -33,11 +33,12 @@
 // Launch shape: one workgroup per (origin, chunk of lines); one lane per
 // (line, bin) of the chunk, so a line's bins sit in adjacent lanes and the
 // per-point line data of one record is a broadcast for most of a wave.  The
-// workgroup walks the ray pairs of its origin; each pair's records (point,
-// segment length, projected velocity, 1/b-bar, branch bit) and the gathered
-// per-point opacity and source factors of the chunk's lines are staged in
-// LDS in chunks of CH records per half, farthest first, and both halves are
-// swept in the same loop (two independent dependency chains per lane).
+// workgroup walks the ray pairs of its origin; each pair's records are staged
+// in LDS in chunks of CH records per half, farthest first -- per record and
+// line the gathered opacity and source factors, per record and bin the
+// profile and erf-difference factors, computed once for all lines -- and
+// both halves are swept in the same loop (two independent dependency chains
+// per lane).
 // Reductions over bins happen once per origin in LDS in a fixed order (no
 // atomics: bit-reproducible).
 
@@ -333,16 +334,15 @@ struct HalfState {
 // spill outside the sweeps); one-width models keep their 67 (seven waves,
 // which for their 12-wave workgroups is the same two workgroups per CU as
 // eight).  Every FP64 launch is held to 128 VGPRs (four waves).
+// ONE_WIDTH: the model has one Doppler width everywhere (T and v_turb the
+// same at every point); it selects only this cap.
 template <typename T, bool ONE_WIDTH>
 constexpr int kWavesPerEu = sizeof(T) == 4 ? (ONE_WIDTH ? 7 : 8) : 4;
 
 // One origin x line chunk, executed by the whole workgroup (blockDim.x
 // threads, at least nlc * nbins).  Shared by the single-model launch and the
-// persistent batched launch, so both give bit-identical results.  ONE_WIDTH:
-// the model has one Doppler width everywhere (erfc values are then reused
-// between consecutive semi-analytic segments; exact, so results do not
-// depend on it).
-template <typename T, bool ONE_WIDTH>
+// persistent batched launch, so both give bit-identical results.
+template <typename T>
 __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, const int chunk,
                                              const int ch, unsigned char *smem)
 {
@@ -671,9 +671,9 @@ void k_formal_solve(FSArgs<T> a, int ch)
         // loaded, so uniform only by construction: say so, or every address
         // derived from the origin becomes per-lane
         const int o = __builtin_amdgcn_readfirstlane(a.order[x * q + min(x, r) + b / kXcds]);
-        solve_origin<T, ONE_WIDTH>(a, o, blockIdx.y, ch, smem);
+        solve_origin<T>(a, o, blockIdx.y, ch, smem);
     } else {
-        solve_origin<T, ONE_WIDTH>(a, blockIdx.x, blockIdx.y, ch, smem);
+        solve_origin<T>(a, blockIdx.x, blockIdx.y, ch, smem);
     }
 }
 
@@ -684,8 +684,8 @@ void k_formal_solve(FSArgs<T> a, int ch)
 // points); workgroups past the live item count or of converged
 // (inactive) models return at once.  The descriptor of the item's model
 // replaces the kernel-argument descriptor of the single-model launch.  (Lane
-// classes mix models, so the one-width reuse is not used here; it changes
-// no result.)
+// classes mix models, so it takes the register cap of models with more than
+// one Doppler width.)
 template <typename T, int MAXT>
 __global__ __launch_bounds__(MAXT) __attribute__((amdgpu_waves_per_eu(kWavesPerEu<T, false>)))
 void k_formal_solve_batch(const FSArgs<T> *__restrict__ descs, const int4 *__restrict__ items,
@@ -696,7 +696,7 @@ void k_formal_solve_batch(const FSArgs<T> *__restrict__ descs, const int4 *__res
     if (it >= *count) return;
     const int4 w = items[it];
     if (!active[w.x]) return;
-    solve_origin<T, false>(descs[w.x], w.y, w.z, ch, smem);
+    solve_origin<T>(descs[w.x], w.y, w.z, ch, smem);
 }
 
 template <typename T>
