@@ -161,9 +161,9 @@ hipError_t launch_formal_solve(const FSArgs<T> &a, hipStream_t s);
 // batched: one workgroup per (model, origin, line chunk) item of a lane class
 template <typename T>
 size_t formal_solve_lds(int ch, int nlc, int nb, int nthreads);
-// records per half staged at once: the largest power of two <= 64 whose LDS
-// fits the workgroup's share of a CU (at most 60 KiB; down to 1 for very
-// wide bin sets)
+// records per half staged at once: the largest chunk (steps of 8 records,
+// at most 64; down to 1 for very wide bin sets) whose LDS fits the share of a
+// CU's 160 KiB that the workgroups its registers allow leave each
 template <typename T>
 int formal_solve_chunk(int nlc, int nb, int nthreads);
 template <typename T>
