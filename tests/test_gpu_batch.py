@@ -81,9 +81,18 @@ def test_batch_equals_single_context(mgx, prec, tol):
     say(f"  iters {its.tolist()} classes {[st['class_threads'][k] for k in used]} "
         f"items {[st['class_items'][k] for k in used]} "
         f"chunk {[st['class_chunk'][k] for k in used]} "
+        f"order {[st['class_order'][k] for k in used]} "
         f"tune {st['tune_seconds']:.2f}s")
     assert nconv == len(models)
     assert st["lane_classes"] == len(used) >= 5
+    # the tuned schedule: a chunk of 1..64 records and one of the two item
+    # orders for every used class, nothing for the unused ones (the results
+    # below equal the lone contexts' bit for bit whichever order was kept)
+    for k in range(16):
+        if k in used:
+            assert 1 <= st["class_chunk"][k] <= 64 and st["class_order"][k] in (0, 1)
+        else:
+            assert st["class_chunk"][k] == 0 and st["class_order"][k] == 0
     assert sum(st["class_items"]) == st["work_items"] == sum(
         m.npoints * -(-m.nlines // max(1, min(m.nlines, 1024 // m.nbins)))
         for m in models)
