@@ -708,15 +708,17 @@ template size_t formal_solve_lds<float>(int, int, int, int);
 template size_t formal_solve_lds<double>(int, int, int, int);
 
 // The LDS a workgroup may take: 160 KiB shared by the workgroups the
-// registers let a CU hold (about 28 waves in FP32, 16 in FP64; whole
-// workgroups only).  The chunk is then the largest that fits, in steps of 8
+// registers let a CU hold (whole workgroups only; measured targets of 28
+// waves per CU in FP32 and 12 in FP64, whose four waves per SIMD hold only
+// two 5-wave workgroups: a workgroup's waves are spread unevenly over the
+// four SIMDs).  The chunk is then the largest that fits, in steps of 8
 // records: a record chunk ends in a barrier and a wait on the next chunk's
 // gathers that only the CU's other workgroups can cover, so fewer, larger
 // chunks matter more than one more resident workgroup (clumpy cloud, two
 // 12-wave workgroups per CU: 56 records per half, 109 against 116 ms with
 // 32; outflow, five 5-wave workgroups: 32 against 16, 9.1 against 10.5 ms;
 // FP64 clumpy cloud, one workgroup per CU with 148 KiB: 56 against 24, 326
-// against 359 ms).
+// against 359 ms; FP64 outflow, two workgroups: 33.9 against 35.7 ms).
 static size_t lds_budget(int nthreads, int target_waves)
 {
     const int waves = (nthreads + 63) / 64;
@@ -728,7 +730,7 @@ static size_t lds_budget(int nthreads, int target_waves)
 template <typename T>
 int formal_solve_chunk(int nlc, int nb, int nthreads)
 {
-    const size_t budget = lds_budget(nthreads, sizeof(T) == 4 ? 28 : 16);
+    const size_t budget = lds_budget(nthreads, sizeof(T) == 4 ? 28 : 12);
     int ch = 64;
     while (lds_layout<T>(ch, nlc, nb, nthreads).total > budget && ch > 1) ch -= ch > 8 ? 8 : 1;
     return ch;
