@@ -42,6 +42,8 @@
 // Reductions over bins happen once per origin in LDS in a fixed order (no
 // atomics: bit-reproducible).
 
+#include <cfloat>
+
 #include "mgx_internal.h"
 
 // Multiply-adds are fused only where one source expression writes them, so
@@ -114,13 +116,16 @@ struct FM<double> {
     static __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
     // 1 / x for x >= 1 (finite or +inf): the hardware estimate refined by two
     // Newton steps (within an ulp; the argument range rules out the
-    // operands IEEE division guards against)
+    // operands IEEE division guards against).  An infinite x is clamped to
+    // the largest double first, whose reciprocal is subnormal: 0 to within
+    // 2^-1022, where the Newton steps on x itself would give NaN.
     static __device__ __forceinline__ double rcp_ge1(double x)
     {
+        x = fmin(x, DBL_MAX);
         double r = __builtin_amdgcn_rcp(x);
         r = fma(r, fma(-x, r, 1.0), r);
         r = fma(r, fma(-x, r, 1.0), r);
-        return isinf(x) ? 0.0 : r;
+        return r;
     }
     static constexpr double erf_scale = 1.0;
     // erfc for x >= 0, branch-free: the product form erfc(x) = t exp(P(t) -
@@ -157,9 +162,10 @@ struct FM<double> {
     }
 
     static __device__ __forceinline__ double expm1_(double x) { return expm1(x); }
+    // max(x, lo) for lo > 0 and x >= 0: one maximum instruction
     static __device__ __forceinline__ double at_least(double x, double lo)
     {
-        return x > lo ? x : lo;
+        return fmax(x, lo);
     }
 };
 
