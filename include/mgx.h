@@ -74,7 +74,7 @@ typedef struct {
        "Semi-analytical approximation for line optical depths"; 0.35).  At
        least MGX_MIN_BRANCH_THRESHOLD. */
     double branch_threshold;
-    double tau_floor;     /* lower bound on a segment optical depth (1e-15)  */
+    double tau_floor;     /* added to every segment optical depth (1e-15)    */
     double chi_min;       /* masing clamp on chi^ij [m^-1 Hz] (1e-30)         */
     double pop_floor;     /* floor of the relative-change denominator (1e-12) */
     /* 3D traces search each walk once and keep its points in a temporary of

@@ -467,7 +467,7 @@ void orc_solve_origin(const orc_model *m, const double *chi_ij, const double *S,
                     } else {
                         dt = orc_dtau_trapezoid(dx, chig[j], chig[j + 1]);
                     }
-                    if (dt < m->tau_floor) dt = m->tau_floor;
+                    dt += m->tau_floor;  /* keeps every segment depth positive */
                     dtau[j] = dt;
                 }
                 const double I0 = orc_planck(nug[0], m->Tcmb);

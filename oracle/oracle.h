@@ -40,7 +40,7 @@ typedef struct {
     double xmax;
     double Tcmb;
     double branch_threshold; /* trapezoid below this Doppler shift in widths */
-    double tau_floor;        /* lower bound on a segment optical depth       */
+    double tau_floor;        /* added to every segment optical depth         */
     double chi_min;          /* masing clamp on the line opacity factor      */
     double pop_floor;        /* floor of the relative-change denominator     */
 } orc_model;

@@ -10,7 +10,8 @@
 //  * Segment optical depth: trapezoidal rule, or the semi-analytic form
 //    dtau = dx (chi^ij_0 + chi^ij_1)/2 (erf(x1) - erf(x0)) / (2 dnu_bar
 //    (x1 - x0)) where the segment's Doppler shift reaches the threshold
-//    (semi-analytic optical depth equation); floored at tau_floor.
+//    (semi-analytic optical depth equation); plus tau_floor, which keeps
+//    every segment depth positive.
 //  * Second-order Feautrier system on the pair grid, eliminated from both
 //    far ends towards the origin with O(1) state per lane.  With the
 //    scaled unknowns f_j = F_j / dtau_{j+1/2} and e_j / dtau_{j+1/2} of the
@@ -102,12 +103,6 @@ struct FM<float> {
         const float s = x * fmaf(x, fmaf(x, fmaf(x, 1.0f / 24.0f, 1.0f / 6.0f), 0.5f), 1.0f);
         return fabsf(x) < 0.1f ? s : e;
     }
-    // max(x, lo) for lo > 0 and x >= 0 (or -0): IEEE bit patterns of
-    // non-negative floats order like signed integers, one integer max
-    static __device__ __forceinline__ float at_least(float x, float lo)
-    {
-        return __int_as_float(max(__float_as_int(x), __float_as_int(lo)));
-    }
 };
 
 template <>
@@ -162,11 +157,6 @@ struct FM<double> {
     }
 
     static __device__ __forceinline__ double expm1_(double x) { return expm1(x); }
-    // max(x, lo) for lo > 0 and x >= 0: one maximum instruction
-    static __device__ __forceinline__ double at_least(double x, double lo)
-    {
-        return fmax(x, lo);
-    }
 };
 
 // erf(b) - erf(a) from ea = erfc(|a|) and eb = erfc(|b|) (arguments scaled
@@ -423,9 +413,9 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
     // semi-analytic
     //   dt/2 = dx sqrt(pi)/8 (cb_P + cb_Q) (erf x_Q - erf x_P) / (b-bar (x_Q - x_P)),
     // both as the far end's term plus unQ times the near-end bin factor.
-    // Floored at tau_floor / 2.
+    // The far end's term carries tau_floor / 2 (visit below).
     auto segment = [&](const HalfState<T> &st, T unQ) -> T {
-        return FM<T>::at_least(unQ * st.vn + st.a, half_floor);
+        return unQ * st.vn + st.a;
     };
 
     double accJ = 0.0, accL = 0.0;
@@ -461,7 +451,7 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
                 s.eps = bdy_I(dv);
             else
                 row(s, segment(s, un), Sn);
-            s.a = uf * vf;
+            s.a = uf * vf + half_floor;  // one multiply-add
             s.vn = vn;
         };
 

@@ -193,8 +193,8 @@ def _reference(m, n, oc, *, quad_linear, mirror=True, cmb_comoving=True):
                         phi1 = mpmath.exp(-x[j + 1] ** 2) / (nul * b[p1] / c *
                                                              mpmath.sqrt(mpmath.pi))
                         dt = dx * (chi[p0][l] * phi0 + chi[p1][l] * phi1) / 2
-                    # optical-depth floor (far-wing lanes of the shifted halves)
-                    dtau.append(max(dt, mpmath.mpf("1e-15")))
+                    # optical-depth floor, added (far-wing lanes of the shifted halves)
+                    dtau.append(dt + mpmath.mpf("1e-15"))
                 Tc = mpmath.mpf(m.Tcmb)
                 if cmb_comoving:
                     I0, IM = _planck_mp(nup[0], Tc), _planck_mp(nup[M], Tc)
