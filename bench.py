@@ -132,7 +132,7 @@ def alu_roofline(ctx, m, ms_per_launch, precision):
     # offsets, the per-point line table (chi', S' in the solve precision)
     # and per-point widths once, J-bar and Lambda* written once (FP64)
     tsz = 4 if precision == "fp32" else 8
-    rec_bytes = 16 if precision == "fp32" else 32
+    rec_bytes = 24 if precision == "fp32" else 48
     alg_bytes = (c["total_records"] * rec_bytes + (m.npoints * m.nrays + 1) * 8 +
                  m.npoints * m.nlines * 2 * tsz + m.npoints * 2 * tsz +
                  m.npoints * m.nlines * 2 * 8)

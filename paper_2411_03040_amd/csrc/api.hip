@@ -436,6 +436,7 @@ extern "C" mgx_status mgx_trace_rays(mgx_ctx *ctx, int64_t *total_records_out)
     const bool f32 = ctx->fp32();
     ctx->rec.ensure((f32 ? sizeof(Rec<float>) : sizeof(Rec<double>)) * n);
     HIPCHK(launch_pack_trace(total, ctx->r_idx.as<int32_t>(), ctx->r_semi.as<uint8_t>(),
+                             f32 ? ctx->bf.p : ctx->bd.p, f32 ? ctx->ibf.p : ctx->ibd.p,
                              ctx->r_dx.as<double>(), ctx->r_dv.as<double>(),
                              ctx->r_ibb.as<double>(), 1.0 / ctx->L_unit, f32, ctx->rec.p,
                              ctx->stream));

@@ -219,6 +219,11 @@ __device__ __forceinline__ T erf_diff(T a, T b, T ea, T eb)
 // the lines and bins one wave reads fall in different banks: the two records
 // of an unrolled step share one address with immediate offsets (FP64: 436
 // against 473 ms per clumpy-cloud solve; the same order costs FP32 6 %).
+// Line gathers a staging thread issues ahead of the bin arithmetic: one in
+// FP32 (more raise the staging's register peak above the sweep's), none in
+// FP64, whose staging registers would spill.
+template <typename T>
+constexpr int kLineAhead = sizeof(T) == 4 ? 1 : 0;
 template <typename T>
 constexpr bool kRowsByRecord = sizeof(T) == 8;
 template <typename T>
@@ -276,15 +281,20 @@ __host__ __device__ inline LDSLayout lds_layout(int ch, int nlc, int nb, int nth
 // Trace records are read once per launch: stream them past the L2 (non-
 // temporal) so they do not evict the per-point line table the gathers reuse.
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v2i __attribute__((ext_vector_type(2)));
+typedef int v4i_a8 __attribute__((ext_vector_type(4), aligned(8)));
 
 __device__ __forceinline__ Rec<float> load_stream(gptr<Rec<float>> p)
 {
-    const v4i v = __builtin_nontemporal_load((gptr<v4i>)p);
+    const v4i v = __builtin_nontemporal_load((gptr<v4i_a8>)p);
+    const v2i w = __builtin_nontemporal_load((gptr<v2i>)p + 2);
     Rec<float> r;
     r.ps = v.x;
     r.dx = __int_as_float(v.y);
-    r.dv = __int_as_float(v.z);
-    r.ibb = __int_as_float(v.w);
+    r.ibb = __int_as_float(v.z);
+    r.b = __int_as_float(v.w);
+    r.dv = __int_as_float(w.x);
+    r.ib = __int_as_float(w.y);
     return r;
 }
 
@@ -292,12 +302,15 @@ __device__ __forceinline__ Rec<double> load_stream(gptr<Rec<double>> p)
 {
     const v4i v0 = __builtin_nontemporal_load((gptr<v4i>)p);
     const v4i v1 = __builtin_nontemporal_load((gptr<v4i>)p + 1);
+    const v4i v2 = __builtin_nontemporal_load((gptr<v4i>)p + 2);
     Rec<double> r;
     r.ps = v0.x;
     r.pad = 0;
     r.dx = __hiloint2double(v0.w, v0.z);
-    r.dv = __hiloint2double(v1.y, v1.x);
-    r.ibb = __hiloint2double(v1.w, v1.z);
+    r.ibb = __hiloint2double(v1.y, v1.x);
+    r.b = __hiloint2double(v1.w, v1.z);
+    r.dv = __hiloint2double(v2.y, v2.x);
+    r.ib = __hiloint2double(v2.w, v2.z);
     return r;
 }
 
@@ -387,6 +400,8 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
     };
     // the boundary intensity at the origin (an empty half's)
     const T I_o = bdy_I((T)0);
+    // 1/b at the origin (the near end of each half's last segment)
+    const T ib_o = ibpt[o];
 
     // staging columns, fixed per thread so the loops need no division:
     // line li of records le0, le0 + lrows, ...; bin f (the lane's own) of
@@ -476,17 +491,17 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
                 sr.dv = rc.dv;
                 if (k > 0) {
                     sr.dvm = rec[base + k - 1].dv;
-                    sr.ibm = ibpt[rec[base + k - 1].ps & 0x7fffffff];
+                    sr.ibm = rec[base + k - 1].ib;
                 } else {  // the origin, dv = 0
                     sr.dvm = (T)0;
-                    sr.ibm = ibpt[o];
+                    sr.ibm = ib_o;
                 }
-                sr.ib = ibpt[p];
+                sr.ib = rc.ib;
                 sr.sibb = rc.ibb * (T)FM<T>::erf_scale;
                 // semi-analytic: half its lane-independent factor; trapezoidal:
                 // a quarter of its length
                 sr.rw = semi ? rc.dx * half : rc.dx * (T)0.25;
-                sr.b = bpt[p];
+                sr.b = rc.b;
                 sr.p = p;
                 const int psn = k + 1 < n ? rec[base + k + 1].ps : 0;
                 sr.pn = k + 1 < n ? psn & 0x7fffffff : -1;
@@ -497,18 +512,22 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
                 s_a[t] = ma;
             }
             __syncthreads();
-            for (int e = le0; e < cnt; e += lrows) {
-                const int li = li_s;
-                const StageRec<T> &sr = s_st[e];
-                const int64_t idx = (int64_t)sr.p * nl + l0 + li;
-                LineRec<T> lr;
-                const T chi_l = chi[idx];
-                const T cb = chi_l * sr.b;
-                lr.uf = (sr.form & 1) ? cb : chi_l;
-                lr.un = (sr.form & 2) ? cb : chi_l;
-                lr.Sn = sr.pn >= 0 ? S[(int64_t)sr.pn * nl + l0 + li] : (T)0;
-                lr.S = S[idx];
-                s_line[li * LY.ls + e * LY.le] = lr;
+            // per (record, line): the gathers of the thread's first
+            // kLineAhead records are issued before the bin factors below
+            // are computed, and stored after them, so that arithmetic
+            // covers their latency
+            constexpr int kA = kLineAhead<T> > 0 ? kLineAhead<T> : 1;
+            T g_chi[kA], g_S[kA], g_Sn[kA];
+    #pragma unroll
+            for (int j = 0; j < kLineAhead<T>; j++) {
+                const int e = le0 < cnt ? le0 + j * lrows : cnt;
+                if (e < cnt) {
+                    const StageRec<T> &sr = s_st[e];
+                    const int64_t idx = (int64_t)sr.p * nl + l0 + li_s;
+                    g_chi[j] = chi[idx];
+                    g_S[j] = S[idx];
+                    g_Sn[j] = sr.pn >= 0 ? S[(int64_t)sr.pn * nl + l0 + li_s] : (T)0;
+                }
             }
             // per (record, bin): the bin factors of the segment towards the
             // origin (P this record, Q the next one)
@@ -528,6 +547,28 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
                     br.vn = sr.rw * FM<T>::phi_of(uQ * sr.ibm);
                 }
                 s_bin[f * LY.bs + e * LY.be] = br;
+            }
+            auto line_rec = [&](const StageRec<T> &sr, T chi_l, T S_l, T Sn_l) {
+                LineRec<T> lr;
+                const T cb = chi_l * sr.b;
+                lr.uf = (sr.form & 1) ? cb : chi_l;
+                lr.un = (sr.form & 2) ? cb : chi_l;
+                lr.Sn = Sn_l;
+                lr.S = S_l;
+                return lr;
+            };
+    #pragma unroll
+            for (int j = 0; j < kLineAhead<T>; j++) {
+                const int e = le0 < cnt ? le0 + j * lrows : cnt;
+                if (e < cnt)
+                    s_line[li_s * LY.ls + e * LY.le] = line_rec(s_st[e], g_chi[j], g_S[j], g_Sn[j]);
+            }
+            // the rest of the thread's records
+            for (int e = le0 < cnt ? le0 + kLineAhead<T> * lrows : cnt; e < cnt; e += lrows) {
+                const StageRec<T> &sr = s_st[e];
+                const int64_t idx = (int64_t)sr.p * nl + l0 + li_s;
+                const T Sn_l = sr.pn >= 0 ? S[(int64_t)sr.pn * nl + l0 + li_s] : (T)0;
+                s_line[li_s * LY.ls + e * LY.le] = line_rec(sr, chi[idx], S[idx], Sn_l);
             }
             __syncthreads();
             // record k of half A is staged at eA + k, of half B at eB + k; a

@@ -54,20 +54,23 @@ struct Counters {
 // Packed trace record used by the formal solution: point index with the
 // semi-analytic flag in bit 31; for a trapezoidal segment its length from
 // the previous record (or the origin), for a semi-analytic one
-// dx sqrt(pi)/4 / (dv_prev - dv) (both scaled by 1/L_unit); the projected
-// velocity difference to the origin; 1/b-bar of the segment.
+// dx sqrt(pi)/4 / (dv_prev - dv) (both scaled by 1/L_unit); 1/b-bar of the
+// segment; the point's Doppler width b; the projected velocity difference to
+// the origin and the point's 1/b (scaled as the solve's per-point table),
+// adjacent so the record after this one reads both with one load.  Carrying
+// the point's widths saves the staging a dependent gather.
 template <typename T>
 struct Rec;
 template <>
-struct alignas(16) Rec<float> {
+struct alignas(8) Rec<float> {
     int32_t ps;
-    float dx, dv, ibb;
+    float dx, ibb, b, dv, ib;
 };
 template <>
 struct alignas(16) Rec<double> {
     int32_t ps;
     int32_t pad;
-    double dx, dv, ibb;
+    double dx, ibb, b, dv, ib;
 };
 
 struct TraceArgs {
@@ -153,7 +156,7 @@ hipError_t launch_trace_emit(const TraceArgs &a, hipStream_t s);
 hipError_t launch_pack_vel4(int N, const double *vel, const double *b2, double4 *out,
                             hipStream_t s);
 hipError_t launch_pack_trace(int64_t n, const int32_t *idx, const uint8_t *semi,
-                             const double *dx, const double *dv, const double *ibb,
+                             const void *bpt, const void *ibpt, const double *dx, const double *dv, const double *ibb,
                              double inv_L, bool fp32, void *out, hipStream_t s);
 hipError_t launch_line_coeffs(const LineArgs &a, hipStream_t s);
 template <typename T>

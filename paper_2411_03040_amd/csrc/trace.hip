@@ -307,51 +307,43 @@ hipError_t launch_pack_vel4(int N, const double *vel, const double *b2, double4 
     return hipGetLastError();
 }
 
-// Convert the double-precision trace into the packed records of the solve.
+// Convert the double-precision trace into the packed records of the solve,
+// with the point's widths from the solve-precision per-point tables.
 template <typename T>
 __global__ void k_pack(int64_t n, const int32_t *__restrict__ idx,
-                       const uint8_t *__restrict__ semi, const double *__restrict__ dx,
+                       const uint8_t *__restrict__ semi, const T *__restrict__ bpt,
+                       const T *__restrict__ ibpt, const double *__restrict__ dx,
                        const double *__restrict__ dv, const double *__restrict__ ibb,
                        double inv_L, Rec<T> *__restrict__ out)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const int32_t p = idx[i];
     Rec<T> r;
-    r.ps = idx[i] | (semi[i] ? (int32_t)0x80000000u : 0);
+    r.ps = p | (semi[i] ? (int32_t)0x80000000u : 0);
+    if constexpr (sizeof(T) == 8) r.pad = 0;
     r.dx = (T)(dx[i] * inv_L);
-    r.dv = (T)dv[i];
     r.ibb = (T)ibb[i];
-    out[i] = r;
-}
-
-template <>
-__global__ void k_pack<double>(int64_t n, const int32_t *__restrict__ idx,
-                               const uint8_t *__restrict__ semi, const double *__restrict__ dx,
-                               const double *__restrict__ dv, const double *__restrict__ ibb,
-                               double inv_L, Rec<double> *__restrict__ out)
-{
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    Rec<double> r;
-    r.ps = idx[i] | (semi[i] ? (int32_t)0x80000000u : 0);
-    r.pad = 0;
-    r.dx = dx[i] * inv_L;
-    r.dv = dv[i];
-    r.ibb = ibb[i];
+    r.b = bpt[p];
+    r.dv = (T)dv[i];
+    r.ib = ibpt[p];
     out[i] = r;
 }
 
 hipError_t launch_pack_trace(int64_t n, const int32_t *idx, const uint8_t *semi,
-                             const double *dx, const double *dv, const double *ibb,
-                             double inv_L, bool fp32, void *out, hipStream_t s)
+                             const void *bpt, const void *ibpt, const double *dx,
+                             const double *dv, const double *ibb, double inv_L, bool fp32,
+                             void *out, hipStream_t s)
 {
     if (n == 0) return hipSuccess;
     const int64_t blocks = (n + 255) / 256;
     if (fp32)
-        k_pack<float><<<blocks, 256, 0, s>>>(n, idx, semi, dx, dv, ibb, inv_L,
+        k_pack<float><<<blocks, 256, 0, s>>>(n, idx, semi, (const float *)bpt,
+                                            (const float *)ibpt, dx, dv, ibb, inv_L,
                                             (Rec<float> *)out);
     else
-        k_pack<double><<<blocks, 256, 0, s>>>(n, idx, semi, dx, dv, ibb, inv_L,
+        k_pack<double><<<blocks, 256, 0, s>>>(n, idx, semi, (const double *)bpt,
+                                             (const double *)ibpt, dx, dv, ibb, inv_L,
                                              (Rec<double> *)out);
     return hipGetLastError();
 }
