@@ -182,13 +182,15 @@ __device__ __forceinline__ T erf_diff(T a, T b, T ea, T eb)
 // staging pass therefore computes them once per (record, bin) and every
 // line's lanes read them; the per-point line data is staged per (record,
 // line).  Both forms of a segment's half depth are a sum over its two ends of
-// a line factor times a bin factor,
+// the point's line factor chi' times a bin factor,
 //   trapezoidal:    h = chi'_P (q phi_P) + chi'_Q (q phi_Q),  q = dx / 4,
-//   semi-analytic:  h = (chi'b)_P W + (chi'b)_Q W,
-// with W the segment's erf difference times its factor (below), so staging
-// picks each end's factors by the segment's form and the sweep evaluates one
-// multiply-add, the same for every segment.  Segment k runs from record k to
-// record k - 1 (the next one towards the origin, or the origin itself):
+//   semi-analytic:  h = chi'_P (b_P W) + chi'_Q (b_Q W),
+// with W the segment's erf difference times its factor (below): the point's
+// Doppler width b, which the semi-analytic form weights each end's opacity
+// with, rides in the bin factor, so a point has one line factor whatever the
+// forms of its two segments, and the sweep evaluates one multiply-add, the
+// same for every segment.  Segment k runs from record k to record k - 1 (the
+// next one towards the origin, or the origin itself):
 //  * MetaA (per record): dv, read by the sweep only at a ray's far end (the
 //    boundary intensity's comoving frequency).
 //  * StageRec (per record, staging only): dv here and at the next record
@@ -196,22 +198,26 @@ __device__ __forceinline__ T erf_diff(T a, T b, T ea, T eb)
 //    the profile), 1/b-bar of the segment (times erf_scale), the segment's
 //    lane-independent factor (trapezoidal: a quarter of its length;
 //    semi-analytic: half of dx sqrt(pi)/4 / (dv_Q - dv_P), which the trace
-//    computed in FP64 and stored in place of the length), b, the point
-//    indices here and at the record beyond (-1 past the far end), and the
-//    forms of the segment that starts here and of the one that ends here
-//    (from the record beyond).
-//  * LineRec (per record and line): the line factor of this point as the far
-//    end of its own segment (uf) and as the near end of the segment from the
-//    record beyond (un): chi' b for a semi-analytic segment, chi' for a
-//    trapezoidal one; S' at the record beyond (the elimination row of this
-//    visit crosses that point) and S' here (read at the origin's row only).
+//    computed in FP64 and stored in place of the length), b here and at the
+//    next record towards the origin, the point indices here and at the
+//    record beyond (-1 past the far end), and the segment's form.
+//  * LineRec (per record and line), two values: the point's line factor
+//    chi' and S' at the record beyond (the elimination row of this visit
+//    crosses that point).  S' at record 0 of each half, needed only for the
+//    row across the last point before the origin, is staged on its own
+//    (2 nlc values).
 //  * BinRec (per record and bin): the bin factors of the segment that starts
 //    here, at its far end (vf, this point) and its near end (vn, the next
-//    point): q phi_P and q phi_Q for a trapezoidal segment, both W =
-//    (erf x_Q - erf x_P) times the factor above times 1/k1 for a
+//    point): q phi_P and q phi_Q for a trapezoidal segment, b_P W and b_Q W
+//    with W = (erf x_Q - erf x_P) times the factor above times 1/k1 for a
 //    semi-analytic one (x_Q - x_P = (dv_Q - dv_P) k1 / b-bar: b-bar cancels
 //    outside the erf arguments).  In FP32 the profile underflows past ~10
 //    widths, where chi' times it is far below the optical-depth floor.
+// A sweep element reads 16 bytes of LDS in FP32 (a LineRec and a BinRec),
+// against 20 with a line record that carries a point's factor for each of
+// its two segments' forms: with the VALU work per element down to eleven
+// instructions, the LDS return bandwidth sets the sweep's pace as much as
+// the VALU does (clumpy cloud: 99.7 -> 84.2 ms per FP32 launch).
 //  (Quarters and halves: the sweep works with half optical depths.)
 // Row order, as measured.  FP32 keeps a record's LineRecs (BinRecs)
 // adjacent: the sweep steps its pointers by nlc (nb) per record.  FP64 keeps
@@ -232,13 +238,12 @@ struct MetaA {
 };
 template <typename T>
 struct StageRec {
-    T dv, dvm, ib, ibm, sibb, rw, b;
-    int32_t p, pn, form;  // form bit 0: this record's segment is
-                          // semi-analytic; bit 1: the one ending here is
+    T dv, dvm, ib, ibm, sibb, rw, b, bm;
+    int32_t p, pn, semi;  // semi: this record's segment is semi-analytic
 };
 template <typename T>
-struct alignas(4 * sizeof(T)) LineRec {
-    T uf, un, Sn, S;
+struct alignas(2 * sizeof(T)) LineRec {
+    T u, Sn;
 };
 template <typename T>
 struct alignas(2 * sizeof(T)) BinRec {
@@ -248,7 +253,7 @@ struct LDSLayout {
     int ch;                  // records per half
     int ls, le, bs, be;      // LineRec (BinRec) index = line (bin) * ls (bs)
                              // + staged record * le (be)
-    size_t st, a, line, bin, total;
+    size_t st, a, s0, line, bin, total;
 };
 
 // Every section starts 16-byte aligned.
@@ -268,6 +273,9 @@ __host__ __device__ inline LDSLayout lds_layout(int ch, int nlc, int nb, int nth
     o = (o + 15) & ~(size_t)15;
     L.a = o;
     o += sizeof(MetaA<T>) * 2 * ch;
+    o = (o + 15) & ~(size_t)15;
+    L.s0 = o;
+    o += sizeof(T) * 2 * (size_t)nlc;
     o = (o + 15) & ~(size_t)15;
     L.line = o;
     o += sizeof(LineRec<T>) * (size_t)rows * nlc;
@@ -339,10 +347,10 @@ struct HalfState {
 
 // Unrolling and occupancy, as measured: the sweep loops take two records
 // per step (no register copies between steps).  FP32 launches other than
-// one-width models are held to 64 VGPRs (eight waves per SIMD; a few bytes
-// spill outside the sweeps); one-width models keep their 67 (seven waves,
-// which for their 12-wave workgroups is the same two workgroups per CU as
-// eight).  Every FP64 launch is held to 128 VGPRs (four waves).
+// one-width models are held to 64 VGPRs (eight waves per SIMD, no spills);
+// one-width models keep their 70 (seven waves, which for their 12-wave
+// workgroups is the same two workgroups per CU as eight).  Every FP64 launch
+// is held to 128 VGPRs (four waves; it needs 123).
 // ONE_WIDTH: the model has one Doppler width everywhere (T and v_turb the
 // same at every point); it selects only this cap.
 template <typename T, bool ONE_WIDTH>
@@ -376,6 +384,7 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
     StageRec<T> *s_st = (StageRec<T> *)(smem + LY.st);
     MetaA<T> *s_a = (MetaA<T> *)(smem + LY.a);
     LineRec<T> *s_line = (LineRec<T> *)(smem + LY.line);
+    T *s_S0 = (T *)(smem + LY.s0);
     BinRec<T> *s_bin = (BinRec<T> *)(smem + LY.bin);
 
     // per-lane constants (bin f: x_f b_o, k1 = 1 + x_f b_o / c, 1/k1)
@@ -390,7 +399,7 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
     const int64_t ol = (int64_t)o * nl + l;
     const T chi_o = chi[ol];
     const T S_o = S[ol];
-    const T cb_o = chi[ol] * bpt[o];
+    const T b_o = bpt[o];
     const T half_floor = (T)(0.5 * a.tau_floor);
     const T half = (T)0.5;
 
@@ -441,10 +450,6 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
         const int np = (int)(off[(int64_t)o * R + rp + 1] - offp);
         const int64_t offm = off[(int64_t)o * R + rm];
         const int nm = (int)(off[(int64_t)o * R + rm + 1] - offm);
-        // the origin's line factor as the near end of each half's last
-        // segment, by that segment's form
-        const T un_om = (nm > 0 && rec[offm].ps < 0) ? cb_o : chi_o;
-        const T un_op = (np > 0 && rec[offp].ps < 0) ? cb_o : chi_o;
 
         // Halves by length: A the longer (all of a chunk's records lie
         // inside it), B the shorter.  The minus half is staged first.
@@ -460,17 +465,16 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
         // point Q (staged record e) of a half: either the far-end boundary
         // intensity or one elimination row
         auto visit = [&](HalfState<T> &s, T dv, auto pl, auto pn, bool far_end) {
-            const T uf = pl->uf, un = pl->un, Sn = pl->Sn;
+            const T u = pl->u, Sn = pl->Sn;
             const T vf = pn->vf, vn = pn->vn;
             if (far_end)
                 s.eps = bdy_I(dv);
             else
-                row(s, segment(s, un), Sn);
-            s.a = uf * vf + half_floor;  // one multiply-add
+                row(s, segment(s, u), Sn);
+            s.a = u * vf + half_floor;  // one multiply-add
             s.vn = vn;
         };
 
-        int eA0 = 0, eB0 = 0;  // staged index of record 0 of each half
         for (int hi = nA; hi > 0; hi -= ch) {
             const int lo = hi - ch > 0 ? hi - ch : 0;
             // valid records of each half in [lo, hi), packed densely: the
@@ -492,9 +496,11 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
                 if (k > 0) {
                     sr.dvm = rec[base + k - 1].dv;
                     sr.ibm = rec[base + k - 1].ib;
+                    sr.bm = rec[base + k - 1].b;
                 } else {  // the origin, dv = 0
                     sr.dvm = (T)0;
                     sr.ibm = ib_o;
+                    sr.bm = b_o;
                 }
                 sr.ib = rc.ib;
                 sr.sibb = rc.ibb * (T)FM<T>::erf_scale;
@@ -503,9 +509,8 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
                 sr.rw = semi ? rc.dx * half : rc.dx * (T)0.25;
                 sr.b = rc.b;
                 sr.p = p;
-                const int psn = k + 1 < n ? rec[base + k + 1].ps : 0;
-                sr.pn = k + 1 < n ? psn & 0x7fffffff : -1;
-                sr.form = (semi ? 1 : 0) | (psn < 0 ? 2 : 0);
+                sr.pn = k + 1 < n ? rec[base + k + 1].ps & 0x7fffffff : -1;
+                sr.semi = semi ? 1 : 0;
                 s_st[t] = sr;
                 MetaA<T> ma;
                 ma.dv = rc.dv;
@@ -517,7 +522,7 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
             // are computed, and stored after them, so that arithmetic
             // covers their latency
             constexpr int kA = kLineAhead<T> > 0 ? kLineAhead<T> : 1;
-            T g_chi[kA], g_S[kA], g_Sn[kA];
+            T g_chi[kA], g_Sn[kA];
     #pragma unroll
             for (int j = 0; j < kLineAhead<T>; j++) {
                 const int e = le0 < cnt ? le0 + j * lrows : cnt;
@@ -525,7 +530,6 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
                     const StageRec<T> &sr = s_st[e];
                     const int64_t idx = (int64_t)sr.p * nl + l0 + li_s;
                     g_chi[j] = chi[idx];
-                    g_S[j] = S[idx];
                     g_Sn[j] = sr.pn >= 0 ? S[(int64_t)sr.pn * nl + l0 + li_s] : (T)0;
                 }
             }
@@ -536,46 +540,53 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
                 const T uP = xb + sr.dv * k1;
                 const T uQ = xb + sr.dvm * k1;
                 BinRec<T> br;
-                if (sr.form & 1) {
+                if (sr.semi) {
                     const T xP = uP * sr.sibb;
                     const T xQ = uQ * sr.sibb;
                     const T eP = FM<T>::erfc_scaled(fabs(xP));
                     const T eQ = FM<T>::erfc_scaled(fabs(xQ));
-                    br.vf = br.vn = erf_diff<T>(xP, xQ, eP, eQ) * (sr.rw * ik1);
+                    const T Wd = erf_diff<T>(xP, xQ, eP, eQ) * (sr.rw * ik1);
+                    br.vf = Wd * sr.b;
+                    br.vn = Wd * sr.bm;
                 } else {
                     br.vf = sr.rw * FM<T>::phi_of(uP * sr.ib);
                     br.vn = sr.rw * FM<T>::phi_of(uQ * sr.ibm);
                 }
                 s_bin[f * LY.bs + e * LY.be] = br;
             }
-            auto line_rec = [&](const StageRec<T> &sr, T chi_l, T S_l, T Sn_l) {
+            auto line_rec = [&](T chi_l, T Sn_l) {
                 LineRec<T> lr;
-                const T cb = chi_l * sr.b;
-                lr.uf = (sr.form & 1) ? cb : chi_l;
-                lr.un = (sr.form & 2) ? cb : chi_l;
+                lr.u = chi_l;
                 lr.Sn = Sn_l;
-                lr.S = S_l;
                 return lr;
+            };
+            // S' at record 0 of each half (minus, plus), for the row across
+            // the last point before the origin
+            auto stage_s0 = [&](int e, const StageRec<T> &sr) {
+                const bool mh = e < cm;
+                if (lo == 0 && (mh ? e : e - cm) == 0)
+                    s_S0[(mh ? 0 : nlc) + li_s] = S[(int64_t)sr.p * nl + l0 + li_s];
             };
     #pragma unroll
             for (int j = 0; j < kLineAhead<T>; j++) {
                 const int e = le0 < cnt ? le0 + j * lrows : cnt;
-                if (e < cnt)
-                    s_line[li_s * LY.ls + e * LY.le] = line_rec(s_st[e], g_chi[j], g_S[j], g_Sn[j]);
+                if (e < cnt) {
+                    s_line[li_s * LY.ls + e * LY.le] = line_rec(g_chi[j], g_Sn[j]);
+                    stage_s0(e, s_st[e]);
+                }
             }
             // the rest of the thread's records
             for (int e = le0 < cnt ? le0 + kLineAhead<T> * lrows : cnt; e < cnt; e += lrows) {
                 const StageRec<T> &sr = s_st[e];
                 const int64_t idx = (int64_t)sr.p * nl + l0 + li_s;
                 const T Sn_l = sr.pn >= 0 ? S[(int64_t)sr.pn * nl + l0 + li_s] : (T)0;
-                s_line[li_s * LY.ls + e * LY.le] = line_rec(sr, chi[idx], S[idx], Sn_l);
+                s_line[li_s * LY.ls + e * LY.le] = line_rec(chi[idx], Sn_l);
+                stage_s0(e, sr);
             }
             __syncthreads();
             // record k of half A is staged at eA + k, of half B at eB + k; a
             // lane's line and bin rows of each half, indexed by record
             const int eA = (a_minus ? 0 : cm) - lo, eB = (a_minus ? cm : 0) - lo;
-            eA0 = eA;  // the last chunk has lo = 0
-            eB0 = eB;
             if constexpr (kRowsByRecord<T>) {
                 const LineRec<T> *la = s_line + ll * LY.ls + eA, *lb = s_line + ll * LY.ls + eB;
                 const BinRec<T> *na = s_bin + f * LY.bs + eA, *nbr = s_bin + f * LY.bs + eB;
@@ -656,10 +667,10 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
                 }
             }
         }
-        // last segment of each non-empty half ends at the origin
-        // (S' at records 0, still staged from the last chunk)
-        if (nA > 0) row(A, segment(A, a_minus ? un_om : un_op), s_line[ll * LY.ls + eA0 * LY.le].S);
-        if (nB > 0) row(B, segment(B, a_minus ? un_op : un_om), s_line[ll * LY.ls + eB0 * LY.le].S);
+        // last segment of each non-empty half ends at the origin (S' at
+        // record 0 of each half, staged with the last chunk)
+        if (nA > 0) row(A, segment(A, chi_o), s_S0[(a_minus ? 0 : nlc) + ll]);
+        if (nB > 0) row(B, segment(B, chi_o), s_S0[(a_minus ? nlc : 0) + ll]);
         // combine in the order minus, plus
         const HalfState<T> &Hm = a_minus ? A : B, &Hp = a_minus ? B : A;
         const T Do = Hm.hm + Hp.hm;
