@@ -766,7 +766,9 @@ template size_t formal_solve_lds<double>(int, int, int, int);
 // 12-wave workgroups per CU: 56 records per half, 109 against 116 ms with
 // 32; outflow, five 5-wave workgroups: 32 against 16, 9.1 against 10.5 ms;
 // FP64 clumpy cloud, one workgroup per CU with 148 KiB: 56 against 24, 326
-// against 359 ms; FP64 outflow, two workgroups: 33.9 against 35.7 ms).
+// against 359 ms; FP64 outflow, two workgroups: 33.9 against 35.7 ms; with
+// two-value line records the clumpy cloud's FP32 chunk reaches 72 records,
+// 83.1 against 83.9 ms at 64).
 static size_t lds_budget(int nthreads, int target_waves)
 {
     const int waves = (nthreads + 63) / 64;
@@ -779,7 +781,7 @@ template <typename T>
 int formal_solve_chunk(int nlc, int nb, int nthreads)
 {
     const size_t budget = lds_budget(nthreads, sizeof(T) == 4 ? 28 : 12);
-    int ch = 64;
+    int ch = 128;
     while (lds_layout<T>(ch, nlc, nb, nthreads).total > budget && ch > 1) ch -= ch > 8 ? 8 : 1;
     return ch;
 }

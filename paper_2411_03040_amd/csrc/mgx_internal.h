@@ -165,7 +165,7 @@ hipError_t launch_formal_solve(const FSArgs<T> &a, hipStream_t s);
 template <typename T>
 size_t formal_solve_lds(int ch, int nlc, int nb, int nthreads);
 // records per half staged at once: the largest chunk (steps of 8 records,
-// at most 64; down to 1 for very wide bin sets) whose LDS fits the share of a
+// at most 128; down to 1 for very wide bin sets) whose LDS fits the share of a
 // CU's 160 KiB that the workgroups its registers allow leave each
 template <typename T>
 int formal_solve_chunk(int nlc, int nb, int nthreads);
