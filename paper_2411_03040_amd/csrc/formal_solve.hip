@@ -343,6 +343,8 @@ struct HalfState {
     T a, vn;       // previous point P: its end's term of the segment from P
                    // towards the origin (uf vf) and that segment's near-end
                    // bin factor
+    T Dn;          // after the first row of a pair: (G, eps) is held as
+                   // (G / Dn, eps / Dn) until the second row divides
 };
 
 // Unrolling and occupancy, as measured: the sweep loops take two records
@@ -474,6 +476,58 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
             s.a = u * vf + half_floor;  // one multiply-add
             s.vn = vn;
         };
+        // Rows in pairs with one reciprocal.  The rows at records 2j + 1 and
+        // 2j of a half form a pair: after the first, (G, eps) is carried as
+        // the fraction (N / Dn, E / Dn) whose denominator 1 + q2 h is the one
+        // a single row divides by; the second row then gives
+        //   N2 = 2 D2 Dn + N,  Dn2 = Dn + N2 h2,  E2 = D2 SP2 Dn + E,
+        // and G = N2 / Dn2, eps = E2 / Dn2 (both denominators are >= 1, and
+        // their product stays far inside the range for any segment depths
+        // a line profile produces).  The row right below a far end at an
+        // even record has no partner and divides at once.  Pairs follow
+        // the record index, not the staging chunks, so every chunk size
+        // gives the same roundings.
+        auto first = [&](HalfState<T> &s, auto pl, auto pn) {
+            const T u = pl->u, Sn = pl->Sn;
+            const T vf = pn->vf, vn = pn->vn;
+            const T h = segment(s, u);
+            const T D = s.hm + h;
+            s.G = D * (T)2 + s.G;
+            s.Dn = s.G * h + (T)1;
+            s.eps = D * Sn + s.eps;
+            s.hm = h;
+            s.a = u * vf + half_floor;
+            s.vn = vn;
+        };
+        auto second = [&](HalfState<T> &s, auto pl, auto pn) {
+            const T u = pl->u, Sn = pl->Sn;
+            const T vf = pn->vf, vn = pn->vn;
+            const T h = segment(s, u);
+            const T D = s.hm + h;
+            const T t = D * s.Dn;
+            const T N = t * (T)2 + s.G;
+            const T r = FM<T>::rcp_ge1(N * h + s.Dn);
+            s.G = N * r;
+            s.eps = (t * Sn + s.eps) * r;
+            s.hm = h;
+            s.a = u * vf + half_floor;
+            s.vn = vn;
+        };
+        // the row at an even record k of a half of n records: the second of
+        // a pair, or a single row right below the far end
+        auto even_row = [&](HalfState<T> &s, int k, int n, auto pl, auto pn) {
+            if (k <= n - 3)
+                second(s, pl, pn);
+            else
+                visit(s, (T)0, pl, pn, false);
+        };
+        // the row at record k (not a far end)
+        auto any_row = [&](HalfState<T> &s, int k, int n, auto pl, auto pn) {
+            if (k & 1)
+                first(s, pl, pn);
+            else
+                even_row(s, k, n, pl, pn);
+        };
 
         for (int hi = nA; hi > 0; hi -= ch) {
             const int lo = hi - ch > 0 ? hi - ch : 0;
@@ -591,47 +645,58 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
                 const LineRec<T> *la = s_line + ll * LY.ls + eA, *lb = s_line + ll * LY.ls + eB;
                 const BinRec<T> *na = s_bin + f * LY.bs + eA, *nbr = s_bin + f * LY.bs + eB;
                 int k = hi - 1;
-                // records beyond the end of B: A alone (its far end first), two
-                // records per step
+                // records beyond the end of B: A alone (its far end first), a
+                // pair of rows per step
                 if (k >= nB && k == nA - 1) {
                     visit(A, s_a[eA + k].dv, la + k, na + k, true);
                     k--;
                 }
                 const int kAB = max(lo, nB);
+                if (k >= kAB && !(k & 1)) {
+                    even_row(A, k, nA, la + k, na + k);
+                    k--;
+                }
                 {
                     // pointers at the lower record of each step: the upper one is
                     // an immediate offset
                     lptr<LineRec<T>> pl = opaque(la + k - 1);
                     lptr<BinRec<T>> pn = opaque(na + k - 1);
                     for (; k > kAB; k -= 2, pl -= 2, pn -= 2) {
-                        visit(A, (T)0, pl + 1, pn + 1, false);
-                        visit(A, (T)0, pl, pn, false);
+                        first(A, pl + 1, pn + 1);
+                        second(A, pl, pn);
                     }
                 }
                 if (k == kAB) {
-                    visit(A, (T)0, la + k, na + k, false);
+                    first(A, la + k, na + k);
                     k--;
                 }
                 // B's far end (A's too when the halves are equally long)
                 if (k >= lo && k == nB - 1) {
-                    const bool a_far = k == nA - 1;
-                    visit(A, a_far ? s_a[eA + k].dv : (T)0, la + k, na + k, a_far);
+                    if (k == nA - 1)
+                        visit(A, s_a[eA + k].dv, la + k, na + k, true);
+                    else
+                        any_row(A, k, nA, la + k, na + k);
                     visit(B, s_a[eB + k].dv, lb + k, nbr + k, true);
+                    k--;
+                }
+                if (k >= lo && !(k & 1)) {
+                    even_row(A, k, nA, la + k, na + k);
+                    even_row(B, k, nB, lb + k, nbr + k);
                     k--;
                 }
                 {
                     lptr<LineRec<T>> pla = opaque(la + k - 1), plb = opaque(lb + k - 1);
                     lptr<BinRec<T>> pna = opaque(na + k - 1), pnb = opaque(nbr + k - 1);
                     for (; k > lo; k -= 2, pla -= 2, plb -= 2, pna -= 2, pnb -= 2) {
-                        visit(A, (T)0, pla + 1, pna + 1, false);
-                        visit(B, (T)0, plb + 1, pnb + 1, false);
-                        visit(A, (T)0, pla, pna, false);
-                        visit(B, (T)0, plb, pnb, false);
+                        first(A, pla + 1, pna + 1);
+                        first(B, plb + 1, pnb + 1);
+                        second(A, pla, pna);
+                        second(B, plb, pnb);
                     }
                 }
                 if (k == lo) {
-                    visit(A, (T)0, la + k, na + k, false);
-                    visit(B, (T)0, lb + k, nbr + k, false);
+                    first(A, la + k, na + k);
+                    first(B, lb + k, nbr + k);
                 }
             } else {
                 int k = hi - 1;
@@ -645,14 +710,30 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
                     k--;
                 }
                 const int kAB = max(lo, nB);
-    #pragma unroll 2
-                for (; k >= kAB; k--, la -= nlc, na -= nb) visit(A, (T)0, la, na, false);
+                if (k >= kAB && !(k & 1)) {
+                    even_row(A, k, nA, la, na);
+                    la -= nlc;
+                    na -= nb;
+                    k--;
+                }
+                for (; k > kAB; k -= 2, la -= 2 * nlc, na -= 2 * nb) {
+                    first(A, la, na);
+                    second(A, la - nlc, na - nb);
+                }
+                if (k == kAB) {
+                    first(A, la, na);
+                    la -= nlc;
+                    na -= nb;
+                    k--;
+                }
                 const LineRec<T> *lb = s_line + (eB + k) * nlc + ll;
                 const BinRec<T> *nbp = s_bin + (eB + k) * nb + f;
                 // B's far end (A's too when the halves are equally long)
                 if (k >= lo && k == nB - 1) {
-                    const bool a_far = k == nA - 1;
-                    visit(A, a_far ? s_a[eA + k].dv : (T)0, la, na, a_far);
+                    if (k == nA - 1)
+                        visit(A, s_a[eA + k].dv, la, na, true);
+                    else
+                        any_row(A, k, nA, la, na);
                     visit(B, s_a[eB + k].dv, lb, nbp, true);
                     la -= nlc;
                     lb -= nlc;
@@ -660,10 +741,24 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
                     nbp -= nb;
                     k--;
                 }
-    #pragma unroll 2
-                for (; k >= lo; k--, la -= nlc, lb -= nlc, na -= nb, nbp -= nb) {
-                    visit(A, (T)0, la, na, false);
-                    visit(B, (T)0, lb, nbp, false);
+                if (k >= lo && !(k & 1)) {
+                    even_row(A, k, nA, la, na);
+                    even_row(B, k, nB, lb, nbp);
+                    la -= nlc;
+                    lb -= nlc;
+                    na -= nb;
+                    nbp -= nb;
+                    k--;
+                }
+                for (; k > lo; k -= 2, la -= 2 * nlc, lb -= 2 * nlc, na -= 2 * nb, nbp -= 2 * nb) {
+                    first(A, la, na);
+                    first(B, lb, nbp);
+                    second(A, la - nlc, na - nb);
+                    second(B, lb - nlc, nbp - nb);
+                }
+                if (k == lo) {
+                    first(A, la, na);
+                    first(B, lb, nbp);
                 }
             }
         }
