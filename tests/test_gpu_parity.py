@@ -229,6 +229,18 @@ def test_formal_solve_moving_cloud(mgx, prec, tolJ, tolL):
     assert ctx.counters()["semi_segments"] > 0
 
 
+@pytest.mark.parametrize("tau_scale", [1e4, 1e7, 1e10])
+@pytest.mark.parametrize("prec,tolJ,tolL", [(0, 1e-10, 1e-10), (1, 1e-5, 1e-5)])
+def test_formal_solve_optically_thick(mgx, tau_scale, prec, tolJ, tolL):
+    """Line optical depths far beyond the workloads' (Lambda* up to 0.9999):
+    the elimination rows that share one reciprocal per pair carry the
+    product of two denominators, which must stay finite and accurate."""
+    m = synth.tiny_cloud(npoints=300, seed=41, k=12, nside=2, nlev=4, nbins=15, vmax=4e3,
+                         tau_scale=tau_scale)
+    ctx, J, L = fs_compare(mgx, m, prec, tolJ=tolJ, tolL=tolL)
+    assert np.all(np.isfinite(J)) and np.all(np.isfinite(L))
+
+
 @pytest.mark.parametrize("prec,tolJ,tolL", [(0, 1e-10, 1e-10), (1, 1e-5, 1e-5)])
 def test_formal_solve_outflow_full_sampled(mgx, outflow, prec, tolJ, tolL):
     origins = synth.origin_sample(outflow.npoints, 48, seed=41)
