@@ -159,8 +159,7 @@ def alu_roofline(ctx, m, ms_per_launch, precision):
 
 def committed_traffic(workload):
     """HBM bytes per formal-solve launch from the committed rocprofv3 counter
-    summary, or None when the kernel source changed since it was taken."""
-    import hashlib
+    summary, or None when the kernel code changed since it was taken."""
     import re
     name = {"outflow": "outflow_50k", "clumpy": "clumpy_200k"}.get(workload)
     if name is None:
@@ -170,13 +169,25 @@ def committed_traffic(workload):
     if not os.path.exists(path):
         return None
     text = open(path).read()
-    m1 = re.search(r"^source_sha256: (\w+)", text, re.M)
+    m1 = re.search(r"^code_sha256: (\w+)", text, re.M)
     m2 = re.search(r"^traffic_bytes_per_launch: ([0-9.e+-]+)", text, re.M)
     if not (m1 and m2):
         return None
-    if hashlib.sha256(open(src, "rb").read()).hexdigest() != m1.group(1):
+    if code_sha256(src) != m1.group(1):
         return None
     return float(m2.group(1))
+
+
+def code_sha256(path):
+    """SHA-256 of a C/HIP source with comments removed and whitespace runs
+    collapsed: a profile stays valid across comment edits, not code edits."""
+    import hashlib
+    import re
+    text = open(path).read()
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    text = " ".join(text.split())
+    return hashlib.sha256(text.encode()).hexdigest()
 
 
 def log(*a):

@@ -29,6 +29,10 @@
 //    carries h = dt/2 and G = 2g instead of dt and g: D = h_m + h,
 //    G <- (2D + G) inv with inv = 1 / (1 + (2D + G) h), one operation fewer
 //    per step, and, the factors being powers of two, the same roundings.
+//    Two consecutive steps share one reciprocal: the first leaves (G, eps)
+//    as a fraction over its denominator 1 + (2D + G) h, the second scales
+//    its own terms by that denominator and divides once (the reciprocal is
+//    the dearest instruction of the step).
 //  * J-bar = sum_pairs 2 w_r sum_f W_f u, Lambda-bar* likewise.
 //
 // Launch shape: one workgroup per (origin, chunk of lines); one lane per
@@ -341,7 +345,7 @@ template <typename T>
 struct HalfState {
     T G, eps, hm;  // elimination state: 2g, eps, half the previous depth
     T a, vn;       // previous point P: its end's term of the segment from P
-                   // towards the origin (uf vf) and that segment's near-end
+                   // towards the origin (u vf) and that segment's near-end
                    // bin factor
     T Dn;          // after the first row of a pair: (G, eps) is held as
                    // (G / Dn, eps / Dn) until the second row divides
@@ -434,14 +438,14 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
     };
 
     // half the optical depth of the segment from the previous point of st
-    // (farther out) to Q, whose line factor as the segment's near end is
-    // unQ: trapezoidal dt/2 = dx/4 (chi'_P phi_P + chi'_Q phi_Q),
+    // (farther out) to Q, whose line factor is uQ: trapezoidal
+    //   dt/2 = dx/4 (chi'_P phi_P + chi'_Q phi_Q),
     // semi-analytic
-    //   dt/2 = dx sqrt(pi)/8 (cb_P + cb_Q) (erf x_Q - erf x_P) / (b-bar (x_Q - x_P)),
-    // both as the far end's term plus unQ times the near-end bin factor.
+    //   dt/2 = dx sqrt(pi)/8 (chi'_P b_P + chi'_Q b_Q) (erf x_Q - erf x_P) / (b-bar (x_Q - x_P)),
+    // both as the far end's term plus uQ times the near-end bin factor.
     // The far end's term carries tau_floor / 2 (visit below).
-    auto segment = [&](const HalfState<T> &st, T unQ) -> T {
-        return unQ * st.vn + st.a;
+    auto segment = [&](const HalfState<T> &st, T uQ) -> T {
+        return uQ * st.vn + st.a;
     };
 
     double accJ = 0.0, accL = 0.0;
