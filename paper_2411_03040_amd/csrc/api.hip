@@ -326,8 +326,15 @@ extern "C" mgx_status mgx_load_model(mgx_ctx *ctx, const mgx_model *m)
     ctx->J.ensure(sizeof(double) * ctx->nrad());
     ctx->L.ensure(sizeof(double) * ctx->nrad());
     ctx->S64.ensure(sizeof(double) * ctx->nrad());
-    ctx->chiT.ensure(tsz * ctx->nrad());
-    ctx->ST.ensure(tsz * ctx->nrad());
+    // line-table rows longer than half a 128-byte cache line start on a line
+    // of their own (a gather of a point's row then touches as few lines as
+    // it can); shorter rows stay packed
+    {
+        const int row = ctx->nlines * (int)tsz;
+        ctx->ldl = row > 64 ? (int)(((row + 127) / 128) * 128 / tsz) : ctx->nlines;
+    }
+    ctx->chiT.ensure(tsz * (size_t)ctx->N * ctx->ldl);
+    ctx->ST.ensure(tsz * (size_t)ctx->N * ctx->ldl);
     ctx->sync();
     ctx->loaded = true;
     ctx->host_cnt = mgx_counters{};
@@ -551,7 +558,7 @@ extern "C" mgx_status mgx_set_lte_populations(mgx_ctx *ctx)
     API_END(ctx)
 }
 
-void mgxh::line_coeffs_into(mgx_ctx *ctx, const double *pops, void *chiT, void *ST,
+void mgxh::line_coeffs_into(mgx_ctx *ctx, const double *pops, void *chiT, void *ST, int ldt,
                             double *S64, Counters *cnt, hipStream_t s, double S_unit)
 {
     LineArgs la{};
@@ -574,6 +581,7 @@ void mgxh::line_coeffs_into(mgx_ctx *ctx, const double *pops, void *chiT, void *
     la.S64 = S64;
     la.chiT = chiT;
     la.ST = ST;
+    la.ldt = ldt;
     la.fp32 = ctx->fp32() ? 1 : 0;
     la.cnt = cnt;
     HIPCHK(launch_reset_counters(cnt, s));
@@ -618,7 +626,8 @@ std::vector<int32_t> mgxh::morton_order(const double *pos, int N)
 
 void mgxh::run_line_coeffs(mgx_ctx *ctx)
 {
-    line_coeffs_into(ctx, ctx->pops.as<double>(), ctx->chiT.p, ctx->ST.p, ctx->S64.as<double>(),
+    line_coeffs_into(ctx, ctx->pops.as<double>(), ctx->chiT.p, ctx->ST.p, ctx->ldl,
+                     ctx->S64.as<double>(),
                      ctx->counters.as<Counters>(), ctx->stream);
 }
 
@@ -704,6 +713,7 @@ FSArgs<T> mgxh::fs_args(mgx_ctx *ctx)
     a.L = ctx->L.as<double>();
     a.order = ctx->order.as<int32_t>();  // null where the table fits the L2
     a.one_width = ctx->one_width ? 1 : 0;
+    a.ldl = ctx->ldl;
     return a;
 }
 template FSArgs<float> mgxh::fs_args<float>(mgx_ctx *);
@@ -1161,8 +1171,8 @@ void mgxh::render_image(mgx_ctx *ctx, RenderBufs &rb, const double *pops, hipStr
     rb.cnt.ensure(sizeof(Counters));
     // intensities in units of I_img = 2 h f_mid^3 / c^2 (source functions too)
     const double I_img = 2.0 * kH * pow(0.5 * (f_min + f_max), 3) / (kC * kC);
-    line_coeffs_into(ctx, pops, rb.chiT.p, rb.ST.p, rb.S64.as<double>(), rb.cnt.as<Counters>(),
-                     s, I_img);
+    line_coeffs_into(ctx, pops, rb.chiT.p, rb.ST.p, ctx->nlines, rb.S64.as<double>(),
+                     rb.cnt.as<Counters>(), s, I_img);
     const int64_t npix = (int64_t)npx * npy;
     RenderGeom g{};
     g.N = N;

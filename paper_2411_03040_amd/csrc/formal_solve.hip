@@ -402,7 +402,8 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
     const T ik1 = (T)(1.0 / (1.0 + xbd / kC));
     const T inv_c = (T)(1.0 / kC);
     const T acmb = (T)acmb_l[l];
-    const int64_t ol = (int64_t)o * nl + l;
+    const int ldl = a.ldl;
+    const int64_t ol = (int64_t)o * ldl + l;
     const T chi_o = chi[ol];
     const T S_o = S[ol];
     const T b_o = bpt[o];
@@ -586,9 +587,9 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
                 const int e = le0 < cnt ? le0 + j * lrows : cnt;
                 if (e < cnt) {
                     const StageRec<T> &sr = s_st[e];
-                    const int64_t idx = (int64_t)sr.p * nl + l0 + li_s;
+                    const int64_t idx = (int64_t)sr.p * ldl + l0 + li_s;
                     g_chi[j] = chi[idx];
-                    g_Sn[j] = sr.pn >= 0 ? S[(int64_t)sr.pn * nl + l0 + li_s] : (T)0;
+                    g_Sn[j] = sr.pn >= 0 ? S[(int64_t)sr.pn * ldl + l0 + li_s] : (T)0;
                 }
             }
             // per (record, bin): the bin factors of the segment towards the
@@ -623,7 +624,7 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
             auto stage_s0 = [&](int e, const StageRec<T> &sr) {
                 const bool mh = e < cm;
                 if (lo == 0 && (mh ? e : e - cm) == 0)
-                    s_S0[(mh ? 0 : nlc) + li_s] = S[(int64_t)sr.p * nl + l0 + li_s];
+                    s_S0[(mh ? 0 : nlc) + li_s] = S[(int64_t)sr.p * ldl + l0 + li_s];
             };
     #pragma unroll
             for (int j = 0; j < kLineAhead<T>; j++) {
@@ -636,8 +637,8 @@ __device__ __forceinline__ void solve_origin(const FSArgs<T> &a, const int o, co
             // the rest of the thread's records
             for (int e = le0 < cnt ? le0 + kLineAhead<T> * lrows : cnt; e < cnt; e += lrows) {
                 const StageRec<T> &sr = s_st[e];
-                const int64_t idx = (int64_t)sr.p * nl + l0 + li_s;
-                const T Sn_l = sr.pn >= 0 ? S[(int64_t)sr.pn * nl + l0 + li_s] : (T)0;
+                const int64_t idx = (int64_t)sr.p * ldl + l0 + li_s;
+                const T Sn_l = sr.pn >= 0 ? S[(int64_t)sr.pn * ldl + l0 + li_s] : (T)0;
                 s_line[li_s * LY.ls + e * LY.le] = line_rec(chi[idx], Sn_l);
                 stage_s0(e, sr);
             }
@@ -1024,12 +1025,13 @@ __global__ void k_line_coeffs(LineArgs a)
     a.S64[i] = S;
     const double chis = chi * a.chiscale[l] / a.b[p];
     const double Ss = S / (a.S_unit > 0.0 ? a.S_unit : a.Iref[l]);
+    const int64_t it = (int64_t)p * a.ldt + l;
     if (a.fp32) {
-        ((float *)a.chiT)[i] = (float)chis;
-        ((float *)a.ST)[i] = (float)Ss;
+        ((float *)a.chiT)[it] = (float)chis;
+        ((float *)a.ST)[it] = (float)Ss;
     } else {
-        ((double *)a.chiT)[i] = chis;
-        ((double *)a.ST)[i] = Ss;
+        ((double *)a.chiT)[it] = chis;
+        ((double *)a.ST)[it] = Ss;
     }
 }
 

@@ -144,6 +144,7 @@ struct mgx_ctx {
     int dim = 3, N = 0, R = 0, nlev = 0, nlines = 0, ncoll_tr = 0, nbins = 0, npairs = 0;
     double mass = 0, xmax = 5, Tcmb = 2.72548, L_unit = 1;
     bool one_width = false;  // T and v_turb^2 the same at every point
+    int ldl = 0;             // row stride of the solve's line table (chiT, ST)
     double vmax = 0, bmax = 0;  // largest |v| and Doppler width b over the points
     std::vector<double> nu_host;  // line centres
     int64_t n_records = 0;
@@ -281,8 +282,9 @@ inline void upload(mgx_ctx *c, DMem &d, const T *src, size_t n)
 // context internals used by the batch and server sources
 void run_line_coeffs(mgx_ctx *ctx);
 // (S_unit > 0: the solve-precision source function is S / S_unit, else S / Iref)
-void line_coeffs_into(mgx_ctx *ctx, const double *pops, void *chiT, void *ST, double *S64,
-                      Counters *cnt, hipStream_t s, double S_unit = 0.0);
+// (ldt: row stride of chiT and ST)
+void line_coeffs_into(mgx_ctx *ctx, const double *pops, void *chiT, void *ST, int ldt,
+                      double *S64, Counters *cnt, hipStream_t s, double S_unit = 0.0);
 bool options_valid(const mgx_options &o);
 void fs_shape(size_t tsize, int nlines, int nbins, int *nlc_out, int *nthreads_out,
               size_t *lds_out);

@@ -101,7 +101,7 @@ struct FSArgs {
     const Rec<T> *rec;
     const int32_t *pair_r, *pair_a;
     const double *pair_w;
-    const T *chi, *S;       // [N][nlines] scaled opacity factor and source
+    const T *chi, *S;       // [N][ldl] scaled opacity factor and source
     const T *bpt, *ibpt;    // [N] b and (scaled) 1/b in T
     const double *b64;      // [N] b
     const double *xf, *W;   // [nbins]
@@ -111,6 +111,7 @@ struct FSArgs {
     double *J, *L;          // [N][nlines]
     const int32_t *order;   // [N] origins in Morton order of their positions
     int one_width;          // every point has the same Doppler width b
+    int ldl;                // row stride of chi and S (>= nlines)
 };
 
 struct LineArgs {
@@ -121,7 +122,8 @@ struct LineArgs {
     double chi_min;
     double S_unit;          // > 0: the solve-precision S is S / S_unit (images), else S / Iref
     double *S64;            // [N][nlines] physical source function
-    void *chiT, *ST;        // [N][nlines] in the solve precision
+    void *chiT, *ST;        // [N][ldt] in the solve precision
+    int ldt;                // their row stride (>= nlines)
     int fp32;
     Counters *cnt;
 };
