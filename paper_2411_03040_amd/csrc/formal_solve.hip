@@ -219,9 +219,9 @@ __device__ __forceinline__ T erf_diff(T a, T b, T ea, T eb)
 //    widths, where chi' times it is far below the optical-depth floor.
 // A sweep element reads 16 bytes of LDS in FP32 (a LineRec and a BinRec),
 // against 20 with a line record that carries a point's factor for each of
-// its two segments' forms: with the VALU work per element down to eleven
-// instructions, the LDS return bandwidth sets the sweep's pace as much as
-// the VALU does (clumpy cloud: 99.7 -> 84.2 ms per FP32 launch).
+// its two segments' forms; at 20 the LDS return bandwidth, not the VALU,
+// set the sweep's pace (clumpy cloud: 99.7 -> 84.2 ms per FP32 launch with
+// the smaller record).
 //  (Quarters and halves: the sweep works with half optical depths.)
 // Row order, as measured.  FP32 keeps a record's LineRecs (BinRecs)
 // adjacent: the sweep steps its pointers by nlc (nb) per record.  FP64 keeps
@@ -347,8 +347,9 @@ struct HalfState {
     T a, vn;       // previous point P: its end's term of the segment from P
                    // towards the origin (u vf) and that segment's near-end
                    // bin factor
-    T Dn;          // after the first row of a pair: (G, eps) is held as
-                   // (G / Dn, eps / Dn) until the second row divides
+    T Dn;          // after the first row of a pair, G and eps hold the
+                   // numerators of N / Dn and E / Dn until the second row
+                   // divides
 };
 
 // Unrolling and occupancy, as measured: the sweep loops take two records
