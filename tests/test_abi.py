@@ -92,3 +92,23 @@ def test_formal_solve_shape_fits_lds():
     assert mgx.formal_solve_shape(mgx.FP64, 9, 31)[0] == 9
     with pytest.raises(mgx.MgxError):
         mgx.formal_solve_shape(mgx.FP32, 1, 1025)
+
+
+def test_profile_code_hash_ignores_comments_only(tmp_path):
+    """The committed kernel profiles are keyed to a hash of the kernel code
+    with comments and whitespace stripped: comment edits keep a profile
+    valid, any code edit invalidates it."""
+    import sys
+    sys.path.insert(0, ROOT)
+    import bench
+    src = ("// header\n__global__ void k(float *x) { /* block\n comment */\n"
+           "    x[0] = 1.0f;  // trailing\n}\n")
+    a = tmp_path / "a.hip"
+    a.write_text(src)
+    b = tmp_path / "b.hip"
+    b.write_text(src.replace("// trailing", "// other words").replace("// header", "")
+                 .replace("    x[0]", "  x[0]"))
+    c = tmp_path / "c.hip"
+    c.write_text(src.replace("1.0f", "2.0f"))
+    assert bench.code_sha256(str(a)) == bench.code_sha256(str(b))
+    assert bench.code_sha256(str(a)) != bench.code_sha256(str(c))
